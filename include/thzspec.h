@@ -1,0 +1,197 @@
+/*
+ * thzspec — batched spectra of sampled THz-TDS traces on MI355X (gfx950):
+ * zero-padded FFT, chirp-Z transform (Bluestein form) and Zoom FFT, as
+ * defined in "Comparison of computing efficiency among FFT, CZT and Zoom FFT
+ * in THz-TDS" (arXiv:2108.03948).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Traces are real samples x[n] = x(n T_s), n < N (Section 2.1, eq. (1)),
+ *   one trace per row: trace b starts at element b * in_stride of x.
+ *   Element type is float (TZ_F32, default) or double (TZ_F64).
+ * - Spectra are written as interleaved complex float (re, im), one row per
+ *   trace: row b starts at complex element b * out_stride of X.
+ * - x and X are DEVICE pointers (HIP global memory, e.g. a torch tensor's
+ *   data_ptr()).  The caller owns them; they must not overlap.  The library
+ *   never copies traces or spectra to or from the host.
+ * - Transforms are forward and unscaled (a plain sum over n, no 1/N), as in
+ *   eqs. (2) and (11).
+ * - Work is enqueued on opts->stream (a hipStream_t; NULL = the null stream)
+ *   and returns before it finishes.  The first call with a new shape builds
+ *   a plan (device tables, see below) and may allocate and synchronise that
+ *   stream; later calls with the same shape reuse it and allocate nothing.
+ * - Every call returns a tz_status.  On TZ_EINVAL / TZ_EUNSUPPORTED nothing
+ *   is launched and X is untouched; tz_last_error() (thread-local) says why.
+ *   TZ_EDEVICE reports a HIP error from an allocation or a launch.
+ * - Plans (chirp tables, filter spectrum, twiddles, FIR taps) are owned by
+ *   the library, cached per device, and freed by tz_release_plans() or at
+ *   process exit.  All entry points are thread-safe.
+ */
+#ifndef THZSPEC_H
+#define THZSPEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Complex parameter in double precision. */
+typedef struct {
+    double re, im;
+} tz_c64;
+
+typedef enum {
+    TZ_OK = 0,
+    TZ_EINVAL = 1,        /* an argument is out of range (nothing launched) */
+    TZ_ENOMEM = 2,        /* a plan table could not be allocated            */
+    TZ_EDEVICE = 3,       /* a HIP call failed                              */
+    TZ_EUNSUPPORTED = 4   /* valid arguments outside what the GPU path does */
+} tz_status;
+
+/* input element type */
+enum { TZ_F32 = 0, TZ_F64 = 1 };
+/* arithmetic of the FFT stages */
+enum { TZ_FP32 = 0, TZ_SPLIT_FP16 = 1, TZ_SPLIT_BF16 = 2 };
+/* flags */
+enum {
+    TZ_HALF = 1  /* fft_zeropad: write bins 0 .. N_fft/2 only (real input) */
+};
+/* job kinds for the uneven batch */
+enum { TZ_JOB_CZT = 0, TZ_JOB_ZOOM = 1 };
+
+typedef struct {
+    int64_t batch;          /* B, number of traces (>= 1; 0 means 1)          */
+    int64_t in_stride;      /* elements between trace starts (0 means N)      */
+    int64_t out_stride;     /* complex elements between spectrum rows
+                               (0 means the number of bins written)           */
+    int32_t in_dtype;       /* TZ_F32 or TZ_F64                               */
+    int32_t precision;      /* TZ_FP32, TZ_SPLIT_FP16 or TZ_SPLIT_BF16        */
+    int32_t flags;          /* TZ_HALF                                        */
+    int32_t fir_taps;       /* zoom_fft low-pass length T (0 means 63)        */
+    double fir_cutoff_hz;   /* zoom_fft cut-off f_c (0 means f_s / (2 D))     */
+    void *stream;           /* hipStream_t, NULL = null stream                */
+} tz_opts;
+
+/* Fill *o with the defaults listed above. */
+void tz_opts_init(tz_opts *o);
+
+/*
+ * Zero-padded FFT (Section 2.1, eqs. (2), (3) and (5)).
+ *   X[k] = sum_{n<N} x[n] exp(-j 2 pi k n / N_fft),  N_fft = N + n_zeros,
+ *   k = 0 .. N_fft - 1 (or 0 .. N_fft/2 with TZ_HALF).
+ * n_zeros is the number of zeros appended to the trace (the "x" of eq. (5));
+ * bin k sits at k f_s / N_fft (eq. (3)).
+ * Errors: TZ_EINVAL if x or X is NULL, N < 1, n_zeros < 0, a stride is too
+ * small, or N_fft exceeds 2^31 - 1.
+ */
+tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X,
+                      const tz_opts *opts);
+
+/*
+ * Chirp-Z transform (Section 2.3, eq. (11)), evaluated in Bluestein form
+ * (eqs. (12)-(15)): chirp premultiply, convolution with the conjugate chirp
+ * through FFT / pointwise product / inverse FFT, chirp postmultiply.
+ *   X[k] = sum_{n<N} x[n] A^{-n} W^{k n},  k = 0 .. M-1.
+ * A = A0 e^{j theta0} is the start point and W = W0 e^{-j phi0} the ratio
+ * between contour points (eqs. (16)-(17)).  The GPU path evaluates the unit
+ * circle (|A| = |W| = 1 within 1e-12); other contours give TZ_EUNSUPPORTED.
+ * Errors: TZ_EINVAL for NULL pointers, N < 1, M < 1, zero or non-finite
+ * A or W.
+ */
+tz_status czt(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *X,
+              const tz_opts *opts);
+
+/*
+ * CZT over the band [f1, f2) with M bins and rational phases: f_s, f1 and f2
+ * in whole hertz.  Equivalent to czt() with A = e^{j 2 pi f1/f_s} and
+ * W = e^{-j 2 pi (f2 - f1)/(M f_s)} (eqs. (22)-(23)); bin k sits at
+ * f1 + k (f2 - f1)/M (eq. (24)).  The chirp phase of sample n is reduced as
+ * an exact integer residue before any sine or cosine is taken.
+ * Errors: TZ_EINVAL for NULL pointers, N < 1, M < 1, f_s < 1, f1 < 0,
+ * f2 <= f1.
+ */
+tz_status czt_band_exact(const void *x, int64_t N, int64_t M, int64_t fs_hz,
+                         int64_t f1_hz, int64_t f2_hz, void *X, const tz_opts *opts);
+
+/*
+ * Zoom FFT (Section 2.2, eqs. (6)-(10)).
+ *   f_N = (f1 + f2)/2;  y[n] = x[n] e^{-j 2 pi f_N n / f_s};
+ *   u[m] = sum_{t<T} h[t] y[mD - t],  m < ceil(N/D)   (y = 0 outside [0,N));
+ *   K = round(M f_s / (D (f2 - f1)))  (half away from zero);
+ *   X[k] = sum_m u[m] exp(-j 2 pi (k - floor(M/2)) m / K),  k < M.
+ * h is a T-tap Hamming-windowed sinc with cut-off f_c, normalised to unit
+ * DC gain (it stands in for the ideal low-pass of eq. (8)).  Bin k sits at
+ * f_N + (k - floor(M/2)) f_s / (D K).
+ * Errors: TZ_EINVAL for NULL pointers, N < 1, M < 1, D < 1, T < 1,
+ * non-finite or non-positive f_s, f2 <= f1, f_c <= 0, K < 1.
+ */
+tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2,
+                   int64_t M, int64_t D, void *X, const tz_opts *opts);
+
+/* ---------------------------------------------------------------------- */
+/* Host-only helpers (pure functions, no device work).                     */
+
+/* W and A for M bins over [f1, f2) at rate f_s, eqs. (22)-(23).
+ * TZ_EINVAL if W or A is NULL, M < 1, f_s <= 0 or f2 <= f1. */
+tz_status czt_band(double fs, double f1, double f2, int64_t M, tz_c64 *W, tz_c64 *A);
+
+/* Zeros to append to an N_fft-point transform so that its bin spacing
+ * shrinks by delta (eqs. (4)-(5)): the smallest integer count z with
+ * f_s/N_fft - f_s/(N_fft + z) >= delta.  -1 if delta <= 0, N_fft < 1 or
+ * delta >= f_s/N_fft (no finite count reaches it). */
+int64_t fft_zero_count(double fs, int64_t N_fft, double delta);
+
+/* CZT points giving the bin spacing of an N_fft-point FFT over [f1, f2)
+ * (eq. (25)), rounded to the nearest integer; -1 on invalid input. */
+int64_t czt_points_for_resolution(double fs, double f1, double f2, int64_t N_fft);
+
+/* Short-DFT length K of the Zoom FFT (see zoom_fft); -1 on invalid input. */
+int64_t zoom_short_length(double fs, double f1, double f2, int64_t M, int64_t D);
+
+/* Device FFT length L the CZT path uses for N samples and M bins per block,
+ * and the number of bin blocks (M is split into blocks when N + M - 1
+ * exceeds the largest single-pass length).  TZ_EUNSUPPORTED if N is too long
+ * for the single-pass path. */
+tz_status czt_plan_shape(int64_t N, int64_t M, int64_t *L, int64_t *blocks);
+
+/* ---------------------------------------------------------------------- */
+/* Uneven batch: many traces of different length, band, M and method in   */
+/* one launch (one persistent kernel, captured once in a hipGraph).        */
+
+typedef struct {
+    int32_t kind;        /* TZ_JOB_CZT or TZ_JOB_ZOOM                         */
+    int32_t fir_taps;    /* zoom only (0 means 63)                            */
+    int64_t N;           /* samples of this trace                             */
+    int64_t M;           /* output bins                                       */
+    int64_t D;           /* zoom decimation (ignored for CZT)                 */
+    int64_t fs_hz;       /* sampling rate, whole hertz                        */
+    int64_t f1_hz;       /* band start, whole hertz                           */
+    int64_t f2_hz;       /* band end (exclusive), whole hertz                 */
+    int64_t in_offset;   /* first sample of this trace in x_flat (elements)   */
+    int64_t out_offset;  /* first bin of this spectrum in X_flat (complex)    */
+} tz_job;
+
+typedef struct tz_batch tz_batch;
+
+/* Build device tables for every job, order the jobs longest-first and
+ * record the launch in a hipGraph on opts->stream.  x_flat holds float
+ * samples; X_flat complex float bins.  TZ_EINVAL for an invalid job (its
+ * index is in tz_last_error()). */
+tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opts,
+                          tz_batch **batch);
+/* Run the batch on device buffers x_flat / X_flat (asynchronous on stream). */
+tz_status tz_batch_launch(tz_batch *batch, const void *x_flat, void *X_flat, void *stream);
+/* Free the batch (synchronises the device first). */
+void tz_batch_destroy(tz_batch *batch);
+
+/* ---------------------------------------------------------------------- */
+const char *tz_last_error(void);   /* thread-local message of the last failure */
+const char *tz_version(void);
+void tz_release_plans(void);       /* free every cached plan (synchronises)    */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THZSPEC_H */

@@ -1,0 +1,304 @@
+"""Python binding of libthzspec (HIP, gfx950): zero-padded FFT, chirp-Z
+transform and Zoom FFT of batched THz-TDS traces.
+
+The binding only marshals arguments: every transform runs in the library's
+HIP kernels.  torch is used for device memory and streams.  There is no CPU
+fallback: if ``libthzspec.so`` is missing, or a tensor is not on the GPU,
+the call raises.
+
+Build the library with ``python -m paper_2108_03948_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = [
+    "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_band", "fft_zero_count",
+    "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "lib", "ThzError",
+    "Batch", "release_plans", "version",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libthzspec.so")
+
+TZ_OK, TZ_EINVAL, TZ_ENOMEM, TZ_EDEVICE, TZ_EUNSUPPORTED = range(5)
+TZ_F32, TZ_F64 = 0, 1
+TZ_FP32, TZ_SPLIT_FP16, TZ_SPLIT_BF16 = 0, 1, 2
+TZ_HALF = 1
+TZ_JOB_CZT, TZ_JOB_ZOOM = 0, 1
+PRECISIONS = {"fp32": TZ_FP32, "split_fp16": TZ_SPLIT_FP16, "split_bf16": TZ_SPLIT_BF16}
+_STATUS = {1: "TZ_EINVAL", 2: "TZ_ENOMEM", 3: "TZ_EDEVICE", 4: "TZ_EUNSUPPORTED"}
+
+
+class ThzError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class tz_c64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class tz_opts(ctypes.Structure):
+    _fields_ = [
+        ("batch", ctypes.c_int64), ("in_stride", ctypes.c_int64), ("out_stride", ctypes.c_int64),
+        ("in_dtype", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("fir_taps", ctypes.c_int32), ("fir_cutoff_hz", ctypes.c_double), ("stream", ctypes.c_void_p),
+    ]
+
+
+class tz_job(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("fir_taps", ctypes.c_int32), ("N", ctypes.c_int64),
+        ("M", ctypes.c_int64), ("D", ctypes.c_int64), ("fs_hz", ctypes.c_int64),
+        ("f1_hz", ctypes.c_int64), ("f2_hz", ctypes.c_int64), ("in_offset", ctypes.c_int64),
+        ("out_offset", ctypes.c_int64),
+    ]
+
+
+# every symbol declared in include/thzspec.h
+EXPORTS = (
+    "tz_opts_init", "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_band", "fft_zero_count",
+    "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "tz_batch_create",
+    "tz_batch_launch", "tz_batch_destroy", "tz_last_error", "tz_version", "tz_release_plans",
+)
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libthzspec.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2108_03948_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp, dbl = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
+        po = ctypes.POINTER(tz_opts)
+        L.tz_opts_init.argtypes = [po]
+        L.tz_opts_init.restype = None
+        L.fft_zeropad.argtypes = [vp, i64, i64, vp, po]
+        L.czt.argtypes = [vp, i64, i64, tz_c64, tz_c64, vp, po]
+        L.czt_band_exact.argtypes = [vp, i64, i64, i64, i64, i64, vp, po]
+        L.zoom_fft.argtypes = [vp, i64, dbl, dbl, dbl, i64, i64, vp, po]
+        L.czt_band.argtypes = [dbl, dbl, dbl, i64, ctypes.POINTER(tz_c64), ctypes.POINTER(tz_c64)]
+        L.fft_zero_count.argtypes = [dbl, i64, dbl]
+        L.fft_zero_count.restype = i64
+        L.czt_points_for_resolution.argtypes = [dbl, dbl, dbl, i64]
+        L.czt_points_for_resolution.restype = i64
+        L.zoom_short_length.argtypes = [dbl, dbl, dbl, i64, i64]
+        L.zoom_short_length.restype = i64
+        L.czt_plan_shape.argtypes = [i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.tz_batch_create.argtypes = [ctypes.POINTER(tz_job), i64, po, ctypes.POINTER(vp)]
+        L.tz_batch_launch.argtypes = [vp, vp, vp, vp]
+        L.tz_batch_destroy.argtypes = [vp]
+        L.tz_batch_destroy.restype = None
+        L.tz_last_error.restype = ctypes.c_char_p
+        L.tz_version.restype = ctypes.c_char_p
+        L.tz_release_plans.restype = None
+        for f in ("fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_band", "czt_plan_shape",
+                  "tz_batch_create", "tz_batch_launch"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+        return L
+
+
+def _check(st: int):
+    if st != TZ_OK:
+        raise ThzError(st, lib().tz_last_error().decode())
+
+
+def version() -> str:
+    return lib().tz_version().decode()
+
+
+def release_plans():
+    lib().tz_release_plans()
+
+
+# ---------------------------------------------------------------------------
+# tensor plumbing
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _traces(x):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("x must be a torch tensor on the GPU")
+    if x.dim() == 1:
+        x = x.unsqueeze(0)
+    if x.dim() != 2:
+        raise ValueError("x must be [N] or [B, N]")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
+    if x.stride(1) != 1:
+        x = x.contiguous()
+    return x
+
+
+def _opts(x, out_stride=0, precision="fp32", flags=0, taps=0, cutoff=0.0, stream=None):
+    torch = _torch()
+    o = tz_opts()
+    lib().tz_opts_init(ctypes.byref(o))
+    o.batch = x.shape[0]
+    o.in_stride = x.stride(0) if x.shape[0] > 1 else x.shape[1]
+    o.out_stride = out_stride
+    o.in_dtype = TZ_F64 if x.dtype == torch.float64 else TZ_F32
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.flags = flags
+    o.fir_taps = taps
+    o.fir_cutoff_hz = cutoff
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    return o
+
+
+def _out(x, bins, out):
+    torch = _torch()
+    if out is None:
+        return torch.empty((x.shape[0], bins), dtype=torch.complex64, device=x.device)
+    if out.dtype != torch.complex64 or not out.is_cuda or out.shape != (x.shape[0], bins) or out.stride(1) != 1:
+        raise ValueError("out must be a complex64 GPU tensor [B, bins] with unit inner stride")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# transforms
+# ---------------------------------------------------------------------------
+def fft_zeropad(x, n_zeros: int, *, half: bool = False, out=None, stream=None):
+    """X[k] = sum_{n<N} x[n] exp(-j 2 pi k n / (N + n_zeros)) for each row of x."""
+    x = _traces(x)
+    nfft = x.shape[1] + int(n_zeros)
+    bins = nfft // 2 + 1 if half else nfft
+    out = _out(x, bins, out)
+    o = _opts(x, out.stride(0), flags=TZ_HALF if half else 0, stream=stream)
+    with _torch().cuda.device(x.device):
+        _check(lib().fft_zeropad(x.data_ptr(), x.shape[1], int(n_zeros), out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def czt(x, M: int, W: complex, A: complex, *, out=None, precision="fp32", stream=None):
+    """X[k] = sum_n x[n] A^-n W^(kn), k < M, for each row of x (unit circle)."""
+    x = _traces(x)
+    out = _out(x, int(M), out)
+    o = _opts(x, out.stride(0), precision=precision, stream=stream)
+    W, A = complex(W), complex(A)
+    with _torch().cuda.device(x.device):
+        _check(lib().czt(x.data_ptr(), x.shape[1], int(M), tz_c64(W.real, W.imag), tz_c64(A.real, A.imag),
+                         out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def czt_band_exact(x, M: int, fs_hz: int, f1_hz: int, f2_hz: int, *, out=None, precision="fp32", stream=None):
+    """CZT over [f1, f2) with M bins, integer-hertz band (exact phase residues)."""
+    x = _traces(x)
+    out = _out(x, int(M), out)
+    o = _opts(x, out.stride(0), precision=precision, stream=stream)
+    with _torch().cuda.device(x.device):
+        _check(lib().czt_band_exact(x.data_ptr(), x.shape[1], int(M), int(fs_hz), int(f1_hz), int(f2_hz),
+                                    out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def zoom_fft(x, fs: float, f1: float, f2: float, M: int, D: int, *, taps: int = 63,
+             cutoff_hz: float | None = None, out=None, precision="fp32", stream=None):
+    """Zoom FFT: mix f_N = (f1+f2)/2 to DC, T-tap Hamming low-pass, decimate by
+    D, K-point DFT on M bins centred on f_N."""
+    x = _traces(x)
+    out = _out(x, int(M), out)
+    o = _opts(x, out.stride(0), precision=precision, taps=int(taps), cutoff=float(cutoff_hz or 0.0),
+              stream=stream)
+    with _torch().cuda.device(x.device):
+        _check(lib().zoom_fft(x.data_ptr(), x.shape[1], float(fs), float(f1), float(f2), int(M), int(D),
+                              out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# host helpers
+# ---------------------------------------------------------------------------
+def czt_band(fs: float, f1: float, f2: float, M: int):
+    W, A = tz_c64(), tz_c64()
+    _check(lib().czt_band(float(fs), float(f1), float(f2), int(M), ctypes.byref(W), ctypes.byref(A)))
+    return complex(W.re, W.im), complex(A.re, A.im)
+
+
+def fft_zero_count(fs: float, N_fft: int, delta: float) -> int:
+    return int(lib().fft_zero_count(float(fs), int(N_fft), float(delta)))
+
+
+def czt_points_for_resolution(fs: float, f1: float, f2: float, N_fft: int) -> int:
+    return int(lib().czt_points_for_resolution(float(fs), float(f1), float(f2), int(N_fft)))
+
+
+def zoom_short_length(fs: float, f1: float, f2: float, M: int, D: int) -> int:
+    return int(lib().zoom_short_length(float(fs), float(f1), float(f2), int(M), int(D)))
+
+
+def czt_plan_shape(N: int, M: int):
+    L, blocks = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().czt_plan_shape(int(N), int(M), ctypes.byref(L), ctypes.byref(blocks)))
+    return L.value, blocks.value
+
+
+# ---------------------------------------------------------------------------
+# uneven batch
+# ---------------------------------------------------------------------------
+class Batch:
+    """Many traces of different length / band / M / method in one launch.
+
+    jobs: list of dicts with keys kind ("czt" | "zoom"), N, M, fs_hz, f1_hz,
+    f2_hz, D (zoom), taps (zoom), in_offset, out_offset."""
+
+    def __init__(self, jobs, stream=None):
+        torch = _torch()
+        arr = (tz_job * len(jobs))()
+        for i, j in enumerate(jobs):
+            a = arr[i]
+            a.kind = TZ_JOB_ZOOM if j["kind"] == "zoom" else TZ_JOB_CZT
+            a.fir_taps = int(j.get("taps", 0))
+            a.N, a.M, a.D = int(j["N"]), int(j["M"]), int(j.get("D", 1))
+            a.fs_hz, a.f1_hz, a.f2_hz = int(j["fs_hz"]), int(j["f1_hz"]), int(j["f2_hz"])
+            a.in_offset, a.out_offset = int(j["in_offset"]), int(j["out_offset"])
+        o = tz_opts()
+        lib().tz_opts_init(ctypes.byref(o))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        h = ctypes.c_void_p()
+        _check(lib().tz_batch_create(arr, len(jobs), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.n_jobs = len(jobs)
+
+    def launch(self, x_flat, X_flat, stream=None):
+        torch = _torch()
+        if x_flat.dtype != torch.float32 or X_flat.dtype != torch.complex64:
+            raise TypeError("x_flat must be float32 and X_flat complex64")
+        if not (x_flat.is_cuda and X_flat.is_cuda):
+            raise TypeError("x_flat and X_flat must be GPU tensors")
+        if stream is None:
+            stream = torch.cuda.current_stream(x_flat.device)
+        _check(lib().tz_batch_launch(self._h, x_flat.data_ptr(), X_flat.data_ptr(),
+                                     ctypes.c_void_p(stream.cuda_stream)))
+        return X_flat
+
+    def close(self):
+        if self._h:
+            lib().tz_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,580 @@
+// C-ABI entry points of libthzspec: argument checking, plan selection and
+// caching, and launch of the hot-path kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "thzspec.h"
+
+namespace tz {
+namespace {
+
+thread_local std::string g_err;
+
+tz_status fail(tz_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+tz_status hip_fail(hipError_t e, const char *what) {
+  return fail(e == hipErrorOutOfMemory ? TZ_ENOMEM : TZ_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define TZ_HIP(call, what)                       \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device-side plan storage
+// ---------------------------------------------------------------------------
+struct DevMem {
+  void *p = nullptr;
+  DevMem() = default;
+  DevMem(const DevMem &) = delete;
+  DevMem &operator=(const DevMem &) = delete;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) {
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
+    return hipMalloc(&p, bytes ? bytes : 16);
+  }
+  template <class T>
+  T *as() const { return (T *)p; }
+};
+
+struct BluePlan {
+  int64_t N, M, Ns, Mb;
+  int nseg, nblk, L;
+  DevMem c_pre, c_post, V;
+};
+
+struct ZoomPlan {
+  std::shared_ptr<BluePlan> blue;
+  int64_t LD, K, D;
+  int T;
+  DevMem g, ph, u;
+  size_t u_bytes = 0;
+  std::mutex u_mu;
+};
+
+struct PadPlan {
+  int64_t N, Nfft;
+  int F, P;
+  std::shared_ptr<BluePlan> blue;  // Nfft with no fast factorisation
+};
+
+struct Device {
+  std::map<int64_t, std::unique_ptr<DevMem>> twiddles;  // L -> e^{-j 2 pi m/L}
+  std::map<int64_t, std::unique_ptr<DevMem>> roots;     // Nfft -> e^{-j 2 pi m/Nfft}
+  std::map<std::string, std::shared_ptr<BluePlan>> blue;
+  std::map<std::string, std::shared_ptr<ZoomPlan>> zoom;
+  std::map<std::string, std::shared_ptr<PadPlan>> pad;
+};
+
+std::mutex g_mu;
+std::map<int, std::unique_ptr<Device>> g_dev;
+
+Device &device_state(int dev) {
+  auto &d = g_dev[dev];
+  if (!d) d.reset(new Device());
+  return *d;
+}
+
+int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// FFT length, bin blocks and input segments of the Bluestein path.
+// One workgroup FFT of length L <= kMaxL must hold Ns samples and Mb bins
+// without wrap-around: Ns + Mb - 1 <= L.
+bool czt_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb, int *nblk) {
+  if (N + M - 1 <= kMaxL) {
+    *L = (int)(next_pow2(N + M - 1) < kMinL ? kMinL : next_pow2(N + M - 1));
+    *Ns = N;
+    *nseg = 1;
+    *Mb = M;
+    *nblk = 1;
+    return true;
+  }
+  int64_t best = -1, bNs = 0, bMb = 0;
+  for (int64_t ns = 256; ns <= kMaxL - 256; ns += 256) {
+    int64_t ns_eff = ns < N ? ns : N;
+    int64_t mb = kMaxL - ns_eff + 1;
+    if (mb > M) mb = M;
+    int64_t cost = ((N + ns_eff - 1) / ns_eff) * ((M + mb - 1) / mb);
+    if (best < 0 || cost < best) {
+      best = cost;
+      bNs = ns_eff;
+      bMb = mb;
+    }
+    if (ns >= N) break;
+  }
+  if (best < 0 || best > 256) return false;
+  *L = kMaxL;
+  *Ns = bNs;
+  *nseg = (int)((N + bNs - 1) / bNs);
+  *Mb = bMb;
+  *nblk = (int)((M + bMb - 1) / bMb);
+  return true;
+}
+
+std::string phase_key(const PhaseParams &p) {
+  char buf[160];
+  if (p.rational)
+    snprintf(buf, sizeof buf, "r%lld/%lld/%lld", (long long)p.pa, (long long)p.pw, (long long)p.q);
+  else
+    snprintf(buf, sizeof buf, "f%a/%a", p.a, p.w);
+  return buf;
+}
+
+tz_status get_twiddles(Device &d, int64_t L, hipStream_t s, const float2 **out) {
+  auto &slot = d.twiddles[L];
+  if (!slot) {
+    std::unique_ptr<DevMem> m(new DevMem());
+    TZ_HIP(m->alloc(sizeof(float2) * L), "twiddle table");
+    TZ_HIP(build_twiddles(m->as<float2>(), L, s), "twiddle build");
+    TZ_HIP(hipStreamSynchronize(s), "twiddle build");
+    slot = std::move(m);
+  }
+  *out = slot->as<float2>();
+  return TZ_OK;
+}
+
+tz_status get_roots(Device &d, int64_t Nfft, hipStream_t s, const float2 **out) {
+  auto &slot = d.roots[Nfft];
+  if (!slot) {
+    std::unique_ptr<DevMem> m(new DevMem());
+    TZ_HIP(m->alloc(sizeof(float2) * Nfft), "root table");
+    TZ_HIP(build_root_table(m->as<float2>(), Nfft, Nfft, s), "root build");
+    TZ_HIP(hipStreamSynchronize(s), "root build");
+    slot = std::move(m);
+  }
+  *out = slot->as<float2>();
+  return TZ_OK;
+}
+
+tz_status get_blue(Device &d, int64_t N, int64_t M, const PhaseParams &p, hipStream_t s,
+                   std::shared_ptr<BluePlan> *out) {
+  char kb[96];
+  snprintf(kb, sizeof kb, "%lld/%lld/", (long long)N, (long long)M);
+  std::string key = std::string(kb) + phase_key(p);
+  auto it = d.blue.find(key);
+  if (it != d.blue.end()) {
+    *out = it->second;
+    return TZ_OK;
+  }
+  auto pl = std::make_shared<BluePlan>();
+  pl->N = N;
+  pl->M = M;
+  if (!czt_shape(N, M, &pl->L, &pl->Ns, &pl->nseg, &pl->Mb, &pl->nblk))
+    return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld needs more than 256 single-pass FFT blocks",
+                (long long)N, (long long)M);
+  TZ_HIP(pl->c_pre.alloc(sizeof(float2) * pl->Ns * pl->nblk), "chirp table");
+  TZ_HIP(pl->c_post.alloc(sizeof(float2) * pl->Mb * pl->nblk * pl->nseg), "chirp table");
+  TZ_HIP(pl->V.alloc(sizeof(float2) * pl->L), "chirp spectrum");
+  TZ_HIP(build_bluestein_tables(p, pl->Ns, pl->nseg, pl->Mb, pl->nblk, pl->L, pl->c_pre.as<float2>(),
+                                pl->c_post.as<float2>(), pl->V.as<float2>(), s),
+         "chirp tables");
+  TZ_HIP(hipStreamSynchronize(s), "chirp tables");
+  d.blue[key] = pl;
+  *out = pl;
+  return TZ_OK;
+}
+
+struct Common {
+  int64_t B, xs, os;
+  int in_kind;
+  int precision, flags;
+  hipStream_t stream;
+};
+
+tz_status check_common(const void *x, int64_t N, void *X, const tz_opts *o, int64_t bins, Common *c) {
+  tz_opts def;
+  tz_opts_init(&def);
+  if (!o) o = &def;
+  if (!x || !X) return fail(TZ_EINVAL, "x and X must be device pointers, got NULL");
+  if (N < 1) return fail(TZ_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
+  c->B = o->batch == 0 ? 1 : o->batch;
+  if (c->B < 1) return fail(TZ_EINVAL, "batch must be >= 1 (got %lld)", (long long)o->batch);
+  c->xs = o->in_stride == 0 ? N : o->in_stride;
+  if (c->xs < N && c->B > 1) return fail(TZ_EINVAL, "in_stride %lld < N %lld", (long long)c->xs, (long long)N);
+  c->os = o->out_stride == 0 ? bins : o->out_stride;
+  if (c->os < bins && c->B > 1)
+    return fail(TZ_EINVAL, "out_stride %lld < bins %lld", (long long)c->os, (long long)bins);
+  if (o->in_dtype != TZ_F32 && o->in_dtype != TZ_F64)
+    return fail(TZ_EINVAL, "in_dtype must be TZ_F32 or TZ_F64");
+  c->in_kind = o->in_dtype == TZ_F64 ? 1 : 0;
+  c->precision = o->precision;
+  if (c->precision != TZ_FP32 && c->precision != TZ_SPLIT_FP16 && c->precision != TZ_SPLIT_BF16)
+    return fail(TZ_EINVAL, "unknown precision %d", c->precision);
+  c->flags = o->flags;
+  c->stream = (hipStream_t)o->stream;
+  if (c->B * (c->xs > c->os ? c->xs : c->os) > ((int64_t)1 << 46))
+    return fail(TZ_EINVAL, "batch too large");
+  return TZ_OK;
+}
+
+bool unit(tz_c64 z) { return fabs(hypot(z.re, z.im) - 1.0) <= 1e-12; }
+bool finite_nonzero(tz_c64 z) { return isfinite(z.re) && isfinite(z.im) && (z.re != 0.0 || z.im != 0.0); }
+
+double frac01(double v) { return v - floor(v); }
+
+tz_status run_blue(Device &d, const BluePlan &pl, const void *x, int in_kind, void *X, const Common &c,
+                   hipStream_t s) {
+  const float2 *tw = nullptr;
+  tz_status st = get_twiddles(d, pl.L, s, &tw);
+  if (st) return st;
+  CztLaunch a;
+  a.x = x;
+  a.in_kind = in_kind;
+  a.xs = c.xs;
+  a.N = pl.N;
+  a.Ns = pl.Ns;
+  a.nseg = pl.nseg;
+  a.c_pre = pl.c_pre.as<float2>();
+  a.c_post = pl.c_post.as<float2>();
+  a.V = pl.V.as<float2>();
+  a.tw = tw;
+  a.X = (float2 *)X;
+  a.os = c.os;
+  a.M = pl.M;
+  a.Mb = pl.Mb;
+  a.nblk = pl.nblk;
+  a.L = pl.L;
+  a.B = c.B;
+  a.precision = c.precision;
+  TZ_HIP(launch_czt(a, s), "czt launch");
+  return TZ_OK;
+}
+
+int current_device() {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return dev;
+}
+
+// reduce n/d (d > 0) and return via num/den
+void reduce(__int128 &n, __int128 &d) {
+  __int128 a = n < 0 ? -n : n, b = d;
+  while (b) {
+    __int128 t = a % b;
+    a = b;
+    b = t;
+  }
+  if (a > 1) {
+    n /= a;
+    d /= a;
+  }
+}
+
+}  // namespace
+}  // namespace tz
+
+using namespace tz;
+
+// ===========================================================================
+extern "C" {
+
+void tz_opts_init(tz_opts *o) {
+  if (!o) return;
+  memset(o, 0, sizeof *o);
+  o->batch = 1;
+  o->in_dtype = TZ_F32;
+  o->precision = TZ_FP32;
+}
+
+const char *tz_last_error(void) { return g_err.c_str(); }
+const char *tz_version(void) { return "thzspec 0.1 gfx950"; }
+
+tz_status czt(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *X, const tz_opts *o) {
+  if (M < 1) return fail(TZ_EINVAL, "M must be >= 1 (got %lld)", (long long)M);
+  if (!finite_nonzero(W) || !finite_nonzero(A)) return fail(TZ_EINVAL, "W and A must be finite and non-zero");
+  Common c;
+  tz_status st = check_common(x, N, X, o, M, &c);
+  if (st) return st;
+  if (!unit(W) || !unit(A))
+    return fail(TZ_EUNSUPPORTED, "GPU path evaluates the unit circle only (|A| = |W| = 1)");
+  PhaseParams p{};
+  p.rational = 0;
+  p.a = frac01(atan2(A.im, A.re) / (2.0 * M_PI));
+  p.w = frac01(-atan2(W.im, W.re) / (2.0 * M_PI));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  std::shared_ptr<BluePlan> pl;
+  if ((st = get_blue(d, N, M, p, c.stream, &pl))) return st;
+  return run_blue(d, *pl, x, c.in_kind, X, c, c.stream);
+}
+
+tz_status czt_band_exact(const void *x, int64_t N, int64_t M, int64_t fs_hz, int64_t f1_hz, int64_t f2_hz,
+                         void *X, const tz_opts *o) {
+  if (M < 1) return fail(TZ_EINVAL, "M must be >= 1 (got %lld)", (long long)M);
+  if (fs_hz < 1 || f1_hz < 0 || f2_hz <= f1_hz) return fail(TZ_EINVAL, "need fs >= 1, f1 >= 0, f2 > f1");
+  Common c;
+  tz_status st = check_common(x, N, X, o, M, &c);
+  if (st) return st;
+  // a = f1/fs, w = (f2-f1)/(M fs), reduced to a common denominator q
+  __int128 na = f1_hz % fs_hz, da = fs_hz;
+  __int128 nw = f2_hz - f1_hz, dw = (__int128)M * fs_hz;
+  reduce(na, da);
+  reduce(nw, dw);
+  __int128 g = da, h = dw;
+  while (h) {
+    __int128 t = g % h;
+    g = h;
+    h = t;
+  }
+  __int128 q = da / g * dw;
+  PhaseParams p{};
+  if (q < ((__int128)1 << 61)) {
+    p.rational = 1;
+    p.q = (int64_t)q;
+    p.pa = (int64_t)(na * (q / da) % q);
+    p.pw = (int64_t)(nw * (q / dw) % q);
+  } else {
+    p.rational = 0;
+  }
+  p.a = frac01((double)f1_hz / (double)fs_hz);
+  p.w = frac01((double)(f2_hz - f1_hz) / ((double)M * (double)fs_hz));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  std::shared_ptr<BluePlan> pl;
+  if ((st = get_blue(d, N, M, p, c.stream, &pl))) return st;
+  return run_blue(d, *pl, x, c.in_kind, X, c, c.stream);
+}
+
+tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const tz_opts *o) {
+  if (n_zeros < 0) return fail(TZ_EINVAL, "n_zeros must be >= 0 (got %lld)", (long long)n_zeros);
+  const int64_t nfft = N + n_zeros;
+  if (nfft > INT32_MAX) return fail(TZ_EINVAL, "N + n_zeros exceeds 2^31 - 1");
+  const bool half = o && (o->flags & TZ_HALF);
+  const int64_t nout = half ? nfft / 2 + 1 : nfft;
+  Common c;
+  tz_status st = check_common(x, N, X, o, nout, &c);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  char kb[64];
+  snprintf(kb, sizeof kb, "%lld/%lld", (long long)N, (long long)nfft);
+  auto &pp = d.pad[kb];
+  if (!pp) {
+    auto pl = std::make_shared<PadPlan>();
+    pl->N = N;
+    pl->Nfft = nfft;
+    pl->F = 0;
+    for (int64_t F = kMinL; F <= kMaxL; F <<= 1)
+      if (F >= N && nfft % F == 0) {
+        pl->F = (int)F;
+        pl->P = (int)(nfft / F);
+        break;
+      }
+    if (!pl->F) {  // no power-of-two factor >= N: evaluate the same bins as a CZT
+      PhaseParams p{};
+      p.rational = 1;
+      p.q = nfft;
+      p.pa = 0;
+      p.pw = 1;
+      p.a = 0.0;
+      p.w = 1.0 / (double)nfft;
+      if ((st = get_blue(d, N, nfft, p, c.stream, &pl->blue))) return st;
+    }
+    pp = pl;
+  }
+  if (pp->blue) {
+    const Common &c2 = c;
+    // the cached Bluestein plan evaluates all Nfft bins; with TZ_HALF only
+    // the first nout rows are wanted, so M is clipped at launch time
+    const float2 *tw = nullptr;
+    if ((st = get_twiddles(d, pp->blue->L, c.stream, &tw))) return st;
+    CztLaunch a;
+    a.x = x;
+    a.in_kind = c.in_kind;
+    a.xs = c2.xs;
+    a.N = N;
+    a.Ns = pp->blue->Ns;
+    a.nseg = pp->blue->nseg;
+    a.c_pre = pp->blue->c_pre.as<float2>();
+    a.c_post = pp->blue->c_post.as<float2>();
+    a.V = pp->blue->V.as<float2>();
+    a.tw = tw;
+    a.X = (float2 *)X;
+    a.os = c2.os;
+    a.M = nout;
+    a.Mb = pp->blue->Mb;
+    a.nblk = pp->blue->nblk;
+    a.L = pp->blue->L;
+    a.B = c.B;
+    a.precision = c.precision;
+    TZ_HIP(launch_czt(a, c.stream), "fft_zeropad (czt) launch");
+    return TZ_OK;
+  }
+  const float2 *tw = nullptr, *root = nullptr;
+  if ((st = get_twiddles(d, pp->F, c.stream, &tw))) return st;
+  if (pp->P > 1 && (st = get_roots(d, nfft, c.stream, &root))) return st;
+  PadLaunch a;
+  a.x = x;
+  a.in_kind = c.in_kind;
+  a.xs = c.xs;
+  a.N = N;
+  a.F = pp->F;
+  a.P = pp->P;
+  a.tw = tw;
+  a.root = root;
+  a.X = (float2 *)X;
+  a.os = c.os;
+  a.nout = nout;
+  a.B = c.B;
+  TZ_HIP(launch_fftpad(a, c.stream), "fft_zeropad launch");
+  return TZ_OK;
+}
+
+tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, int64_t M, int64_t D, void *X,
+                   const tz_opts *o) {
+  if (M < 1 || D < 1) return fail(TZ_EINVAL, "M and D must be >= 1");
+  if (!isfinite(fs) || !isfinite(f1) || !isfinite(f2) || fs <= 0.0 || f2 <= f1)
+    return fail(TZ_EINVAL, "need finite fs > 0 and f2 > f1");
+  const int T = (o && o->fir_taps) ? o->fir_taps : 63;
+  if (T < 1) return fail(TZ_EINVAL, "fir_taps must be >= 1");
+  const double fc = (o && o->fir_cutoff_hz != 0.0) ? o->fir_cutoff_hz : fs / (2.0 * (double)D);
+  if (!(fc > 0.0) || !isfinite(fc)) return fail(TZ_EINVAL, "fir_cutoff_hz must be > 0");
+  const int64_t K = zoom_short_length(fs, f1, f2, M, D);
+  if (K < 1) return fail(TZ_EINVAL, "short-DFT length K = round(M fs / (D (f2 - f1))) is < 1");
+  Common c;
+  tz_status st = check_common(x, N, X, o, M, &c);
+  if (st) return st;
+  const int64_t LD = (N + D - 1) / D;
+  const double nuN = 0.5 * (f1 + f2) / fs;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  char kb[200];
+  snprintf(kb, sizeof kb, "%lld/%lld/%lld/%d/%a/%a/%lld", (long long)N, (long long)M, (long long)D, T,
+           nuN - floor(nuN), fc / fs, (long long)K);
+  auto &zp = d.zoom[kb];
+  if (!zp) {
+    auto pl = std::make_shared<ZoomPlan>();
+    pl->LD = LD;
+    pl->K = K;
+    pl->D = D;
+    pl->T = T;
+    // short DFT: X[k] = sum_m u[m] e^{-j 2 pi (k - floor(M/2)) m / K}: a CZT with
+    // W = e^{-j 2 pi / K} and A = e^{-j 2 pi floor(M/2) / K} (rational, q = K)
+    PhaseParams p{};
+    p.rational = 1;
+    p.q = K;
+    p.pw = 1 % K;
+    p.pa = (K - (M / 2) % K) % K;
+    p.w = 1.0 / (double)K;
+    p.a = (double)p.pa / (double)K;
+    if ((st = get_blue(d, LD, M, p, c.stream, &pl->blue))) return st;
+    TZ_HIP(pl->g.alloc(sizeof(float2) * T), "zoom taps");
+    TZ_HIP(pl->ph.alloc(sizeof(float2) * LD), "zoom phasors");
+    TZ_HIP(build_zoom_tables(pl->g.as<float2>(), T, fc / fs, nuN - floor(nuN), pl->ph.as<float2>(), LD, D,
+                             c.stream),
+           "zoom tables");
+    TZ_HIP(hipStreamSynchronize(c.stream), "zoom tables");
+    zp = pl;
+  }
+  ZoomPlan &z = *zp;
+  const size_t ub = sizeof(float2) * (size_t)LD * (size_t)c.B;
+  if (ub > z.u_bytes) {
+    TZ_HIP(hipStreamSynchronize(c.stream), "zoom workspace");
+    TZ_HIP(z.u.alloc(ub), "zoom workspace");
+    z.u_bytes = ub;
+  }
+  ZoomFrontLaunch f;
+  f.x = x;
+  f.in_kind = c.in_kind;
+  f.xs = c.xs;
+  f.N = N;
+  f.D = D;
+  f.LD = LD;
+  f.T = T;
+  f.g = z.g.as<float2>();
+  f.ph = z.ph.as<float2>();
+  f.u = z.u.as<float2>();
+  f.B = c.B;
+  TZ_HIP(launch_zoom_front(f, c.stream), "zoom front-end launch");
+  Common c2 = c;
+  c2.xs = LD;
+  return run_blue(d, *z.blue, z.u.p, 2, X, c2, c.stream);
+}
+
+// ---------------------------------------------------------------------------
+tz_status czt_band(double fs, double f1, double f2, int64_t M, tz_c64 *W, tz_c64 *A) {
+  if (!W || !A) return fail(TZ_EINVAL, "W and A must not be NULL");
+  if (M < 1 || !(fs > 0.0) || !isfinite(fs) || !isfinite(f1) || !isfinite(f2) || !(f2 > f1))
+    return fail(TZ_EINVAL, "need M >= 1, fs > 0, f2 > f1");
+  const double w = (f2 - f1) / ((double)M * fs);
+  const double a = f1 / fs;
+  W->re = cos(2.0 * M_PI * w);
+  W->im = -sin(2.0 * M_PI * w);
+  A->re = cos(2.0 * M_PI * a);
+  A->im = sin(2.0 * M_PI * a);
+  return TZ_OK;
+}
+
+int64_t fft_zero_count(double fs, int64_t N_fft, double delta) {
+  if (!(fs > 0.0) || N_fft < 1 || !(delta > 0.0) || !isfinite(delta)) return -1;
+  const double df = fs / (double)N_fft;
+  if (delta >= df) return -1;
+  // eq. (5): x = fs N / (fs - delta N) - N
+  double xz = fs * (double)N_fft / (fs - delta * (double)N_fft) - (double)N_fft;
+  int64_t z = (int64_t)ceil(xz);
+  if (z < 0) z = 0;
+  // settle rounding at the boundary against eq. (4) itself
+  while (z > 0 && df - fs / (double)(N_fft + z - 1) >= delta) --z;
+  while (df - fs / (double)(N_fft + z) < delta) ++z;
+  return z;
+}
+
+int64_t czt_points_for_resolution(double fs, double f1, double f2, int64_t N_fft) {
+  if (!(fs > 0.0) || !(f2 > f1) || N_fft < 1) return -1;
+  return (int64_t)llround((f2 - f1) / fs * (double)N_fft);
+}
+
+int64_t zoom_short_length(double fs, double f1, double f2, int64_t M, int64_t D) {
+  if (!(fs > 0.0) || !(f2 > f1) || M < 1 || D < 1 || !isfinite(fs) || !isfinite(f1) || !isfinite(f2))
+    return -1;
+  return (int64_t)llround((double)M * fs / ((double)D * (f2 - f1)));
+}
+
+tz_status czt_plan_shape(int64_t N, int64_t M, int64_t *L, int64_t *blocks) {
+  if (N < 1 || M < 1 || !L || !blocks) return fail(TZ_EINVAL, "need N, M >= 1 and non-NULL outputs");
+  int l, nseg, nblk;
+  int64_t ns, mb;
+  if (!czt_shape(N, M, &l, &ns, &nseg, &mb, &nblk))
+    return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld too long for the single-pass path", (long long)N,
+                (long long)M);
+  *L = l;
+  *blocks = (int64_t)nblk * nseg;
+  return TZ_OK;
+}
+
+void tz_release_plans(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  (void)hipDeviceSynchronize();
+  g_dev.clear();
+}
+
+}  // extern "C"

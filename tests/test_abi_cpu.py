@@ -1,0 +1,151 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol declared in
+include/thzspec.h, its host helpers follow the paper's formulas and values,
+and invalid arguments are rejected before any device work."""
+import ctypes
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "thzspec.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_values.json")
+
+
+@pytest.fixture(scope="module")
+def tz():
+    import paper_2108_03948_amd as tz
+    if not os.path.exists(tz.LIB_PATH):
+        from paper_2108_03948_amd import build
+        build.build()
+    tz.lib()
+    return tz
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(tz):
+    declared = header_functions()
+    assert "czt" in declared and "fft_zeropad" in declared and "zoom_fft" in declared
+    L = ctypes.CDLL(tz.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), f"{name} declared in thzspec.h but not exported"
+    assert sorted(tz.EXPORTS) == declared
+
+
+def test_version(tz):
+    assert "gfx950" in tz.version()
+
+
+def test_czt_band_eq22_23(tz):
+    fs, f1, f2, M = 20e12, 0.2e12, 2.5e12, 4096
+    W, A = tz.czt_band(fs, f1, f2, M)
+    assert abs(W - np.exp(-2j * np.pi * (f2 - f1) / (M * fs))) < 1e-15
+    assert abs(A - np.exp(2j * np.pi * f1 / fs)) < 1e-15
+    with pytest.raises(tz.ThzError):
+        tz.czt_band(fs, f2, f1, M)
+
+
+def test_fft_zero_count_inverts_eq4(tz):
+    # eq. (5) gives the zeros x reaching a resolution change delta (eq. (4))
+    g = json.load(open(GOLDEN))["timing_sweep_step"]
+    fs, N = 10e12, 500                      # Section 3.2: T_s = 100 fs, N = 500
+    df = fs / N
+    assert df == pytest.approx(g["start_hz"])
+    for steps in range(1, 30):
+        delta = steps * g["step_hz"]        # Fig. 11: 0.5 GHz steps from 20 GHz
+        z = tz.fft_zero_count(fs, N, delta)
+        assert df - fs / (N + z) >= delta * (1 - 1e-12)
+        assert z == 0 or df - fs / (N + z - 1) < delta
+        x = fs * N / (fs - delta * N) - N   # eq. (5) with L = N_FFT
+        assert z == math.ceil(x - 1e-9)
+    assert tz.fft_zero_count(fs, N, df) == -1
+    assert tz.fft_zero_count(fs, N, 0.0) == -1
+
+
+def test_paper_resolutions_through_helpers(tz):
+    g = json.load(open(GOLDEN))
+    # eq. (25): CZT points over [f1, f2) matching an N_FFT-point FFT's spacing
+    assert tz.czt_points_for_resolution(8000, 100, 1000, 128) == round(900 / 8000 * 128)
+    e = g["thz_fft_resolution_N500"]
+    fs = 1.0 / e["Ts_s"]
+    assert fs / e["N"] == pytest.approx(e["printed_hz"])
+    # a CZT with M = N over a band B has spacing B/N; 2.98 GHz at N = 500
+    # means B = 1.49 THz, and the same band at N = 250 gives 5.96 GHz
+    c500, c250 = g["thz_czt_resolution_N500"], g["thz_czt_resolution_N250"]
+    band = c500["printed_hz"] * 500
+    W, _ = tz.czt_band(fs, 0.0, band, 250)
+    assert -np.angle(W) / (2 * np.pi) * fs == pytest.approx(c250["printed_hz"], rel=1e-12)
+
+
+def test_zoom_short_length(tz):
+    assert tz.zoom_short_length(20e12, 0.1e12, 3.0e12, 1024, 8) == 883
+    assert tz.zoom_short_length(100e12, 0.05e12, 0.10e12, 1 << 18, 64) == 8_192_000
+    assert tz.zoom_short_length(20e12, 0.2e12, 2.5e12, 4096, 6) == 5936
+    assert tz.zoom_short_length(10.0, 0.0, 4.0, 1, 1) == 3  # 2.5 rounds away from zero
+    assert tz.zoom_short_length(1.0, 2.0, 1.0, 1, 1) == -1
+
+
+def test_czt_plan_shape(tz):
+    assert tz.czt_plan_shape(4096, 4096) == (8192, 1)
+    assert tz.czt_plan_shape(1024, 1024) == (2048, 1)
+    assert tz.czt_plan_shape(1, 1) == (256, 1)
+    assert tz.czt_plan_shape(8193, 8192) == (16384, 1)
+    L, blocks = tz.czt_plan_shape(16384, 8192)
+    assert L == 16384 and blocks > 1
+
+
+def _raw(tz, fn, *args):
+    st = fn(*args)
+    return st, tz.lib().tz_last_error().decode()
+
+
+def test_invalid_arguments_rejected_before_device_work(tz):
+    L = tz.lib()
+    o = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(o))
+    one = tz.tz_c64(1.0, 0.0)
+    w = tz.tz_c64(math.cos(0.1), -math.sin(0.1))
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation
+    cases = [
+        (L.czt, (None, 10, 10, w, one, fake, ctypes.byref(o)), "NULL"),
+        (L.czt, (fake, 0, 10, w, one, fake, ctypes.byref(o)), "N must be"),
+        (L.czt, (fake, 10, 0, w, one, fake, ctypes.byref(o)), "M must be"),
+        (L.czt, (fake, 10, 10, tz.tz_c64(0.0, 0.0), one, fake, ctypes.byref(o)), "non-zero"),
+        (L.czt, (fake, 10, 10, tz.tz_c64(float("nan"), 0.0), one, fake, ctypes.byref(o)), "finite"),
+        (L.fft_zeropad, (fake, 10, -1, fake, ctypes.byref(o)), "n_zeros"),
+        (L.fft_zeropad, (fake, 10, 1 << 31, fake, ctypes.byref(o)), "2^31"),
+        (L.zoom_fft, (fake, 100, 20e12, 2e12, 1e12, 64, 4, fake, ctypes.byref(o)), "f2 > f1"),
+        (L.zoom_fft, (fake, 100, 20e12, 1e12, 2e12, 64, 0, fake, ctypes.byref(o)), "D must be"),
+        (L.czt_band_exact, (fake, 10, 10, 0, 1, 2, fake, ctypes.byref(o)), "fs >= 1"),
+    ]
+    for fn, args, msg in cases:
+        st, err = _raw(tz, fn, *args)
+        assert st == tz.TZ_EINVAL, (fn.__name__, st, err)
+        assert msg in err, (fn.__name__, err)
+    # a spiral contour is valid input but outside the GPU path
+    o2 = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(o2))
+    st, err = _raw(tz, L.czt, fake, 10, 10, tz.tz_c64(1.01, 0.0), one, fake, ctypes.byref(o2))
+    assert st == tz.TZ_EUNSUPPORTED and "unit circle" in err
+    # strides smaller than a row
+    o3 = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(o3))
+    o3.batch, o3.in_stride = 4, 5
+    st, err = _raw(tz, L.czt, fake, 10, 10, w, one, fake, ctypes.byref(o3))
+    assert st == tz.TZ_EINVAL and "in_stride" in err
+
+
+def test_binding_refuses_cpu_tensors(tz):
+    import torch
+    with pytest.raises(TypeError):
+        tz.czt(torch.zeros(4, 16), 8, 1.0, 1.0)
