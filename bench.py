@@ -1,0 +1,267 @@
+"""Benchmark: spectra of a batch of THz-TDS traces on one MI355X.
+
+Workload (one "step" = one pass of the whole path over the batch):
+  8192 synthetic traces (4096 sample/reference pairs) x 4096 FP32 samples at
+  f_s = 20 THz, already resident in HBM;
+    czt         M = 4096 bins over 0.2 - 2.5 THz        (Bluestein, L = 8192)
+    fft_zeropad to N_fft = 65536 (61440 zeros)          (16 x 4096-point FFTs)
+    zoom_fft    same band, M = 4096, D = 6, 63 taps     (K = 5936)
+value = CZT outputs (8192 x 4096 bins) per second of the whole step.
+The same run reports each transform's own rate, the roofline of the
+dominant kernel (HIP events on the launch stream), and the FP64 oracle timed
+on the host cores over a bounded sample.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--calib-copy]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CZT outputs/s over batched THz traces; %HBM peak; MFMA vs FP32 at 1e-5 err"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ["paper_2108_03948_amd/csrc/kernels.hip", "paper_2108_03948_amd/csrc/fft_core.h"]
+
+N_PAIRS, N, FS = 4096, 4096, 20e12
+F1, F2, M = 0.2e12, 2.5e12, 4096
+NFFT = 65536
+ZOOM_D, ZOOM_T = 6, 63
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# algorithmic work per launch (minimum bytes: read x once, write X once;
+# flops: 5 L log2 L per complex FFT plus the pointwise complex products)
+def fft_work(B):
+    by = B * (N * 4 + NFFT * 8)
+    P, F = NFFT // 4096, 4096
+    fl = B * P * (5 * F * 12 + 6 * N)
+    return by, fl
+
+
+def czt_work(B, L=8192):
+    by = B * (N * 4 + M * 8)
+    fl = B * (2 * 5 * L * 13 + 6 * (N + L + M))
+    return by, fl
+
+
+def zoom_work(B):
+    LD = -(-N // ZOOM_D)
+    by = B * (N * 4 + M * 8)
+    fl = B * (LD * ZOOM_T * 4 + 2 * 5 * 8192 * 13 + 6 * (LD + 8192 + M))
+    return by, fl
+
+
+def cpu_baseline(x_np, budget_s=12.0):
+    """Time the FP64 oracle on a bounded sample of the same workload and
+    scale it to CZT outputs per second of the whole step."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    x64 = x_np.astype(np.float64)
+    W = np.exp(-2j * np.pi * (F2 - F1) / (M * FS))
+    A = np.exp(2j * np.pi * F1 / FS)
+    # calibrate on one trace, then size the sample to the budget
+    t0 = time.perf_counter()
+    oracle.czt(x64[:1], M, W, A)
+    t_czt1 = time.perf_counter() - t0
+    n = max(1, min(64, int(budget_s * 0.5 / max(t_czt1, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.czt(x64[:n], M, W, A)
+    t_czt = (time.perf_counter() - t0) / n
+    fb = np.arange(0, NFFT, 16)          # every 16th bin of the zero-padded FFT
+    nf = max(1, n // 4)
+    t0 = time.perf_counter()
+    oracle.fft_zeropad(x64[:nf], NFFT - N, fb)
+    t_fft = (time.perf_counter() - t0) / nf * (NFFT / fb.size)
+    t0 = time.perf_counter()
+    oracle.zoom_fft(x64[:nf], FS, F1, F2, M, ZOOM_D, taps=ZOOM_T)
+    t_zoom = (time.perf_counter() - t0) / nf
+    per_trace = t_czt + t_fft + t_zoom
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return {
+        "value": M / per_trace,
+        "unit": "CZT outputs/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"FP64 direct-summation oracle, {cores} OpenMP threads: czt on {n} traces x {M} bins, "
+                   f"zoom on {nf} traces x {M} bins, fft_zeropad on {nf} traces x every 16th of {NFFT} "
+                   f"bins (scaled x16); per-trace times summed and scaled to the 8192-trace step"),
+        "seconds_per_trace": {"czt": t_czt, "fft_zeropad": t_fft, "zoom": t_zoom},
+        "extrapolated_step_s": per_trace * 2 * N_PAIRS,
+        "cpu_model": _cpu_model(),
+    }
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 1 GiB device copy (calibrates rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the per-trace path has no "
+              "cross-GPU step, see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2108_03948_amd as tz
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("bench: generating 8192 x 4096 synthetic traces")
+    x_np = synth.pairs(N_PAIRS, N=N, fs=FS)
+    x = torch.from_numpy(x_np).to(dev)
+    B = x.shape[0]
+    W, A = tz.czt_band(FS, F1, F2, M)
+    Xc = torch.empty((B, M), dtype=torch.complex64, device=dev)
+    Xf = torch.empty((B, NFFT), dtype=torch.complex64, device=dev)
+    Xz = torch.empty((B, M), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        tz.czt(x, M, W, A, out=Xc, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        tz.fft_zeropad(x, NFFT - N, out=Xf, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+        tz.zoom_fft(x, FS, F1, F2, M, ZOOM_D, taps=ZOOM_T, out=Xz, stream=stream)
+        if ev is not None:
+            ev[3].record(stream)
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of 1 GiB done")
+
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    log(f"bench: timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step_events = sum(e[0].elapsed_time(e[3]) for e in evs) / args.steps
+    ms_czt = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    ms_fft = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    ms_zoom = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    log(f"bench: step {ms_per_step:.3f} ms (events {ms_step_events:.3f}); czt {ms_czt:.3f}, "
+        f"fft_zeropad {ms_fft:.3f}, zoom {ms_zoom:.3f} ms")
+
+    kernels = {}
+    for name, ms, (by, fl), bins in (("czt", ms_czt, czt_work(B), B * M),
+                                     ("fft_zeropad", ms_fft, fft_work(B), B * NFFT),
+                                     ("zoom_fft", ms_zoom, zoom_work(B), B * M)):
+        kernels[name] = {
+            "ms": ms, "bins_per_s": bins / (ms * 1e-3),
+            "alg_bytes": by, "alg_flops": fl,
+            "GBps": by / (ms * 1e-3) / 1e9, "hbm_frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "TFLOPs": fl / (ms * 1e-3) / 1e12, "fp32_frac": fl / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+        }
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    dk = kernels[dom]
+    hbm_bound = dk["alg_flops"] / dk["alg_bytes"] < FP32_VECTOR_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    traffic = None
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("source_hash") == kernel_source_hash() and dom in t.get("kernels", {}):
+            traffic = t["kernels"][dom]["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
+    if hbm_bound:
+        roof = {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["hbm_frac"], "traffic": traffic, "kernel": dom}
+    else:
+        roof = {"bound": "alu", "achieved": dk["TFLOPs"], "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": dk["fp32_frac"], "traffic": traffic, "kernel": dom}
+
+    # a sampled parity check of this very run (oracle on 2 traces)
+    import oracle
+    rows = [0, B - 1]
+    x64 = x_np[rows].astype(np.float64)
+    ref = oracle.czt(x64, M, W, A)
+    got = Xc[rows].cpu().numpy()
+    err = float(np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)))
+
+    out = {
+        "metric": METRIC,
+        "value": B * M / (ms_per_step * 1e-3),
+        "unit": "CZT outputs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "8192 THz-TDS traces (4096 sample/reference pairs) x 4096 FP32 samples, fs 20 THz; "
+                        "per step: czt M=4096 over 0.2-2.5 THz + fft_zeropad to 65536 + zoom_fft "
+                        "(same band, M=4096, D=6, 63 taps)",
+            "traces": B, "samples": N, "czt_bins": M, "fft_bins": NFFT, "zoom_decimation": ZOOM_D,
+            "zoom_taps": ZOOM_T,
+        },
+        "roofline": roof,
+        "czt_only": {"value": B * M / (ms_czt * 1e-3), "ms": ms_czt},
+        "kernels": kernels,
+        "mfma_vs_fp32": None,
+        "czt_rel_l2_sampled": err,
+    }
+    if not args.no_cpu:
+        log("bench: timing the FP64 oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(x_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,69 @@
+"""Summarise rocprofv3 output of bench.py into short text files under profiles/.
+
+  python bench_profiles.py stats <kernel_stats.csv> <out.md> "<command>"
+  python bench_profiles.py traffic <fetch_counter.csv> <write_counter.csv> <out.json> "<cmd>"
+
+Byte counters are scaled by what the same counters read for the 1 GiB device
+copy that ``bench.py --calib-copy`` runs first (dispatch with the largest grid
+among the runtime's copy kernels).
+"""
+from __future__ import annotations
+
+import csv
+import json
+import os
+import sys
+
+KERNEL_KEYS = {"czt": "k_czt<8192, 0", "fft_zeropad": "k_fftpad", "zoom_front": "k_zoom_front",
+               "zoom_short_dft": "k_czt<8192, 2"}
+
+
+def stats(path, out, cmd):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics\n", f"Command:\n\n    {cmd}\n",
+             "| kernel | calls | average (us) | min (us) | max (us) | share (%) |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].split("(")[0]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.2f} | "
+                     f"{float(r['MinNs'])/1e3:.2f} | {float(r['MaxNs'])/1e3:.2f} | {float(r['Percentage']):.2f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def _per_dispatch(path, counter):
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            out.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return out
+
+
+def traffic(fetch_csv, write_csv, out, cmd, source_hash):
+    f = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = _per_dispatch(write_csv, "WRITE_SIZE")
+    copy_f = max((x for x in f if "copyBuffer" in x[0]), key=lambda x: x[1])
+    copy_w = max((x for x in w if "copyBuffer" in x[0]), key=lambda x: x[1])
+    gib_kib = 1024.0 * 1024.0
+    sf, sw = gib_kib / copy_f[2], gib_kib / copy_w[2]
+    res = {"command": cmd, "source_hash": source_hash,
+           "calibration": {"copy_bytes": 1 << 30, "fetch_kib": copy_f[2], "write_kib": copy_w[2],
+                           "fetch_scale": sf, "write_scale": sw},
+           "kernels": {}}
+    for name, key in KERNEL_KEYS.items():
+        fv = [x[2] for x in f if key in x[0]]
+        wv = [x[2] for x in w if key in x[0]]
+        if fv and wv:
+            fb = sum(fv) / len(fv) * 1024 * sf
+            wb = sum(wv) / len(wv) * 1024 * sw
+            res["kernels"][name] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                                    "hbm_bytes_per_launch": fb + wb}
+    json.dump(res, open(out, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    else:
+        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+        import bench
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], bench.kernel_source_hash())
