@@ -80,6 +80,7 @@ struct ZoomPlan {
 struct PadPlan {
   int64_t N, Nfft;
   int F, P;
+  int realF = 0, realP = 0;  // whole-spectrum real-input kernel (N_fft = 2 realP realF)
   std::shared_ptr<BluePlan> blue;  // Nfft with no fast factorisation
 };
 
@@ -383,6 +384,15 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
     pl->N = N;
     pl->Nfft = nfft;
     pl->F = 0;
+    if (nfft % 2 == 0) {
+      const int64_t nh = nfft / 2;
+      for (int64_t F = 1024; F <= 2048; F <<= 1)
+        if (2 * F >= N && nh % F == 0 && fftpad_real_supported((int)F, (int)(nh / F))) {
+          pl->realF = (int)F;
+          pl->realP = (int)(nh / F);
+          break;
+        }
+    }
     for (int64_t F = kMinL; F <= kMaxL; F <<= 1)
       if (F >= N && nfft % F == 0) {
         pl->F = (int)F;
@@ -427,6 +437,28 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
     a.B = c.B;
     a.precision = c.precision;
     TZ_HIP(launch_czt(a, c.stream), "fft_zeropad (czt) launch");
+    return TZ_OK;
+  }
+  if (pp->realF) {
+    const float2 *tw = nullptr, *rh = nullptr, *rf = nullptr;
+    if ((st = get_twiddles(d, pp->realF, c.stream, &tw))) return st;
+    if ((st = get_roots(d, nfft / 2, c.stream, &rh))) return st;
+    if ((st = get_roots(d, nfft, c.stream, &rf))) return st;
+    PadRealLaunch a;
+    a.x = x;
+    a.in_kind = c.in_kind;
+    a.xs = c.xs;
+    a.N = N;
+    a.F = pp->realF;
+    a.P = pp->realP;
+    a.tw = tw;
+    a.root_h = rh;
+    a.root_f = rf;
+    a.X = (float2 *)X;
+    a.os = c.os;
+    a.half = half ? 1 : 0;
+    a.B = c.B;
+    TZ_HIP(launch_fftpad_real(a, c.stream), "fft_zeropad launch");
     return TZ_OK;
   }
   const float2 *tw = nullptr, *root = nullptr;

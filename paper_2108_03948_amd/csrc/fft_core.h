@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace tz {
 
 // ---------------------------------------------------------------------------
@@ -220,9 +222,95 @@ __device__ __forceinline__ unsigned opaque_zero() {
   return z;
 }
 
+// ---------------------------------------------------------------------------
+// Buffer access.  A buffer resource holds a uniform base address and a byte
+// extent in scalar registers; each lane supplies a 32-bit byte offset.  Reads
+// at or past the extent return 0 and writes there are dropped (the hardware
+// range check of raw buffers), which gives zero padding and ragged tails
+// without per-lane address arithmetic or branches.
+// ---------------------------------------------------------------------------
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, uint64_t bytes) {
+  const uint32_t n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n, 0x00020000);
+}
+__device__ __forceinline__ float ld_f32(Rsrc r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double ld_f64(Rsrc r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ float2 ld_c64(Rsrc r, unsigned off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void st_c64(float2 v, Rsrc r, unsigned off) {
+  using U2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)off, 0, 0);
+}
+// real sample n of a float (KIND 0) or double (KIND 1) trace
+template <int KIND>
+__device__ __forceinline__ float ld_real(Rsrc r, unsigned n) {
+  if constexpr (KIND == 1)
+    return (float)ld_f64(r, 8 * n);
+  else
+    return ld_f32(r, 4 * n);
+}
+
 // index clamped into [0, lim) for loads that must not branch (lim >= 1);
 // the caller discards the value where a < lim fails
 __device__ __forceinline__ unsigned clamp_idx(unsigned a, unsigned lim) { return a < lim ? a : lim - 1; }
+
+// Twiddles W_L^m = e^{-j 2 pi m / L} held in LDS as two short tables,
+//   W_L^m = lo[m mod 128] * hi[m / 128],   lo[i] = W_L^i, hi[i] = W_L^{128 i},
+// filled from the double-precision-built global table at kernel start
+// (128 + L/128 entries, <= 2 KB).  Each factor is correctly rounded, so a
+// twiddle carries about 1.5 ulp of error, and LDS latency replaces the L2
+// latency of a scattered lookup in the full table.
+constexpr int kTwLo = 128;
+template <int L>
+constexpr int tw_lds_points() { return kTwLo + (L + kTwLo - 1) / kTwLo; }
+
+struct TwLds {
+  const float2 *lo, *hi;
+  __device__ __forceinline__ float2 operator()(unsigned m) const { return cmul(lo[m & (kTwLo - 1)], hi[m >> 7]); }
+};
+
+// copy the two tables from the global table tw (L entries) into LDS twl;
+// the caller synchronises before first use
+template <int L>
+__device__ __forceinline__ TwLds load_twiddles(float2 *twl, const float2 *__restrict__ tw, unsigned tid,
+                                               unsigned nthreads) {
+  constexpr int NHI = (L + kTwLo - 1) / kTwLo;
+  for (unsigned i = tid; i < (unsigned)(kTwLo + NHI); i += nthreads)
+    twl[i] = (i < (unsigned)kTwLo) ? tw[i < (unsigned)L ? i : 0] : tw[(i - kTwLo) * kTwLo];
+  return TwLds{twl, twl + kTwLo};
+}
+
+// v[r] *= W^{base r}, r = 1 .. R-1.  With r = r1 + 4 r2 the twiddle factors
+// as W^{base r1} W^{4 base r2}; the two factors are applied one after the
+// other (the same multiply count as forming their product first), so only
+// 2 x 3 table twiddles are live at a time.
+template <int R>
+__device__ __forceinline__ void apply_twiddles(float2 *v, const TwLds &tw, unsigned base) {
+  if constexpr (R <= 4) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw(base * r));
+  } else {
+    float2 a[4], c[R / 4];
+#pragma unroll
+    for (int r1 = 1; r1 < 4; ++r1) a[r1] = tw(base * r1);
+#pragma unroll
+    for (int r2 = 1; r2 < R / 4; ++r2) c[r2] = tw(4 * base * r2);
+#pragma unroll
+    for (int r2 = 0; r2 < R / 4; ++r2)
+#pragma unroll
+      for (int r1 = 0; r1 < 4; ++r1) {
+        const int r = r1 + 4 * r2;
+        if (r1 != 0) v[r] = cmul(v[r], a[r1]);
+        if (r2 != 0) v[r] = cmul(v[r], c[r2]);
+      }
+  }
+}
 
 // LDS index with one pad slot every 16 points (breaks the power-of-two
 // strides of the first passes across banks)
@@ -257,20 +345,17 @@ struct Fft {
   // one pass: twiddle + butterfly in registers, then (unless last) exchange
   // through LDS into the layout of the next pass.
   template <int p>
-  __device__ __forceinline__ static void pass(float2 (&v)[E], float2 *lds, int t,
-                                              const float2 *__restrict__ tw) {
+  __device__ __forceinline__ static void pass(float2 (&v)[E], float2 *lds, int t, const TwLds &tw) {
     constexpr int R = Plan::list[p];
     constexpr int NS = ns_before(p);
     constexpr int NB = E / R;
     constexpr int TWS = L / (NS * R);  // table stride of this pass
-    const unsigned z = opaque_zero();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int j = t + i * NT;
       if constexpr (NS > 1) {
         const unsigned jm = (unsigned)(j % NS);
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], tw[jm * r * TWS + z]);
+        apply_twiddles<R>(&v[i * R], tw, jm * TWS);
       }
       Dft<R>::template run<1>(&v[i * R]);
     }
@@ -296,15 +381,13 @@ struct Fft {
   }
 
   template <int... ps>
-  __device__ __forceinline__ static void run_passes(float2 (&v)[E], float2 *lds, int t,
-                                                    const float2 *__restrict__ tw,
+  __device__ __forceinline__ static void run_passes(float2 (&v)[E], float2 *lds, int t, const TwLds &tw,
                                                     std::integer_sequence<int, ps...>) {
     (pass<ps>(v, lds, t, tw), ...);
   }
 
   // forward FFT in place: v in "in_slot" layout -> v in "out_slot" layout
-  __device__ __forceinline__ static void forward(float2 (&v)[E], float2 *lds, int t,
-                                                 const float2 *__restrict__ tw) {
+  __device__ __forceinline__ static void forward(float2 (&v)[E], float2 *lds, int t, const TwLds &tw) {
     run_passes(v, lds, t, tw, std::make_integer_sequence<int, P>{});
   }
 
@@ -317,6 +400,141 @@ struct Fft {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = w[e];
     }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// One FFT per wavefront.  A single wave of 64 lanes holds all F points
+// (E = F/64 per lane, point lane + 64 e in register e), so passes need no
+// workgroup barrier: LDS operations of one wave execute in issue order, and a
+// compiler-level wave barrier keeps them in program order.  Each exchange
+// goes through a private LDS window of F/2 points in two halves (write the
+// outputs that fall in a half, read the next pass's inputs from it, then the
+// other half), halving the LDS a wave needs.
+// ---------------------------------------------------------------------------
+template <int F>
+struct WaveShape;
+template <> struct WaveShape<1024> { using Plan = Radices<16, 16, 4>; };
+template <> struct WaveShape<2048> { using Plan = Radices<16, 16, 8>; };
+template <> struct WaveShape<4096> { using Plan = Radices<16, 16, 16>; };
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int F>
+struct WaveFft {
+  static constexpr int NT = 64;
+  static constexpr int E = F / NT;
+  using Plan = typename WaveShape<F>::Plan;
+  static constexpr int P = Plan::count;
+  static constexpr int R_first = Plan::list[0];
+  static constexpr int R_last = Plan::list[P - 1];
+  // windows of F/2 points for F >= 2048 (32+ points per lane); smaller FFTs
+  // exchange through a full window in one step
+  static constexpr int PARTS = F >= 2048 ? 2 : 1;
+  static constexpr int HALF = F / PARTS;
+  static_assert(Plan::product() == F, "radix plan must multiply to F");
+
+  __device__ __forceinline__ static constexpr int in_slot(int e) { return slot_of<E, R_first>(e); }
+  __device__ __forceinline__ static constexpr int out_slot(int e) { return slot_of<E, R_last>(e); }
+  static constexpr int ns_before(int p) {
+    int ns = 1;
+    for (int i = 0; i < p; ++i) ns *= Plan::list[i];
+    return ns;
+  }
+  // LDS points of the private window
+  static constexpr int window() { return F / (F >= 2048 ? 2 : 1) + F / (F >= 2048 ? 2 : 1) / 16; }
+
+  template <int p>
+  __device__ __forceinline__ static void pass(float2 (&v)[E], float2 *win, int lane, const TwLds &tw) {
+    constexpr int R = Plan::list[p];
+    constexpr int NS = ns_before(p);
+    constexpr int NB = E / R;
+    constexpr int TWS = F / (NS * R);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = lane + i * NT;
+      if constexpr (NS > 1) {
+        const unsigned jm = (unsigned)(j % NS);
+        apply_twiddles<R>(&v[i * R], tw, jm * TWS);
+      }
+      Dft<R>::template run<1>(&v[i * R]);
+      __builtin_amdgcn_sched_barrier(0);  // one butterfly's temporaries live at a time
+    }
+    if constexpr (p + 1 < P) {
+      // inputs of the next pass go to nv: slots of v may still hold outputs
+      // of the other half that have not been written yet
+      float2 nv[E];
+      exchange<p, 0>(v, nv, win, lane);
+      if constexpr (PARTS == 2) exchange<p, 1>(v, nv, win, lane);
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = nv[e];
+    }
+  }
+
+  // Which half of the window output r of butterfly slot i lands in.  The
+  // Stockham position (j/NS) NS R + j%NS + r NS is non-decreasing in j, so
+  // checking lanes 0 and 63 decides it for the whole wave at compile time.
+  template <int p, int i, int r>
+  static constexpr bool out_upper() {
+    if constexpr (PARTS == 1) return false;
+    constexpr int R = Plan::list[p];
+    constexpr int NS = ns_before(p);
+    constexpr int j0 = i * NT, j1 = 63 + i * NT;
+    constexpr int pos0 = (j0 / NS) * NS * R + j0 % NS + r * NS;
+    constexpr int pos1 = (j1 / NS) * NS * R + j1 % NS + r * NS;
+    static_assert((pos0 >= HALF) == (pos1 >= HALF), "an output slot straddles both halves");
+    return pos0 >= HALF;
+  }
+
+  template <int p, int h, int i, int... rs>
+  __device__ __forceinline__ static void write_slot(const float2 (&v)[E], float2 *win, int lane,
+                                                    std::integer_sequence<int, rs...>) {
+    constexpr int R = Plan::list[p];
+    constexpr int NS = ns_before(p);
+    const int j = lane + i * NT;
+    const int base = (j / NS) * NS * R + (j % NS) - h * HALF;
+    ((out_upper<p, i, rs>() == (h == 1) ? (void)(win[lds_idx(base + rs * NS)] = v[i * R + rs]) : (void)0), ...);
+  }
+  template <int p, int h, int... is>
+  __device__ __forceinline__ static void write_half(const float2 (&v)[E], float2 *win, int lane,
+                                                    std::integer_sequence<int, is...>) {
+    constexpr int R = Plan::list[p];
+    (write_slot<p, h, is>(v, win, lane, std::make_integer_sequence<int, R>{}), ...);
+  }
+
+  // exchange of half h: write the outputs of pass p that fall in half h, then
+  // read the inputs of pass p+1 held there (j + r2 F/R2 is in the upper half
+  // exactly when r2 >= R2/2).  Reads of half 0 are issued before the writes
+  // of half 1 and LDS executes a wave's operations in order, so the window is
+  // reused safely.
+  template <int p, int h>
+  __device__ __forceinline__ static void exchange(const float2 (&v)[E], float2 (&nv)[E], float2 *win, int lane) {
+    constexpr int R = Plan::list[p];
+    constexpr int R2 = Plan::list[p + 1];
+    constexpr int NB = E / R, NB2 = E / R2;
+    wave_sync();
+    write_half<p, h>(v, win, lane, std::make_integer_sequence<int, NB>{});
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < NB2; ++i) {
+      const int j = lane + i * NT;
+#pragma unroll
+      for (int r = h * (R2 / PARTS); r < (h + 1) * (R2 / PARTS); ++r)
+        nv[i * R2 + r] = win[lds_idx(j + r * (F / R2) - h * HALF)];
+    }
+  }
+
+  template <int... ps>
+  __device__ __forceinline__ static void run_passes(float2 (&v)[E], float2 *win, int lane, const TwLds &tw,
+                                                    std::integer_sequence<int, ps...>) {
+    (pass<ps>(v, win, lane, tw), ...);
+  }
+  __device__ __forceinline__ static void forward(float2 (&v)[E], float2 *win, int lane, const TwLds &tw) {
+    run_passes(v, win, lane, tw, std::make_integer_sequence<int, P>{});
   }
 };
 

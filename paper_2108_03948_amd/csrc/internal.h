@@ -57,6 +57,22 @@ struct PadLaunch {
 };
 hipError_t launch_fftpad(const PadLaunch &a, hipStream_t s);
 
+// Zero-padded FFT of real traces, whole spectrum per workgroup:
+// N_fft = 2 P F, ceil(N/2) <= F.  root_h = W_{N_fft/2}^m, root_f = W_{N_fft}^m.
+struct PadRealLaunch {
+  const void *x;
+  int in_kind;
+  int64_t xs, N;
+  int F, P;
+  const float2 *tw, *root_h, *root_f;
+  float2 *X;
+  int64_t os;
+  int half;
+  int64_t B;
+};
+bool fftpad_real_supported(int F, int P);
+hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s);
+
 // Zoom front end: u[b][m] = ph[m] sum_t g[t] x[b][mD - t], m < LD.
 struct ZoomFrontLaunch {
   const void *x;

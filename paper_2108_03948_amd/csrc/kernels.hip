@@ -38,14 +38,18 @@ __global__ void __launch_bounds__(Fft<L>::NT)
           int64_t os, int64_t M, int64_t Mb, int nblk) {
   using F = Fft<L>;
   constexpr int NT = F::NT, E = F::E;
+  constexpr int XB = KIND == 1 ? 8 : (KIND == 2 ? 8 : 4);  // bytes per input sample
   __shared__ float2 lds[lds_points<L>()];
+  __shared__ float2 twl[tw_lds_points<L>()];
   const unsigned t = threadIdx.x;
   const int64_t b = blockIdx.x / nblk;
   const int blk = blockIdx.x % nblk;
   const int64_t k0 = (int64_t)blk * Mb;
-  // per-trace bases are uniform (scalar registers); lane offsets are 32-bit
-  const float2 *pre = c_pre + (int64_t)blk * Ns;
   const int64_t kmax = (M - k0 < Mb) ? (M - k0) : Mb;  // bins of this block
+  const TwLds twd = load_twiddles<L>(twl, tw, t, NT);
+  __syncthreads();
+  const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
+  const Rsrc rX = make_rsrc(X + b * os + k0, (uint64_t)kmax * 8);
 
   float2 acc[SEG ? E : 1];
   float2 v[E];
@@ -53,54 +57,40 @@ __global__ void __launch_bounds__(Fft<L>::NT)
   for (int s = 0; s < nloop; ++s) {
     const int64_t n0 = (int64_t)s * Ns;
     const int64_t nmax = (N - n0 < Ns) ? (N - n0) : Ns;  // samples of this segment
-    const unsigned nlim = (unsigned)nmax;
-    const unsigned z0 = opaque_zero();
+    // reads past the segment return 0: the zero padding of y up to L
+    const Rsrc rx = make_rsrc((const char *)x + (b * xs + n0) * XB, (uint64_t)nmax * XB);
+    const Rsrc rp = make_rsrc(c_pre + (int64_t)blk * Ns, (uint64_t)nmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const unsigned n = t + NT * e;
-      const unsigned nc = clamp_idx(n, nlim) + z0;
-      const float2 c = pre[nc];
-      float2 val;
+      const float2 c = ld_c64(rp, 8 * n);
       if constexpr (KIND == 2)
-        val = cmul(((const float2 *)x + b * xs + n0)[nc], c);
-      else if constexpr (KIND == 1)
-        val = cscale(c, (float)((const double *)x + b * xs + n0)[nc]);
+        v[F::in_slot(e)] = cmul(ld_c64(rx, 8 * n), c);
       else
-        val = cscale(c, ((const float *)x + b * xs + n0)[nc]);
-      v[F::in_slot(e)] = (n < nlim) ? val : make_float2(0.f, 0.f);
+        v[F::in_slot(e)] = cscale(c, ld_real<KIND>(rx, n));
     }
-    F::forward(v, lds, t, tw);
-    const unsigned z1 = opaque_zero();
+    F::forward(v, lds, t, twd);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const unsigned k = t + NT * e;
-      v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], V[k + z1]));
+      v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * k)));
     }
     F::out_to_in(v);
-    F::forward(v, lds, t, tw);
-    const float2 *post = c_post + ((int64_t)s * nblk + blk) * Mb;
-    float2 *Xb = X + b * os + k0;
-    const unsigned klim = (unsigned)kmax;
-    const unsigned z2 = opaque_zero();
+    F::forward(v, lds, t, twd);
+    const Rsrc rq = make_rsrc(c_post + ((int64_t)s * nblk + blk) * Mb, (uint64_t)kmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const unsigned k = t + NT * e;
-      const float2 r = cmul(cconj(v[F::out_slot(e)]), post[clamp_idx(k, klim) + z2]);
-      if constexpr (SEG) {
+      const float2 r = cmul(cconj(v[F::out_slot(e)]), ld_c64(rq, 8 * k));
+      if constexpr (SEG)
         acc[e] = (s == 0) ? r : cadd(acc[e], r);
-      } else {
-        if (k < klim) Xb[k] = r;
-      }
+      else
+        st_c64(r, rX, 8 * k);  // bins past this block are dropped
     }
   }
   if constexpr (SEG) {
-    float2 *Xb = X + b * os + k0;
-    const unsigned klim = (unsigned)kmax;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const unsigned k = t + NT * e;
-      if (k < klim) Xb[k] = acc[e];
-    }
+    for (int e = 0; e < E; ++e) st_c64(acc[e], rX, 8 * (t + NT * e));
   }
 }
 
@@ -121,28 +111,26 @@ __global__ void __launch_bounds__(Fft<FL>::NT)
   using F = Fft<FL>;
   constexpr int NT = F::NT, E = F::E;
   __shared__ float2 lds[lds_points<FL>()];
+  __shared__ float2 twl[tw_lds_points<FL>()];
   const unsigned t = threadIdx.x;
   const int64_t g = blockIdx.x;
   const int64_t xcd = g & 7, slot = g >> 3;
   const int64_t b = (slot / P) * 8 + xcd;
   const int r = (int)(slot % P);
   if (b >= B) return;  // whole workgroup leaves before any barrier
+  const TwLds twd = load_twiddles<FL>(twl, tw, t, NT);
+  __syncthreads();
 
-  const unsigned nlim = (unsigned)N;
+  const Rsrc rx = make_rsrc((const char *)x + b * xs * (KIND == 1 ? 8 : 4), (uint64_t)N * (KIND == 1 ? 8 : 4));
+  const Rsrc rr = make_rsrc(root, (uint64_t)(P * (int64_t)N) * 8);
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const unsigned n = t + NT * e;
-    const unsigned nc = clamp_idx(n, nlim);
-    float xv;
-    if constexpr (KIND == 1)
-      xv = (float)((const double *)x + b * xs)[nc];
-    else
-      xv = ((const float *)x + b * xs)[nc];
-    const float2 val = (P > 1) ? cscale(root[(unsigned)r * nc], xv) : make_float2(xv, 0.f);
-    v[F::in_slot(e)] = (n < nlim) ? val : make_float2(0.f, 0.f);
+    const unsigned n = t + NT * e;  // samples past N read as 0
+    const float xv = ld_real<KIND>(rx, n);
+    v[F::in_slot(e)] = (P > 1) ? cscale(ld_c64(rr, 8 * ((unsigned)r * n)), xv) : make_float2(xv, 0.f);
   }
-  F::forward(v, lds, t, tw);
+  F::forward(v, lds, t, twd);
   float2 *Xb = X + b * os + r;
   // bins k = q P + r < nout  <=>  q < qlim
   const unsigned qlim = (unsigned)((nout - r + P - 1) / P);
@@ -150,6 +138,108 @@ __global__ void __launch_bounds__(Fft<FL>::NT)
   for (int e = 0; e < E; ++e) {
     const unsigned q = t + NT * e;
     if (q < qlim) Xb[(size_t)q * P] = v[F::out_slot(e)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Zero-padded FFT of a real trace, whole spectrum per workgroup.
+//
+// With Nh = N_fft/2 and z[m] = x[2m] + j x[2m+1] (m < ceil(N/2)), the
+// Nh-point FFT Z of z gives every bin of the real trace:
+//   X[k] = (Z[k] + conj Z[Nh-k])/2 - j W_{Nfft}^k (Z[k] - conj Z[Nh-k])/2,
+//   0 <= k <= Nh,   X[N_fft - k] = conj X[k]          (indices of Z mod Nh).
+// Z itself is P independent F-point FFTs (Nh = P F, F >= N/2):
+//   Z[P q + r] = FFT_F( z[m] W_{Nh}^{r m} )[q],
+// one per wavefront (wave r), so the whole spectrum of the trace sits in the
+// registers of one workgroup with no workgroup barrier during the FFTs.  It
+// is then staged through LDS in two halves, quarters {0,3} and {1,2} of Z (the
+// halves that pair k with Nh-k), and every output row is written as
+// contiguous runs, ascending for X[k] and descending for its mirror.
+// ---------------------------------------------------------------------------
+template <int F, int P>
+struct PadWaveShape {
+  using FF = WaveFft<F>;
+  static constexpr int E = FF::E;
+  static constexpr int NH = P * F;
+  static constexpr int STAGE = NH / 2 + 1;  // one half of Z plus the shared element Z[3Nh/4]
+  static constexpr int LDS_FFT = P * FF::window();
+  static constexpr int LDS_STAGE = STAGE + STAGE / 16 + 1;
+  static constexpr int LDS = LDS_FFT > LDS_STAGE ? LDS_FFT : LDS_STAGE;
+  static_assert(E % 4 == 0, "quarters of Z must align with register slots");
+};
+
+template <int F, int P, int KIND>
+__global__ void __launch_bounds__(64 * P)
+    k_fftpad_real(const void *__restrict__ x, int64_t xs, int64_t N, const float2 *__restrict__ root_h,
+                  const float2 *__restrict__ root_f, const float2 *__restrict__ tw, float2 *__restrict__ X,
+                  int64_t os, int half) {
+  using Sh = PadWaveShape<F, P>;
+  using FF = typename Sh::FF;
+  constexpr int E = Sh::E, NH = Sh::NH, NTH = 64 * P;
+  __shared__ float2 lds[Sh::LDS];
+  __shared__ float2 twl[tw_lds_points<F>()];
+  __shared__ float2 rtl[tw_lds_points<NH>()];
+  const unsigned tid = threadIdx.x;
+  const unsigned r = tid / 64, lane = tid % 64;
+  const int64_t b = blockIdx.x;
+  const TwLds twd = load_twiddles<F>(twl, tw, tid, NTH);
+  const TwLds rtd = load_twiddles<NH>(rtl, root_h, tid, NTH);
+  __syncthreads();
+
+  // z[m] = x[2m] + j x[2m+1]; samples past N read as 0
+  const Rsrc rx = make_rsrc((const char *)x + b * xs * (KIND == 1 ? 8 : 4), (uint64_t)N * (KIND == 1 ? 8 : 4));
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const unsigned m = lane + 64 * e;
+    const float2 zz = make_float2(ld_real<KIND>(rx, 2 * m), ld_real<KIND>(rx, 2 * m + 1));
+    v[FF::in_slot(e)] = cmul(zz, rtd(r * m));
+  }
+  FF::forward(v, lds + r * FF::window(), lane, twd);
+
+  float2 *Xb = X + b * os;
+  constexpr unsigned Q4 = NH / 4;
+  // two staging phases: A = quarters {0, 3}, B = quarters {1, 2}
+#pragma unroll
+  for (int ph = 0; ph < 2; ++ph) {
+    __syncthreads();  // FFT windows / previous phase reads are done
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int quarter = (4 * e) / E;
+      const unsigned q = lane + 64 * e;
+      const unsigned k = P * q + r;
+      const float2 z = v[FF::out_slot(e)];
+      if (ph == 0) {
+        if (quarter == 0) lds[lds_idx(k)] = z;
+        if (quarter == 3) lds[lds_idx(k - NH / 2)] = z;
+      } else {
+        if (quarter == 1 || quarter == 2) lds[lds_idx(k - Q4)] = z;
+        if (quarter == 3 && k == 3 * Q4) lds[lds_idx(NH / 2)] = z;
+      }
+    }
+    __syncthreads();
+    // outputs of this phase:  A: k in [0, Nh/4) U (3Nh/4, Nh];  B: k in [Nh/4, 3Nh/4]
+    const unsigned nout = ph == 0 ? NH / 2 : NH / 2 + 1;
+    for (unsigned i = tid; i < nout; i += NTH) {
+      unsigned k, sk, sm;  // bin, staging slot of Z[k], staging slot of Z[Nh-k]
+      if (ph == 0) {
+        k = (i < Q4) ? i : i + NH / 2 + 1;
+        const unsigned kz = k % NH, mz = (NH - k) % NH;
+        sk = kz < Q4 ? kz : kz - NH / 2;
+        sm = mz < Q4 ? mz : mz - NH / 2;
+      } else {
+        k = Q4 + i;
+        sk = k - Q4;
+        sm = (NH - k) - Q4;
+      }
+      const float2 a = lds[lds_idx(sk)];
+      const float2 c = cconj(lds[lds_idx(sm)]);
+      const float2 ev = cscale(cadd(a, c), 0.5f);
+      const float2 od = cscale(cmul_mj(csub(a, c)), 0.5f);
+      const float2 xk = cadd(ev, cmul(root_f[k], od));
+      Xb[k] = xk;
+      if (!half && k != 0 && k != NH) Xb[2 * NH - k] = cconj(xk);
+    }
   }
 }
 
@@ -244,6 +334,36 @@ hipError_t launch_fftpad(const PadLaunch &a, hipStream_t s) {
     case 4096: pad_dispatch<4096>(a, s); break;
     case 8192: pad_dispatch<8192>(a, s); break;
     case 16384: pad_dispatch<16384>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int F, int P>
+static void pad_real_launch(const PadRealLaunch &a, hipStream_t s) {
+  const dim3 grid((unsigned)a.B), block(64 * P);
+  if (a.in_kind == 1)
+    hipLaunchKernelGGL((k_fftpad_real<F, P, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.root_h, a.root_f, a.tw,
+                       a.X, a.os, a.half);
+  else
+    hipLaunchKernelGGL((k_fftpad_real<F, P, 0>), grid, block, 0, s, a.x, a.xs, a.N, a.root_h, a.root_f, a.tw,
+                       a.X, a.os, a.half);
+}
+
+// (F, P) pairs with a compiled whole-spectrum kernel
+bool fftpad_real_supported(int F, int P) {
+  switch (F * 100 + P) {
+    case 102408: case 102416: case 204808: case 204816: return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s) {
+  switch (a.F * 100 + a.P) {
+    case 102408: pad_real_launch<1024, 8>(a, s); break;   // N_fft 16384, N <= 2048
+    case 102416: pad_real_launch<1024, 16>(a, s); break;  // N_fft 32768, N <= 2048
+    case 204808: pad_real_launch<2048, 8>(a, s); break;   // N_fft 32768, N <= 4096
+    case 204816: pad_real_launch<2048, 16>(a, s); break;  // N_fft 65536, N <= 4096
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

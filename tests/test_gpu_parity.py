@@ -123,7 +123,9 @@ def test_czt_segments_and_blocks(tz, dev, orc, N, M):
 
 @pytest.mark.parametrize("N,nz,half", [(1, 0, False), (100, 156, False), (1000, 1048, False),
                                        (1024, 15360, False), (300, 212, True), (1000, 537, False),
-                                       (4096, 61440, True), (5000, 11384, False)])
+                                       (4096, 61440, True), (5000, 11384, False), (2048, 30720, False),
+                                       (4000, 28768, True), (7999, 57537, False), (511, 15873, False),
+                                       (3, 16381, False), (4096, 61440, False)])
 def test_fft_zeropad_shapes(tz, dev, orc, N, nz, half):
     rng = np.random.default_rng(N + nz)
     x = rng.standard_normal((3, N)).astype(np.float32)
