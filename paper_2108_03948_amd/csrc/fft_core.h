@@ -275,6 +275,24 @@ struct TwLds {
   __device__ __forceinline__ float2 operator()(unsigned m) const { return cmul(lo[m & (kTwLo - 1)], hi[m >> 7]); }
 };
 
+// Twiddles from one half-circle table in LDS: W_L^m = t[m] for m < L/2 and
+// -t[m - L/2] above (W_L^{L/2} = -1); one LDS read and no arithmetic per
+// twiddle.  Used where L/2 points of LDS are affordable.
+template <int L>
+struct TwHalf {
+  const float2 *t;
+  __device__ __forceinline__ float2 operator()(unsigned m) const {
+    const float2 w = t[m & (L / 2 - 1)];
+    return (m & (L / 2)) ? make_float2(-w.x, -w.y) : w;
+  }
+};
+template <int L>
+__device__ __forceinline__ TwHalf<L> load_half_twiddles(float2 *twl, const float2 *__restrict__ tw, unsigned tid,
+                                                        unsigned nthreads) {
+  for (unsigned i = tid; i < (unsigned)(L / 2); i += nthreads) twl[i] = tw[i];
+  return TwHalf<L>{twl};
+}
+
 // copy the two tables from the global table tw (L entries) into LDS twl;
 // the caller synchronises before first use
 template <int L>
@@ -290,6 +308,12 @@ __device__ __forceinline__ TwLds load_twiddles(float2 *twl, const float2 *__rest
 // as W^{base r1} W^{4 base r2}; the two factors are applied one after the
 // other (the same multiply count as forming their product first), so only
 // 2 x 3 table twiddles are live at a time.
+template <int R, int L>
+__device__ __forceinline__ void apply_twiddles(float2 *v, const TwHalf<L> &tw, unsigned base) {
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw(base * r));
+}
+
 template <int R>
 __device__ __forceinline__ void apply_twiddles(float2 *v, const TwLds &tw, unsigned base) {
   if constexpr (R <= 4) {
@@ -344,8 +368,8 @@ struct Fft {
 
   // one pass: twiddle + butterfly in registers, then (unless last) exchange
   // through LDS into the layout of the next pass.
-  template <int p>
-  __device__ __forceinline__ static void pass(float2 (&v)[E], float2 *lds, int t, const TwLds &tw) {
+  template <int p, class TW>
+  __device__ __forceinline__ static void pass(float2 (&v)[E], float2 *lds, int t, const TW &tw) {
     constexpr int R = Plan::list[p];
     constexpr int NS = ns_before(p);
     constexpr int NB = E / R;
@@ -380,14 +404,15 @@ struct Fft {
     }
   }
 
-  template <int... ps>
-  __device__ __forceinline__ static void run_passes(float2 (&v)[E], float2 *lds, int t, const TwLds &tw,
+  template <class TW, int... ps>
+  __device__ __forceinline__ static void run_passes(float2 (&v)[E], float2 *lds, int t, const TW &tw,
                                                     std::integer_sequence<int, ps...>) {
     (pass<ps>(v, lds, t, tw), ...);
   }
 
   // forward FFT in place: v in "in_slot" layout -> v in "out_slot" layout
-  __device__ __forceinline__ static void forward(float2 (&v)[E], float2 *lds, int t, const TwLds &tw) {
+  template <class TW>
+  __device__ __forceinline__ static void forward(float2 (&v)[E], float2 *lds, int t, const TW &tw) {
     run_passes(v, lds, t, tw, std::make_integer_sequence<int, P>{});
   }
 
@@ -448,8 +473,8 @@ struct WaveFft {
   // LDS points of the private window
   static constexpr int window() { return F / (F >= 2048 ? 2 : 1) + F / (F >= 2048 ? 2 : 1) / 16; }
 
-  template <int p>
-  __device__ __forceinline__ static void pass(float2 (&v)[E], float2 *win, int lane, const TwLds &tw) {
+  template <int p, class TW>
+  __device__ __forceinline__ static void pass(float2 (&v)[E], float2 *win, int lane, const TW &tw) {
     constexpr int R = Plan::list[p];
     constexpr int NS = ns_before(p);
     constexpr int NB = E / R;
@@ -528,12 +553,13 @@ struct WaveFft {
     }
   }
 
-  template <int... ps>
-  __device__ __forceinline__ static void run_passes(float2 (&v)[E], float2 *win, int lane, const TwLds &tw,
+  template <class TW, int... ps>
+  __device__ __forceinline__ static void run_passes(float2 (&v)[E], float2 *win, int lane, const TW &tw,
                                                     std::integer_sequence<int, ps...>) {
     (pass<ps>(v, win, lane, tw), ...);
   }
-  __device__ __forceinline__ static void forward(float2 (&v)[E], float2 *win, int lane, const TwLds &tw) {
+  template <class TW>
+  __device__ __forceinline__ static void forward(float2 (&v)[E], float2 *win, int lane, const TW &tw) {
     run_passes(v, win, lane, tw, std::make_integer_sequence<int, P>{});
   }
 };

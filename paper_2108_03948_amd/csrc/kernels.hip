@@ -39,14 +39,22 @@ __global__ void __launch_bounds__(Fft<L>::NT)
   using F = Fft<L>;
   constexpr int NT = F::NT, E = F::E;
   constexpr int XB = KIND == 1 ? 8 : (KIND == 2 ? 8 : 4);  // bytes per input sample
+  // two-level twiddle table (a half-circle table measured slower here: its
+  // extra loads in flight cost occupancy)
+  constexpr bool kHalf = false;
   __shared__ float2 lds[lds_points<L>()];
-  __shared__ float2 twl[tw_lds_points<L>()];
+  __shared__ float2 twl[kHalf ? L / 2 : tw_lds_points<L>()];
   const unsigned t = threadIdx.x;
   const int64_t b = blockIdx.x / nblk;
   const int blk = blockIdx.x % nblk;
   const int64_t k0 = (int64_t)blk * Mb;
   const int64_t kmax = (M - k0 < Mb) ? (M - k0) : Mb;  // bins of this block
-  const TwLds twd = load_twiddles<L>(twl, tw, t, NT);
+  const auto twd = [&]() {
+    if constexpr (kHalf)
+      return load_half_twiddles<L>(twl, tw, t, NT);
+    else
+      return load_twiddles<L>(twl, tw, t, NT);
+  }();
   __syncthreads();
   const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
   const Rsrc rX = make_rsrc(X + b * os + k0, (uint64_t)kmax * 8);
@@ -177,13 +185,15 @@ __global__ void __launch_bounds__(64 * P)
   using FF = typename Sh::FF;
   constexpr int E = Sh::E, NH = Sh::NH, NTH = 64 * P;
   __shared__ float2 lds[Sh::LDS];
-  __shared__ float2 twl[tw_lds_points<F>()];
+  __shared__ float2 twl[F / 2];
   __shared__ float2 rtl[tw_lds_points<NH>()];
+  __shared__ float2 rfl[tw_lds_points<2 * NH>()];
   const unsigned tid = threadIdx.x;
   const unsigned r = tid / 64, lane = tid % 64;
   const int64_t b = blockIdx.x;
-  const TwLds twd = load_twiddles<F>(twl, tw, tid, NTH);
+  const TwHalf<F> twd = load_half_twiddles<F>(twl, tw, tid, NTH);
   const TwLds rtd = load_twiddles<NH>(rtl, root_h, tid, NTH);
+  const TwLds rfd = load_twiddles<2 * NH>(rfl, root_f, tid, NTH);
   __syncthreads();
 
   // z[m] = x[2m] + j x[2m+1]; samples past N read as 0
@@ -197,8 +207,32 @@ __global__ void __launch_bounds__(64 * P)
   }
   FF::forward(v, lds + r * FF::window(), lane, twd);
 
-  float2 *Xb = X + b * os;
   constexpr unsigned Q4 = NH / 4;
+  const Rsrc rX = make_rsrc(X + b * os, (uint64_t)(half ? NH + 1 : 2 * NH) * 8);
+  // X[k] from Z[k] and Z[Nh-k] (staged at slots sk, sm)
+  auto bin = [&](unsigned k, unsigned sk, unsigned sm) {
+    const float2 a = lds[lds_idx(sk)];
+    const float2 c = cconj(lds[lds_idx(sm)]);
+    const float2 ev = cscale(cadd(a, c), 0.5f);
+    const float2 od = cscale(cmul_mj(csub(a, c)), 0.5f);
+    return cadd(ev, cmul(rfd(k), od));
+  };
+  using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rX, 0, 0, 0));
+  // bins k, k+1 with one 16-byte store, and their mirrors N_fft-k-1, N_fft-k
+  // with another (k = 0 and k + 1 = Nh have no mirror)
+  auto store_pair = [&](unsigned k, float2 x0, float2 x1) {
+    __builtin_amdgcn_raw_buffer_store_b128(
+        __builtin_bit_cast(U4, make_float4(x0.x, x0.y, x1.x, x1.y)), rX, (int)(8 * k), 0, 0);
+    if (!half) {
+      if (k == 0)
+        st_c64(cconj(x1), rX, 8 * (2 * NH - 1));
+      else if (k + 1 == NH)
+        st_c64(cconj(x0), rX, 8 * (2 * NH - k));
+      else
+        __builtin_amdgcn_raw_buffer_store_b128(
+            __builtin_bit_cast(U4, make_float4(x1.x, -x1.y, x0.x, -x0.y)), rX, (int)(8 * (2 * NH - k - 1)), 0, 0);
+    }
+  };
   // two staging phases: A = quarters {0, 3}, B = quarters {1, 2}
 #pragma unroll
   for (int ph = 0; ph < 2; ++ph) {
@@ -218,27 +252,31 @@ __global__ void __launch_bounds__(64 * P)
       }
     }
     __syncthreads();
-    // outputs of this phase:  A: k in [0, Nh/4) U (3Nh/4, Nh];  B: k in [Nh/4, 3Nh/4]
-    const unsigned nout = ph == 0 ? NH / 2 : NH / 2 + 1;
-    for (unsigned i = tid; i < nout; i += NTH) {
-      unsigned k, sk, sm;  // bin, staging slot of Z[k], staging slot of Z[Nh-k]
-      if (ph == 0) {
-        k = (i < Q4) ? i : i + NH / 2 + 1;
-        const unsigned kz = k % NH, mz = (NH - k) % NH;
-        sk = kz < Q4 ? kz : kz - NH / 2;
-        sm = mz < Q4 ? mz : mz - NH / 2;
-      } else {
-        k = Q4 + i;
-        sk = k - Q4;
-        sm = (NH - k) - Q4;
+    if (ph == 0) {
+      // A: k in [0, Nh/4) U (3Nh/4, Nh], as Nh/4 pairs (k, k+1)
+      for (unsigned i = 2 * tid; i < NH / 2; i += 2 * NTH) {
+        const unsigned k = (i < Q4) ? i : i + NH / 2 + 1;
+        unsigned sk[2], sm[2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          const unsigned kz = (k + d) % NH, mz = (NH - (k + d)) % NH;
+          sk[d] = kz < Q4 ? kz : kz - NH / 2;
+          sm[d] = mz < Q4 ? mz : mz - NH / 2;
+        }
+        store_pair(k, bin(k, sk[0], sm[0]), bin(k + 1, sk[1], sm[1]));
       }
-      const float2 a = lds[lds_idx(sk)];
-      const float2 c = cconj(lds[lds_idx(sm)]);
-      const float2 ev = cscale(cadd(a, c), 0.5f);
-      const float2 od = cscale(cmul_mj(csub(a, c)), 0.5f);
-      const float2 xk = cadd(ev, cmul(root_f[k], od));
-      Xb[k] = xk;
-      if (!half && k != 0 && k != NH) Xb[2 * NH - k] = cconj(xk);
+    } else {
+      // B: k in [Nh/4, 3Nh/4) as pairs, then the single bin 3Nh/4
+      for (unsigned i = 2 * tid; i < NH / 2; i += 2 * NTH) {
+        const unsigned k = Q4 + i;
+        store_pair(k, bin(k, k - Q4, NH - k - Q4), bin(k + 1, k + 1 - Q4, NH - k - 1 - Q4));
+      }
+      if (tid == 0) {
+        const unsigned k = 3 * Q4;
+        const float2 xk = bin(k, NH / 2, Q4 - Q4);
+        st_c64(xk, rX, 8 * k);
+        if (!half) st_c64(cconj(xk), rX, 8 * (2 * NH - k));
+      }
     }
   }
 }
