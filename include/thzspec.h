@@ -185,6 +185,11 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
 tz_status tz_batch_launch(tz_batch *batch, const void *x_flat, void *X_flat, void *stream);
 /* Free the batch (synchronises the device first). */
 void tz_batch_destroy(tz_batch *batch);
+/* Write a one-line description of the batch into buf (NUL-terminated, at
+ * most len bytes): jobs, work units per FFT length, and the schedule the
+ * autotuner picked at the first launch with the time of every candidate.
+ * Returns the length of the full description. */
+int64_t tz_batch_describe(const tz_batch *batch, char *buf, int64_t len);
 
 /* ---------------------------------------------------------------------- */
 const char *tz_last_error(void);   /* thread-local message of the last failure */

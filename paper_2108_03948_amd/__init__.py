@@ -63,7 +63,8 @@ class tz_job(ctypes.Structure):
 EXPORTS = (
     "tz_opts_init", "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_band", "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "tz_batch_create",
-    "tz_batch_launch", "tz_batch_destroy", "tz_last_error", "tz_version", "tz_release_plans",
+    "tz_batch_launch", "tz_batch_destroy", "tz_batch_describe", "tz_last_error", "tz_version",
+    "tz_release_plans",
 )
 
 _lock = threading.Lock()
@@ -99,6 +100,8 @@ def lib() -> ctypes.CDLL:
         L.tz_batch_launch.argtypes = [vp, vp, vp, vp]
         L.tz_batch_destroy.argtypes = [vp]
         L.tz_batch_destroy.restype = None
+        L.tz_batch_describe.argtypes = [vp, ctypes.c_char_p, i64]
+        L.tz_batch_describe.restype = i64
         L.tz_last_error.restype = ctypes.c_char_p
         L.tz_version.restype = ctypes.c_char_p
         L.tz_release_plans.restype = None
@@ -291,6 +294,11 @@ class Batch:
         _check(lib().tz_batch_launch(self._h, x_flat.data_ptr(), X_flat.data_ptr(),
                                      ctypes.c_void_p(stream.cuda_stream)))
         return X_flat
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        lib().tz_batch_describe(self._h, buf, len(buf))
+        return buf.value.decode()
 
     def close(self):
         if self._h:

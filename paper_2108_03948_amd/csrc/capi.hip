@@ -101,46 +101,6 @@ Device &device_state(int dev) {
   return *d;
 }
 
-int64_t next_pow2(int64_t v) {
-  int64_t p = 1;
-  while (p < v) p <<= 1;
-  return p;
-}
-
-// FFT length, bin blocks and input segments of the Bluestein path.
-// One workgroup FFT of length L <= kMaxL must hold Ns samples and Mb bins
-// without wrap-around: Ns + Mb - 1 <= L.
-bool czt_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb, int *nblk) {
-  if (N + M - 1 <= kMaxL) {
-    *L = (int)(next_pow2(N + M - 1) < kMinL ? kMinL : next_pow2(N + M - 1));
-    *Ns = N;
-    *nseg = 1;
-    *Mb = M;
-    *nblk = 1;
-    return true;
-  }
-  int64_t best = -1, bNs = 0, bMb = 0;
-  for (int64_t ns = 256; ns <= kMaxL - 256; ns += 256) {
-    int64_t ns_eff = ns < N ? ns : N;
-    int64_t mb = kMaxL - ns_eff + 1;
-    if (mb > M) mb = M;
-    int64_t cost = ((N + ns_eff - 1) / ns_eff) * ((M + mb - 1) / mb);
-    if (best < 0 || cost < best) {
-      best = cost;
-      bNs = ns_eff;
-      bMb = mb;
-    }
-    if (ns >= N) break;
-  }
-  if (best < 0 || best > 256) return false;
-  *L = kMaxL;
-  *Ns = bNs;
-  *nseg = (int)((N + bNs - 1) / bNs);
-  *Mb = bMb;
-  *nblk = (int)((M + bMb - 1) / bMb);
-  return true;
-}
-
 std::string phase_key(const PhaseParams &p) {
   char buf[160];
   if (p.rational)
@@ -291,6 +251,44 @@ void reduce(__int128 &n, __int128 &d) {
 }
 
 }  // namespace
+
+void set_last_error(const char *msg) { g_err = msg; }
+
+PhaseParams band_phase(int64_t fs_hz, int64_t f1_hz, int64_t f2_hz, int64_t M) {
+  __int128 na = f1_hz % fs_hz, da = fs_hz;
+  __int128 nw = f2_hz - f1_hz, dw = (__int128)M * fs_hz;
+  reduce(na, da);
+  reduce(nw, dw);
+  __int128 g = da, h = dw;
+  while (h) {
+    __int128 t = g % h;
+    g = h;
+    h = t;
+  }
+  const __int128 q = da / g * dw;
+  PhaseParams p{};
+  if (q < ((__int128)1 << 61)) {
+    p.rational = 1;
+    p.q = (int64_t)q;
+    p.pa = (int64_t)(na * (q / da) % q);
+    p.pw = (int64_t)(nw * (q / dw) % q);
+  }
+  p.a = frac01((double)f1_hz / (double)fs_hz);
+  p.w = frac01((double)(f2_hz - f1_hz) / ((double)M * (double)fs_hz));
+  return p;
+}
+
+PhaseParams zoom_phase(int64_t K, int64_t M) {
+  PhaseParams p{};
+  p.rational = 1;
+  p.q = K;
+  p.pw = 1 % K;
+  p.pa = (K - (M / 2) % K) % K;
+  p.w = 1.0 / (double)K;
+  p.a = (double)p.pa / (double)K;
+  return p;
+}
+
 }  // namespace tz
 
 using namespace tz;
@@ -335,29 +333,7 @@ tz_status czt_band_exact(const void *x, int64_t N, int64_t M, int64_t fs_hz, int
   Common c;
   tz_status st = check_common(x, N, X, o, M, &c);
   if (st) return st;
-  // a = f1/fs, w = (f2-f1)/(M fs), reduced to a common denominator q
-  __int128 na = f1_hz % fs_hz, da = fs_hz;
-  __int128 nw = f2_hz - f1_hz, dw = (__int128)M * fs_hz;
-  reduce(na, da);
-  reduce(nw, dw);
-  __int128 g = da, h = dw;
-  while (h) {
-    __int128 t = g % h;
-    g = h;
-    h = t;
-  }
-  __int128 q = da / g * dw;
-  PhaseParams p{};
-  if (q < ((__int128)1 << 61)) {
-    p.rational = 1;
-    p.q = (int64_t)q;
-    p.pa = (int64_t)(na * (q / da) % q);
-    p.pw = (int64_t)(nw * (q / dw) % q);
-  } else {
-    p.rational = 0;
-  }
-  p.a = frac01((double)f1_hz / (double)fs_hz);
-  p.w = frac01((double)(f2_hz - f1_hz) / ((double)M * (double)fs_hz));
+  const PhaseParams p = band_phase(fs_hz, f1_hz, f2_hz, M);
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
   std::shared_ptr<BluePlan> pl;
@@ -511,13 +487,7 @@ tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, in
     pl->T = T;
     // short DFT: X[k] = sum_m u[m] e^{-j 2 pi (k - floor(M/2)) m / K}: a CZT with
     // W = e^{-j 2 pi / K} and A = e^{-j 2 pi floor(M/2) / K} (rational, q = K)
-    PhaseParams p{};
-    p.rational = 1;
-    p.q = K;
-    p.pw = 1 % K;
-    p.pa = (K - (M / 2) % K) % K;
-    p.w = 1.0 / (double)K;
-    p.a = (double)p.pa / (double)K;
+    const PhaseParams p = zoom_phase(K, M);
     if ((st = get_blue(d, LD, M, p, c.stream, &pl->blue))) return st;
     TZ_HIP(pl->g.alloc(sizeof(float2) * T), "zoom taps");
     TZ_HIP(pl->ph.alloc(sizeof(float2) * LD), "zoom phasors");

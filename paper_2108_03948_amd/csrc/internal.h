@@ -17,6 +17,53 @@ struct PhaseParams {
 constexpr int kMaxL = 16384;
 constexpr int kMinL = 256;
 
+inline int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// FFT length, bin blocks and input segments of the Bluestein path.
+// One workgroup FFT of length L <= kMaxL must hold Ns samples and Mb bins
+// without wrap-around: Ns + Mb - 1 <= L.  Returns false when more than 256
+// block x segment pieces would be needed.
+inline bool czt_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb, int *nblk) {
+  if (N + M - 1 <= kMaxL) {
+    *L = (int)(next_pow2(N + M - 1) < kMinL ? kMinL : next_pow2(N + M - 1));
+    *Ns = N;
+    *nseg = 1;
+    *Mb = M;
+    *nblk = 1;
+    return true;
+  }
+  int64_t best = -1, bNs = 0, bMb = 0;
+  for (int64_t ns = 256; ns <= kMaxL - 256; ns += 256) {
+    const int64_t ns_eff = ns < N ? ns : N;
+    int64_t mb = kMaxL - ns_eff + 1;
+    if (mb > M) mb = M;
+    const int64_t cost = ((N + ns_eff - 1) / ns_eff) * ((M + mb - 1) / mb);
+    if (best < 0 || cost < best) {
+      best = cost;
+      bNs = ns_eff;
+      bMb = mb;
+    }
+    if (ns >= N) break;
+  }
+  if (best < 0 || best > 256) return false;
+  *L = kMaxL;
+  *Ns = bNs;
+  *nseg = (int)((N + bNs - 1) / bNs);
+  *Mb = bMb;
+  *nblk = (int)((M + bMb - 1) / bMb);
+  return true;
+}
+
+// phase parameters of a CZT over [f1, f2) with M bins, integer hertz:
+// a = f1/fs, w = (f2 - f1)/(M fs), exact when the common denominator fits
+PhaseParams band_phase(int64_t fs_hz, int64_t f1_hz, int64_t f2_hz, int64_t M);
+// phase parameters of the zoom short DFT: W = e^{-j 2 pi / K}, A = e^{-j 2 pi floor(M/2) / K}
+PhaseParams zoom_phase(int64_t K, int64_t M);
+
 // ---- plan-time table builders (tables.hip) ----
 hipError_t build_twiddles(float2 *tw, int64_t L, hipStream_t s);
 hipError_t build_root_table(float2 *w, int64_t n, int64_t q, hipStream_t s);
@@ -86,5 +133,8 @@ struct ZoomFrontLaunch {
 hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s);
 
 bool fft_length_supported(int64_t L);
+
+// message returned by tz_last_error() on this thread
+void set_last_error(const char *msg);
 
 }  // namespace tz

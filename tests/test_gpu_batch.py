@@ -1,0 +1,151 @@
+"""GPU parity of the uneven batch (one graph launch, persistent kernels).
+
+Every job is checked against the FP64 oracle on sampled bins (first, last and
+random ones; all bins for short jobs), to relative L2 <= 1e-6, for a mixed
+CZT / Zoom batch that covers every FFT-length class, bin blocks and input
+segments; the full 20000-job workload is run once with sampled checks.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tz():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_03948_amd as tz
+    tz.lib()
+    return tz
+
+
+def make_jobs(meta, offs):
+    jobs, out = [], 0
+    for i, j in enumerate(meta):
+        jobs.append(dict(kind=j["kind"], N=j["N"], M=j["M"], D=j["D"], taps=j["taps"],
+                         fs_hz=int(round(j["fs"])), f1_hz=int(round(j["f1"])), f2_hz=int(round(j["f2"])),
+                         in_offset=int(offs[i]), out_offset=out))
+        out += j["M"]
+    return jobs, out
+
+
+def check_jobs(orc, x_flat, offs, jobs, X, rows, rng, max_bins=96, full_below=2_000_000):
+    worst = 0.0
+    for i in rows:
+        j = jobs[i]
+        x = x_flat[offs[i]:offs[i + 1]].astype(np.float64)
+        M = j["M"]
+        if j["N"] * M <= full_below:
+            bins = np.arange(M)
+        else:
+            bins = np.unique(np.concatenate([[0, M - 1], rng.choice(M, max_bins, replace=False)]))
+        got = X[j["out_offset"] + bins]
+        if j["kind"] == "czt":
+            ref = orc.czt_band_exact(x, M, j["fs_hz"], j["f1_hz"], j["f2_hz"], bins)[0]
+        else:
+            full = orc.zoom_fft(x, j["fs_hz"], j["f1_hz"], j["f2_hz"], M, j["D"], taps=j["taps"])[0]
+            ref = full[bins]
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        worst = max(worst, e)
+        assert e <= TOL, f"job {i} ({j['kind']} N={j['N']} M={M}): rel L2 {e:.3e}"
+    return worst
+
+
+def run_batch(tz, x_flat, jobs, total_bins):
+    import torch
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(x_flat).to(dev)
+    Xd = torch.zeros(total_bins, dtype=torch.complex64, device=dev)
+    b = tz.Batch(jobs)
+    b.launch(xd, Xd)
+    torch.cuda.synchronize()
+    return b, xd, Xd
+
+
+def test_small_uneven_batch_all_classes(tz, orc):
+    x_flat, offs, meta = synth.uneven(B=48, seed=7, Nmin=1, Nmax=16384, Mmin=1, Mmax=8192)
+    # lengths down to 1 sample put the pulse outside the window; seeded
+    # normal samples keep every job non-zero
+    x_flat = np.random.default_rng(70).standard_normal(x_flat.size).astype(np.float32)
+    jobs, total = make_jobs(meta, offs)
+    say(f"case: uneven batch of {len(jobs)} jobs, N in [{min(j['N'] for j in jobs)}, "
+        f"{max(j['N'] for j in jobs)}], M in [{min(j['M'] for j in jobs)}, {max(j['M'] for j in jobs)}]")
+    b, xd, Xd = run_batch(tz, x_flat, jobs, total)
+    X = Xd.cpu().numpy()
+    worst = check_jobs(orc, x_flat, offs, jobs, X, range(len(jobs)), np.random.default_rng(1))
+    say(f"  worst rel L2 {worst:.3e}")
+    # a second launch on the same buffers is bitwise identical
+    Xd.zero_()
+    b.launch(xd, Xd)
+    import torch
+    torch.cuda.synchronize()
+    assert np.array_equal(Xd.cpu().numpy().view(np.uint32), X.view(np.uint32))
+    b.close()
+
+
+def test_batch_matches_single_calls(tz, orc):
+    import torch
+    dev = torch.device("cuda:0")
+    x_flat, offs, meta = synth.uneven(B=12, seed=11, Nmin=500, Nmax=6000, Mmin=100, Mmax=3000)
+    jobs, total = make_jobs(meta, offs)
+    say("case: batch vs single-call entry points, 12 jobs")
+    b, xd, Xd = run_batch(tz, x_flat, jobs, total)
+    for i, j in enumerate(jobs):
+        x = xd[offs[i]:offs[i + 1]].unsqueeze(0)
+        if j["kind"] == "czt":
+            one = tz.czt_band_exact(x, j["M"], j["fs_hz"], j["f1_hz"], j["f2_hz"])
+        else:
+            one = tz.zoom_fft(x, j["fs_hz"], j["f1_hz"], j["f2_hz"], j["M"], j["D"], taps=j["taps"])
+        got = Xd[j["out_offset"]:j["out_offset"] + j["M"]]
+        e = float((got - one[0]).abs().norm() / one[0].abs().norm())
+        assert e <= 1e-6, (i, e)
+    b.close()
+
+
+def test_batch_rejects_bad_jobs(tz):
+    bad = [dict(kind="czt", N=100, M=10, fs_hz=1000, f1_hz=300, f2_hz=200, in_offset=0, out_offset=0)]
+    with pytest.raises(tz.ThzError) as e:
+        tz.Batch(bad)
+    assert e.value.status == tz.TZ_EINVAL and "job 0" in str(e.value)
+
+
+def test_full_uneven_workload_sampled(tz, orc):
+    """The 20000-trace workload (N in [512, 16384], own band and M in
+    [256, 8192], CZT/Zoom 50/50) in one graph launch; 40 seeded jobs checked."""
+    import torch
+    t0 = time.time()
+    x_flat, offs, meta = synth.uneven(B=20000, seed=1003)
+    jobs, total = make_jobs(meta, offs)
+    say(f"case: full uneven workload, {len(jobs)} jobs, {x_flat.size} samples, {total} bins "
+        f"(generated in {time.time() - t0:.1f} s)")
+    t0 = time.time()
+    b, xd, Xd = run_batch(tz, x_flat, jobs, total)
+    say(f"  create + tuned first launch {time.time() - t0:.1f} s")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    b.launch(xd, Xd)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    say(f"  one launch {ms:.3f} ms = {total / ms * 1e3:.3e} bins/s")
+    say(f"  {b.describe()}")
+    X = Xd.cpu().numpy()
+    rng = np.random.default_rng(5)
+    rows = sorted(set(rng.choice(len(jobs), 38, replace=False).tolist()) | {0, len(jobs) - 1})
+    worst = check_jobs(orc, x_flat, offs, jobs, X, rows, rng, max_bins=64, full_below=0)
+    say(f"  worst rel L2 over {len(rows)} sampled jobs {worst:.3e}")
+    assert np.isfinite(X).all()
+    b.close()
