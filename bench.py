@@ -228,8 +228,31 @@ def main():
     rows = [0, B - 1]
     x64 = x_np[rows].astype(np.float64)
     ref = oracle.czt(x64, M, W, A)
-    got = Xc[rows].cpu().numpy()
-    err = float(np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)))
+
+    def rel_err(Xd):
+        got = Xd[rows].cpu().numpy()
+        return float(np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)))
+
+    err = rel_err(Xc)
+
+    # the same CZT with the radix-16 passes on the matrix cores
+    mfma = {"fp32_ms": ms_czt}
+    Xs = torch.empty_like(Xc)
+    for prec in ("split_fp16", "split_bf16"):
+        for _ in range(2):
+            tz.czt(x, M, W, A, out=Xs, precision=prec, stream=stream)
+        reps = max(5, args.steps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            tz.czt(x, M, W, A, out=Xs, precision=prec, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        mfma[prec] = {"ms": ms, "speedup_vs_fp32": ms_czt / ms, "rel_l2_sampled": rel_err(Xs),
+                      "bins_per_s": B * M / (ms * 1e-3)}
+        log(f"bench: czt {prec} {ms:.3f} ms ({ms_czt / ms:.2f}x fp32), rel L2 {mfma[prec]['rel_l2_sampled']:.2e}")
 
     out = {
         "metric": METRIC,
@@ -254,7 +277,7 @@ def main():
         "roofline": roof,
         "czt_only": {"value": B * M / (ms_czt * 1e-3), "ms": ms_czt},
         "kernels": kernels,
-        "mfma_vs_fp32": None,
+        "mfma_vs_fp32": mfma,
         "czt_rel_l2_sampled": err,
     }
     if not args.no_cpu:

@@ -52,7 +52,12 @@ typedef enum {
 
 /* input element type */
 enum { TZ_F32 = 0, TZ_F64 = 1 };
-/* arithmetic of the FFT stages */
+/* arithmetic of the FFT stages.  TZ_SPLIT_FP16 / TZ_SPLIT_BF16 run the
+ * radix-16 passes of czt() / czt_band_exact() on the matrix cores as dense
+ * 16-point DFT-matrix products with operands split into high and low 16-bit
+ * parts and FP32 accumulation (for FFT lengths 4096, 8192 and 16384 with one
+ * bin block and real input; other shapes and the other transforms return
+ * TZ_EUNSUPPORTED). */
 enum { TZ_FP32 = 0, TZ_SPLIT_FP16 = 1, TZ_SPLIT_BF16 = 2 };
 /* flags */
 enum {

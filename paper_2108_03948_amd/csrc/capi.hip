@@ -226,6 +226,14 @@ tz_status run_blue(Device &d, const BluePlan &pl, const void *x, int in_kind, vo
   a.L = pl.L;
   a.B = c.B;
   a.precision = c.precision;
+  if (c.precision != TZ_FP32) {
+    if (!czt_mfma_supported(pl.L, pl.nseg, pl.nblk, in_kind))
+      return fail(TZ_EUNSUPPORTED, "split precision needs L in {4096, 8192, 16384} with one bin block "
+                                   "(N + M - 1 <= 16384) and real input; this plan has L=%d",
+                  pl.L);
+    TZ_HIP(launch_czt_mfma(a, s), "czt (split precision) launch");
+    return TZ_OK;
+  }
   TZ_HIP(launch_czt(a, s), "czt launch");
   return TZ_OK;
 }
@@ -350,6 +358,7 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
   Common c;
   tz_status st = check_common(x, N, X, o, nout, &c);
   if (st) return st;
+  if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "fft_zeropad runs in FP32 only");
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
   char kb[64];
@@ -471,6 +480,7 @@ tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, in
   Common c;
   tz_status st = check_common(x, N, X, o, M, &c);
   if (st) return st;
+  if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "zoom_fft runs in FP32 only");
   const int64_t LD = (N + D - 1) / D;
   const double nuN = 0.5 * (f1 + f2) / fs;
   std::lock_guard<std::mutex> lk(g_mu);

@@ -90,6 +90,10 @@ struct CztLaunch {
   int precision;  // TZ_FP32 / split
 };
 hipError_t launch_czt(const CztLaunch &a, hipStream_t s);
+// split-precision (MFMA) variant: L in {4096, 8192, 16384}, one segment, one
+// bin block, real input
+bool czt_mfma_supported(int L, int nseg, int nblk, int in_kind);
+hipError_t launch_czt_mfma(const CztLaunch &a, hipStream_t s);
 
 // Zero-padded FFT, direct (N_fft = F) or split (N_fft = P * F, F >= N).
 struct PadLaunch {

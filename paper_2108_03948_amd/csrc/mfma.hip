@@ -1,0 +1,292 @@
+// Split-precision chirp-Z transform: the radix-16 passes of both FFTs run on
+// the matrix cores as a batched dense DFT-matrix product, the rest of the
+// Bluestein pipeline is the FP32 path's.
+//
+// A radix-16 pass computes y_j = F16 x_j for every butterfly j.  In real form
+//   [Re y; Im y] = [[Fr, -Fi], [Fi, Fr]] [Re x; Im x]   (32 x 32 times 32 x 1),
+// so 32 butterflies make one 32x32x32 real product: two
+// v_mfma_f32_32x32x16_{f16,bf16} per operand pair (K = 16 + 16).  Operands are
+// split into a high and a low part in the 16-bit type, and the product is
+// accumulated in FP32 as  Ah Bh + Ah Bl + Al Bh  (the Al Bl term is below the
+// FP32 rounding of the sum).  Each butterfly's inputs are scaled by a power of
+// two so that their largest component sits near 2^13: FP16's range holds the
+// high part and its low part stays normal; the scale is exact and is undone
+// on the FP32 result.
+//
+// Lane layout of the 32x32x16 operations (checked on the device):
+//   A (32 x 16): lane l holds row l%32, k = 8(l/32) + q, q < 8;
+//   B (16 x 32): lane l holds column l%32, k = 8(l/32) + q;
+//   C (32 x 32): lane l holds column l%32, rows (r%4) + 8(r/4) + 4(l/32), r < 16.
+// Wave w owns butterflies j = 64 w + 32 g + l%32 (g = 0, 1); lane half h = l/32
+// holds inputs 8h .. 8h+7 of its butterfly and, after the product, outputs
+// {4h .. 4h+3} and {8+4h .. 8+4h+3}.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.h"
+#include "internal.h"
+#include "thzspec.h"
+
+namespace tz {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+
+template <int PREC>
+struct Split;
+template <>
+struct Split<TZ_SPLIT_FP16> {
+  using V = half8;
+  using S = _Float16;
+  __device__ static float16v mfma(V a, V b, float16v c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Split<TZ_SPLIT_BF16> {
+  using V = bf8;
+  using S = __bf16;
+  __device__ static float16v mfma(V a, V b, float16v c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+};
+
+// index of output c (c < 8) held by lane half h
+__device__ __forceinline__ int out_k(int h, int c) { return (c < 4) ? 4 * h + c : 8 + 4 * h + (c - 4); }
+
+template <int L, int PREC>
+struct MfmaFft {
+  using SP = Split<PREC>;
+  using V = typename SP::V;
+  using S = typename SP::S;
+  static constexpr int NT = L / 16;          // threads: one radix-16 butterfly each
+  static constexpr int E = 16;               // points per thread
+  static constexpr int RT = L / 4096;        // trailing VALU radix (1, 2 or 4)
+  static constexpr int Q = L / 16;           // stride between the inputs of a butterfly
+  static_assert(L == 4096 || L == 8192 || L == 16384, "three radix-16 passes plus radix 1, 2 or 4");
+
+  // DFT-matrix operands of this lane: rows i = l%32, columns k = 8h + q;
+  // a1 multiplies Re x, a2 multiplies Im x.
+  V a1h, a1l, a2h, a2l;
+
+  __device__ void init(int lane) {
+    const int i = lane % 32, h = lane / 32;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = 8 * h + q;
+      const int m = ((i % 16) * k) % 16;
+      double s, c;
+      sincospi((double)m / 8.0, &s, &c);    // e^{-j 2 pi m/16} = c - j s
+      const float fr = (float)c, fi = (float)(-s);
+      const float v1 = (i < 16) ? fr : fi;  // coefficient of Re x[k]
+      const float v2 = (i < 16) ? -fi : fr; // coefficient of Im x[k]
+      const S h1 = (S)v1, h2 = (S)v2;
+      a1h[q] = h1;
+      a1l[q] = (S)(v1 - (float)h1);
+      a2h[q] = h2;
+      a2l[q] = (S)(v2 - (float)h2);
+    }
+  }
+
+  // y = F16 x for this lane's butterfly: x[q] are inputs 8h+q, results are
+  // outputs out_k(h, c), c < 8
+  __device__ __forceinline__ void butterfly(float2 (&x)[8], float2 (&y)[8]) const {
+    float mx = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fmaxf(fabsf(x[q].x), fabsf(x[q].y)));
+    mx = fmaxf(mx, __shfl_xor(mx, 32));  // partner lane holds the other 8 inputs
+    int ex = 0;
+    (void)frexpf(mx, &ex);
+    const int sh = (mx > 0.f) ? 13 - ex : 0;  // largest component near 2^13
+    const float up = ldexpf(1.f, sh), down = ldexpf(1.f, -sh);
+    V brh, brl, bih, bil;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float xr = x[q].x * up, xi = x[q].y * up;
+      const S hr = (S)xr, hi = (S)xi;
+      brh[q] = hr;
+      brl[q] = (S)(xr - (float)hr);
+      bih[q] = hi;
+      bil[q] = (S)(xi - (float)hi);
+    }
+    float16v c = {};
+    c = SP::mfma(a1h, brh, c);
+    c = SP::mfma(a1h, brl, c);
+    c = SP::mfma(a1l, brh, c);
+    c = SP::mfma(a2h, bih, c);
+    c = SP::mfma(a2h, bil, c);
+    c = SP::mfma(a2l, bih, c);
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      y[cc] = make_float2(c[cc] * down, c[8 + cc] * down);          // outputs 4h + cc
+      y[4 + cc] = make_float2(c[4 + cc] * down, c[12 + cc] * down);  // outputs 8 + 4h + cc
+    }
+  }
+
+  // one radix-16 pass p on the matrix cores: twiddle, product, exchange.
+  // xin[g][q] = input 8h+q of butterfly j(g); on return xin holds the inputs
+  // of pass p+1 in the same layout (p < 2), or of the trailing pass in the
+  // VALU layout v (p == 2).
+  template <int p>
+  __device__ __forceinline__ void pass(float2 (&xin)[2][8], float2 (&v)[E], float2 *lds, int wave, int lane,
+                                       const TwLds &tw) const {
+    constexpr int NS = p == 0 ? 1 : (p == 1 ? 16 : 256);
+    constexpr int TWS = L / (NS * 16);
+    const int h = lane / 32;
+    float2 y[2][8];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int j = 64 * wave + 32 * g + lane % 32;
+      if constexpr (NS > 1) {
+        const unsigned jm = (unsigned)(j % NS);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xin[g][q] = cmul(xin[g][q], tw(jm * (unsigned)(8 * h + q) * TWS));
+      }
+      butterfly(xin[g], y[g]);
+    }
+    __syncthreads();  // previous readers of LDS are done
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int j = 64 * wave + 32 * g + lane % 32;
+      const int base = (j / NS) * NS * 16 + (j % NS);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) lds[lds_idx(base + out_k(h, c) * NS)] = y[g][c];
+    }
+    __syncthreads();
+    if constexpr (p < 2) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int j = 64 * wave + 32 * g + lane % 32;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xin[g][q] = lds[lds_idx(j + (8 * h + q) * Q)];
+      }
+    } else {
+      // layout of the trailing pass (radix RT) or, with RT = 1, the final
+      // natural-order layout t + NT e
+      constexpr int R = RT > 1 ? RT : 16;
+      constexpr int NB = E / R;
+      const int t = threadIdx.x;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[i * R + r] = lds[lds_idx(t + i * NT + r * (L / R))];
+    }
+  }
+
+  // trailing VALU pass of radix RT over the 4096-point sub-transforms
+  __device__ __forceinline__ void trailing(float2 (&v)[E], const TwLds &tw) const {
+    if constexpr (RT > 1) {
+      constexpr int NB = E / RT;
+      const int t = threadIdx.x;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int j = t + i * NT;
+        apply_twiddles<RT>(&v[i * RT], tw, (unsigned)(j % 4096));
+        Dft<RT>::template run<1>(&v[i * RT]);
+      }
+    }
+  }
+
+  // register slot of element t + NT e after the transform
+  __device__ __forceinline__ static constexpr int out_slot(int e) {
+    return RT > 1 ? slot_of<E, RT>(e) : slot_of<E, 16>(e);
+  }
+};
+
+// Bluestein CZT with split-precision radix-16 passes (single bin block,
+// single segment, real input).  Same tables and algebra as k_czt.
+template <int L, int PREC, int KIND>
+__global__ void __launch_bounds__(L / 16)
+    k_czt_mfma(const void *__restrict__ x, int64_t xs, int64_t N, const float2 *__restrict__ c_pre,
+               const float2 *__restrict__ c_post, const float2 *__restrict__ V, const float2 *__restrict__ tw,
+               float2 *__restrict__ X, int64_t os, int64_t M) {
+  using MF = MfmaFft<L, PREC>;
+  constexpr int NT = MF::NT, E = MF::E, Q = MF::Q;
+  constexpr int XB = KIND == 1 ? 8 : 4;
+  __shared__ float2 lds[lds_points<L>()];
+  __shared__ float2 twl[tw_lds_points<L>()];
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64, h = lane / 32;
+  const int64_t b = blockIdx.x;
+  const TwLds twd = load_twiddles<L>(twl, tw, t, NT);
+  MF mf;
+  mf.init(lane);
+  __syncthreads();
+  const Rsrc rx = make_rsrc((const char *)x + b * xs * XB, (uint64_t)N * XB);
+  const Rsrc rp = make_rsrc(c_pre, (uint64_t)N * 8);
+  const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
+  const Rsrc rq = make_rsrc(c_post, (uint64_t)M * 8);
+  const Rsrc rX = make_rsrc(X + b * os, (uint64_t)M * 8);
+
+  float2 xin[2][8];
+  float2 v[E];
+  // FFT 1: premultiplied input straight into the matrix-core layout
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int j = 64 * wave + 32 * g + lane % 32;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const unsigned n = (unsigned)(j + (8 * h + q) * Q);
+      float xv;
+      if constexpr (KIND == 1)
+        xv = (float)ld_f64(rx, 8 * n);
+      else
+        xv = ld_f32(rx, 4 * n);
+      xin[g][q] = cscale(ld_c64(rp, 8 * n), xv);
+    }
+  }
+  mf.template pass<0>(xin, v, lds, wave, lane, twd);
+  mf.template pass<1>(xin, v, lds, wave, lane, twd);
+  mf.template pass<2>(xin, v, lds, wave, lane, twd);
+  mf.trailing(v, twd);
+  // spectral product with the conjugate chirp, then the inverse FFT as the
+  // conjugate of a forward FFT of the conjugate
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const unsigned k = (unsigned)(t + NT * e);
+    v[MF::out_slot(e)] = cconj(cmul(v[MF::out_slot(e)], ld_c64(rV, 8 * k)));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds[lds_idx(t + NT * e)] = v[MF::out_slot(e)];
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int j = 64 * wave + 32 * g + lane % 32;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xin[g][q] = lds[lds_idx(j + (8 * h + q) * Q)];
+  }
+  mf.template pass<0>(xin, v, lds, wave, lane, twd);
+  mf.template pass<1>(xin, v, lds, wave, lane, twd);
+  mf.template pass<2>(xin, v, lds, wave, lane, twd);
+  mf.trailing(v, twd);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const unsigned k = (unsigned)(t + NT * e);
+    st_c64(cmul(cconj(v[MF::out_slot(e)]), ld_c64(rq, 8 * k)), rX, 8 * k);
+  }
+}
+
+bool czt_mfma_supported(int L, int nseg, int nblk, int in_kind) {
+  return (L == 4096 || L == 8192 || L == 16384) && nseg == 1 && nblk == 1 && in_kind != 2;
+}
+
+template <int L, int PREC>
+static void mfma_dispatch(const CztLaunch &a, hipStream_t s) {
+  const dim3 grid((unsigned)a.B), block(L / 16);
+  if (a.in_kind == 1)
+    hipLaunchKernelGGL((k_czt_mfma<L, PREC, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.c_post, a.V, a.tw,
+                       a.X, a.os, a.M);
+  else
+    hipLaunchKernelGGL((k_czt_mfma<L, PREC, 0>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.c_post, a.V, a.tw,
+                       a.X, a.os, a.M);
+}
+
+hipError_t launch_czt_mfma(const CztLaunch &a, hipStream_t s) {
+  if (!czt_mfma_supported(a.L, a.nseg, a.nblk, a.in_kind)) return hipErrorInvalidValue;
+  const bool f16 = a.precision == TZ_SPLIT_FP16;
+  switch (a.L) {
+    case 4096: f16 ? mfma_dispatch<4096, TZ_SPLIT_FP16>(a, s) : mfma_dispatch<4096, TZ_SPLIT_BF16>(a, s); break;
+    case 8192: f16 ? mfma_dispatch<8192, TZ_SPLIT_FP16>(a, s) : mfma_dispatch<8192, TZ_SPLIT_BF16>(a, s); break;
+    default: f16 ? mfma_dispatch<16384, TZ_SPLIT_FP16>(a, s) : mfma_dispatch<16384, TZ_SPLIT_BF16>(a, s); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tz

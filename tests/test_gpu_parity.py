@@ -212,3 +212,34 @@ def test_full_size_batch_sampled(tz, dev, orc):
     sym = (Fr[:, 65536 - k] - Fr[:, k].conj()).abs().max() / Fr.abs().max()
     say(f"  fft Hermitian defect {float(sym):.2e}")
     assert float(sym) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# split precision: radix-16 passes on the matrix cores (hi + lo operands)
+# ---------------------------------------------------------------------------
+TOL_SPLIT = 1e-5
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("N,M", [(2000, 2000), (4096, 4096), (8192, 8000), (3000, 1)])
+def test_czt_split_precision(tz, dev, orc, prec, N, M):
+    x = synth.pairs(2, N=N)
+    fs, f1, f2 = 20e12, 0.2e12, 2.5e12
+    W, A = tz.czt_band(fs, f1, f2, M)
+    L, _ = tz.czt_plan_shape(N, M)
+    say(f"case: czt {prec} N={N} M={M} L={L}")
+    X = tz.czt(to_dev(x, dev), M, W, A, precision=prec).cpu().numpy()
+    ref = orc.czt(x.astype(np.float64), M, W, A)
+    r = rel_rows(X, ref)
+    say(f"  {prec}: max rel L2 {r.max():.3e}")
+    assert np.all(np.isfinite(X))
+    # hi + lo keeps ~22 (fp16) or ~16 (bf16) significant bits per operand;
+    # accumulation is FP32 in both cases
+    assert r.max() <= TOL_SPLIT
+
+
+def test_split_precision_rejects_other_shapes(tz, dev):
+    x = to_dev(np.ones((1, 100), np.float32), dev)
+    with pytest.raises(tz.ThzError) as e:
+        tz.czt(x, 100, np.exp(-0.01j), 1.0, precision="split_fp16")   # L = 256
+    assert e.value.status == tz.TZ_EUNSUPPORTED
