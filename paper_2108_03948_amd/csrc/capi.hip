@@ -62,19 +62,42 @@ struct DevMem {
   T *as() const { return (T *)p; }
 };
 
+// Device scratch of a plan, one buffer per stream: work on one stream is
+// ordered, and calls on different streams never share a buffer.
+struct Workspace {
+  std::map<hipStream_t, std::pair<std::unique_ptr<DevMem>, size_t>> per;
+  tz_status get(hipStream_t s, size_t bytes, void **out) {
+    auto &e = per[s];
+    if (!e.first) e.first.reset(new DevMem());
+    if (bytes > e.second) {
+      TZ_HIP(hipStreamSynchronize(s), "workspace");  // the old buffer may still be read
+      TZ_HIP(e.first->alloc(bytes), "workspace");
+      e.second = bytes;
+    }
+    *out = e.first->p;
+    return TZ_OK;
+  }
+};
+
+// Traces per four-step chunk: the chunk's L-point intermediates (written by
+// one kernel, read by the next) are kept near this many bytes so that they
+// stay in the last-level cache.
+constexpr int64_t kLongChunkBytes = (int64_t)128 << 20;
+
 struct BluePlan {
   int64_t N, M, Ns, Mb;
   int nseg, nblk, L;
-  DevMem c_pre, c_post, V;
+  int L1 = 0;  // > 0: four-step long path, L = L1 * (L / L1)
+  DevMem c_pre, c_post, V, tbig;
+  Workspace work;
 };
 
 struct ZoomPlan {
   std::shared_ptr<BluePlan> blue;
   int64_t LD, K, D;
   int T;
-  DevMem g, ph, u;
-  size_t u_bytes = 0;
-  std::mutex u_mu;
+  DevMem g, ph;
+  Workspace u;
 };
 
 struct PadPlan {
@@ -136,6 +159,25 @@ tz_status get_roots(Device &d, int64_t Nfft, hipStream_t s, const float2 **out) 
   return TZ_OK;
 }
 
+// Shape of a Bluestein plan: 1 = single-pass workgroup FFTs (with bin blocks
+// and input segments when N + M - 1 > 16384), 0 = four-step long path of
+// length *Llong, -1 = too long for either.  The long path is taken when the
+// blocks x segments of the single-pass form would transform more points than
+// one long FFT pair.
+int blue_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb, int *nblk, int *L1,
+               int64_t *Llong) {
+  const bool seg_ok = czt_shape(N, M, L, Ns, nseg, Mb, nblk);
+  if (seg_ok && *nseg == 1 && *nblk == 1) return 1;
+  int64_t Lb = next_pow2(N + M - 1);
+  if (Lb < ((int64_t)1 << 17)) Lb = (int64_t)1 << 17;
+  const bool long_ok = long_shape(Lb, L1);
+  if (long_ok && (!seg_ok || (int64_t)*nseg * *nblk * kMaxL > Lb)) {
+    *Llong = Lb;
+    return 0;
+  }
+  return seg_ok ? 1 : -1;
+}
+
 tz_status get_blue(Device &d, int64_t N, int64_t M, const PhaseParams &p, hipStream_t s,
                    std::shared_ptr<BluePlan> *out) {
   char kb[96];
@@ -149,13 +191,26 @@ tz_status get_blue(Device &d, int64_t N, int64_t M, const PhaseParams &p, hipStr
   auto pl = std::make_shared<BluePlan>();
   pl->N = N;
   pl->M = M;
-  if (!czt_shape(N, M, &pl->L, &pl->Ns, &pl->nseg, &pl->Mb, &pl->nblk))
-    return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld needs more than 256 single-pass FFT blocks",
-                (long long)N, (long long)M);
+  int L1 = 0;
+  int64_t Llong = 0;
+  const int seg = blue_shape(N, M, &pl->L, &pl->Ns, &pl->nseg, &pl->Mb, &pl->nblk, &L1, &Llong);
+  if (seg < 0)
+    return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld: N + M - 1 exceeds the longest FFT (2^24)", (long long)N,
+                (long long)M);
+  if (seg == 0) {
+    pl->L = (int)Llong;
+    pl->L1 = L1;
+    pl->Ns = N;
+    pl->Mb = M;
+    pl->nseg = pl->nblk = 1;
+    TZ_HIP(pl->tbig.alloc(sizeof(float2) * (2048 + Llong / 2048)), "twiddle table");
+    TZ_HIP(build_root_table(pl->tbig.as<float2>(), 2048, Llong, s), "twiddle table");
+    TZ_HIP(build_root_table(pl->tbig.as<float2>() + 2048, Llong / 2048, Llong / 2048, s), "twiddle table");
+  }
   TZ_HIP(pl->c_pre.alloc(sizeof(float2) * pl->Ns * pl->nblk), "chirp table");
   TZ_HIP(pl->c_post.alloc(sizeof(float2) * pl->Mb * pl->nblk * pl->nseg), "chirp table");
   TZ_HIP(pl->V.alloc(sizeof(float2) * pl->L), "chirp spectrum");
-  TZ_HIP(build_bluestein_tables(p, pl->Ns, pl->nseg, pl->Mb, pl->nblk, pl->L, pl->c_pre.as<float2>(),
+  TZ_HIP(build_bluestein_tables(p, pl->Ns, pl->nseg, pl->Mb, pl->nblk, pl->L, pl->L1, pl->c_pre.as<float2>(),
                                 pl->c_post.as<float2>(), pl->V.as<float2>(), s),
          "chirp tables");
   TZ_HIP(hipStreamSynchronize(s), "chirp tables");
@@ -202,8 +257,46 @@ bool finite_nonzero(tz_c64 z) { return isfinite(z.re) && isfinite(z.im) && (z.re
 
 double frac01(double v) { return v - floor(v); }
 
-tz_status run_blue(Device &d, const BluePlan &pl, const void *x, int in_kind, void *X, const Common &c,
+// four-step path: chunks of traces through the plan's per-stream workspace
+tz_status run_long(Device &d, BluePlan &pl, const void *x, int in_kind, void *X, const Common &c, int64_t M,
                    hipStream_t s) {
+  if (c.precision != TZ_FP32)
+    return fail(TZ_EUNSUPPORTED, "split precision needs L in {4096, 8192, 16384}; N=%lld, M=%lld uses the "
+                                 "four-step FP32 path (L=%d)",
+                (long long)pl.N, (long long)pl.M, pl.L);
+  LongLaunch a;
+  a.L1 = pl.L1;
+  a.L2 = pl.L / pl.L1;
+  tz_status st = get_twiddles(d, a.L1, s, &a.tw_col);
+  if (st) return st;
+  if ((st = get_twiddles(d, a.L2, s, &a.tw_row))) return st;
+  a.chunk = kLongChunkBytes / ((int64_t)pl.L * 8);
+  if (a.chunk < 1) a.chunk = 1;
+  if (a.chunk > c.B) a.chunk = c.B;
+  void *w = nullptr;
+  if ((st = pl.work.get(s, sizeof(float2) * (size_t)pl.L * (size_t)a.chunk, &w))) return st;
+  a.work = (float2 *)w;
+  a.x = x;
+  a.in_kind = in_kind;
+  a.xs = c.xs;
+  a.N = pl.N;
+  a.c_pre = pl.c_pre.as<float2>();
+  a.c_post = pl.c_post.as<float2>();
+  a.Vt = pl.V.as<float2>();
+  a.tbig = pl.tbig.as<float2>();
+  a.X = (float2 *)X;
+  a.os = c.os;
+  a.M = M;
+  a.B = c.B;
+  TZ_HIP(launch_czt_long(a, s), "czt (four-step) launch");
+  return TZ_OK;
+}
+
+// M_out < pl.M evaluates only the first M_out bins (0 = all)
+tz_status run_blue(Device &d, BluePlan &pl, const void *x, int in_kind, void *X, const Common &c,
+                   hipStream_t s, int64_t M_out = 0) {
+  const int64_t M = M_out > 0 ? M_out : pl.M;
+  if (pl.L1) return run_long(d, pl, x, in_kind, X, c, M, s);
   const float2 *tw = nullptr;
   tz_status st = get_twiddles(d, pl.L, s, &tw);
   if (st) return st;
@@ -220,7 +313,7 @@ tz_status run_blue(Device &d, const BluePlan &pl, const void *x, int in_kind, vo
   a.tw = tw;
   a.X = (float2 *)X;
   a.os = c.os;
-  a.M = pl.M;
+  a.M = M;
   a.Mb = pl.Mb;
   a.nblk = pl.nblk;
   a.L = pl.L;
@@ -397,32 +490,9 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
     pp = pl;
   }
   if (pp->blue) {
-    const Common &c2 = c;
     // the cached Bluestein plan evaluates all Nfft bins; with TZ_HALF only
-    // the first nout rows are wanted, so M is clipped at launch time
-    const float2 *tw = nullptr;
-    if ((st = get_twiddles(d, pp->blue->L, c.stream, &tw))) return st;
-    CztLaunch a;
-    a.x = x;
-    a.in_kind = c.in_kind;
-    a.xs = c2.xs;
-    a.N = N;
-    a.Ns = pp->blue->Ns;
-    a.nseg = pp->blue->nseg;
-    a.c_pre = pp->blue->c_pre.as<float2>();
-    a.c_post = pp->blue->c_post.as<float2>();
-    a.V = pp->blue->V.as<float2>();
-    a.tw = tw;
-    a.X = (float2 *)X;
-    a.os = c2.os;
-    a.M = nout;
-    a.Mb = pp->blue->Mb;
-    a.nblk = pp->blue->nblk;
-    a.L = pp->blue->L;
-    a.B = c.B;
-    a.precision = c.precision;
-    TZ_HIP(launch_czt(a, c.stream), "fft_zeropad (czt) launch");
-    return TZ_OK;
+    // the first nout are wanted
+    return run_blue(d, *pp->blue, x, c.in_kind, X, c, c.stream, nout);
   }
   if (pp->realF) {
     const float2 *tw = nullptr, *rh = nullptr, *rf = nullptr;
@@ -499,21 +569,17 @@ tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, in
     // W = e^{-j 2 pi / K} and A = e^{-j 2 pi floor(M/2) / K} (rational, q = K)
     const PhaseParams p = zoom_phase(K, M);
     if ((st = get_blue(d, LD, M, p, c.stream, &pl->blue))) return st;
-    TZ_HIP(pl->g.alloc(sizeof(float2) * T), "zoom taps");
-    TZ_HIP(pl->ph.alloc(sizeof(float2) * LD), "zoom phasors");
-    TZ_HIP(build_zoom_tables(pl->g.as<float2>(), T, fc / fs, nuN - floor(nuN), pl->ph.as<float2>(), LD, D,
+    TZ_HIP(pl->g.alloc(sizeof(double2) * T), "zoom taps");
+    TZ_HIP(pl->ph.alloc(sizeof(double2) * LD), "zoom phasors");
+    TZ_HIP(build_zoom_tables(pl->g.as<double2>(), T, fc / fs, nuN - floor(nuN), pl->ph.as<double2>(), LD, D,
                              c.stream),
            "zoom tables");
     TZ_HIP(hipStreamSynchronize(c.stream), "zoom tables");
     zp = pl;
   }
   ZoomPlan &z = *zp;
-  const size_t ub = sizeof(float2) * (size_t)LD * (size_t)c.B;
-  if (ub > z.u_bytes) {
-    TZ_HIP(hipStreamSynchronize(c.stream), "zoom workspace");
-    TZ_HIP(z.u.alloc(ub), "zoom workspace");
-    z.u_bytes = ub;
-  }
+  void *u = nullptr;
+  if ((st = z.u.get(c.stream, sizeof(float2) * (size_t)LD * (size_t)c.B, &u))) return st;
   ZoomFrontLaunch f;
   f.x = x;
   f.in_kind = c.in_kind;
@@ -522,14 +588,14 @@ tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, in
   f.D = D;
   f.LD = LD;
   f.T = T;
-  f.g = z.g.as<float2>();
-  f.ph = z.ph.as<float2>();
-  f.u = z.u.as<float2>();
+  f.g = z.g.as<double2>();
+  f.ph = z.ph.as<double2>();
+  f.u = (float2 *)u;
   f.B = c.B;
   TZ_HIP(launch_zoom_front(f, c.stream), "zoom front-end launch");
   Common c2 = c;
   c2.xs = LD;
-  return run_blue(d, *z.blue, z.u.p, 2, X, c2, c.stream);
+  return run_blue(d, *z.blue, u, 2, X, c2, c.stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,13 +639,14 @@ int64_t zoom_short_length(double fs, double f1, double f2, int64_t M, int64_t D)
 
 tz_status czt_plan_shape(int64_t N, int64_t M, int64_t *L, int64_t *blocks) {
   if (N < 1 || M < 1 || !L || !blocks) return fail(TZ_EINVAL, "need N, M >= 1 and non-NULL outputs");
-  int l, nseg, nblk;
-  int64_t ns, mb;
-  if (!czt_shape(N, M, &l, &ns, &nseg, &mb, &nblk))
-    return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld too long for the single-pass path", (long long)N,
+  int l, nseg, nblk, l1;
+  int64_t ns, mb, llong;
+  const int k = blue_shape(N, M, &l, &ns, &nseg, &mb, &nblk, &l1, &llong);
+  if (k < 0)
+    return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld: N + M - 1 exceeds the longest FFT (2^24)", (long long)N,
                 (long long)M);
-  *L = l;
-  *blocks = (int64_t)nblk * nseg;
+  *L = k == 0 ? llong : l;
+  *blocks = k == 0 ? 1 : (int64_t)nblk * nseg;
   return TZ_OK;
 }
 

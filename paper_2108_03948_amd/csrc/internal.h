@@ -67,10 +67,11 @@ PhaseParams zoom_phase(int64_t K, int64_t M);
 // ---- plan-time table builders (tables.hip) ----
 hipError_t build_twiddles(float2 *tw, int64_t L, hipStream_t s);
 hipError_t build_root_table(float2 *w, int64_t n, int64_t q, hipStream_t s);
-// c_pre [nblk][Ns], c_post [nseg][nblk][Mb], V [L]
+// c_pre [nblk][Ns], c_post [nseg][nblk][Mb], V [L]; with L1 > 0, V is stored
+// in four-step order: V[k1 L2 + k2] holds bin k1 + L1 k2 (L = L1 L2)
 hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, int64_t Mb, int nblk,
-                                  int64_t L, float2 *c_pre, float2 *c_post, float2 *V, hipStream_t s);
-hipError_t build_zoom_tables(float2 *g, int T, double nu_c, double nu_N, float2 *ph, int64_t LD,
+                                  int64_t L, int L1, float2 *c_pre, float2 *c_post, float2 *V, hipStream_t s);
+hipError_t build_zoom_tables(double2 *g, int T, double nu_c, double nu_N, double2 *ph, int64_t LD,
                              int64_t D, hipStream_t s);
 
 // ---- hot-path launchers (kernels.hip) ----
@@ -94,6 +95,26 @@ hipError_t launch_czt(const CztLaunch &a, hipStream_t s);
 // bin block, real input
 bool czt_mfma_supported(int L, int nseg, int nblk, int in_kind);
 hipError_t launch_czt_mfma(const CztLaunch &a, hipStream_t s);
+
+// Four-step Bluestein CZT for long traces (one segment, one bin block):
+// L = L1 L2 with L1 in {512, 1024} and 256 <= L2 <= 16384.  work holds
+// chunk * L complex values; traces run chunk at a time.
+struct LongLaunch {
+  const void *x;
+  int in_kind;  // 0 = f32 real, 1 = f64 real, 2 = complex f32
+  int64_t xs, N;
+  const float2 *c_pre, *c_post, *Vt;  // Vt in four-step order
+  const float2 *tw_col, *tw_row;      // FFT twiddles of lengths L1 and L2
+  const float2 *tbig;                 // W_L^i (i < 2048), then W_L^{2048 i}
+  float2 *work;
+  float2 *X;
+  int64_t os, M;
+  int L1, L2;
+  int64_t B, chunk;
+};
+// L1 for a four-step length L (a power of two in [2^17, 2^24]); false otherwise
+bool long_shape(int64_t L, int *L1);
+hipError_t launch_czt_long(const LongLaunch &a, hipStream_t s);
 
 // Zero-padded FFT, direct (N_fft = F) or split (N_fft = P * F, F >= N).
 struct PadLaunch {
@@ -130,7 +151,7 @@ struct ZoomFrontLaunch {
   int in_kind;
   int64_t xs, N, D, LD;
   int T;
-  const float2 *g, *ph;
+  const double2 *g, *ph;  // FP64 modulated taps and mixing phasors
   float2 *u;
   int64_t B;
 };

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fft_core.h"
 #include "internal.h"
 
@@ -286,28 +288,72 @@ __global__ void __launch_bounds__(64 * P)
 // decimation fused, evaluated only at the kept outputs:
 //   u[m] = e^{-j 2 pi nu_N m D} sum_{t<T} g[t] x[mD - t],  g[t] = h[t] e^{j 2 pi nu_N t}
 // (the same as filtering y[n] = x[n] e^{-j 2 pi nu_N n} with h and keeping
-// every D-th output).
+// every D-th output).  Taps and phasors are FP64 and the T-term sums are
+// accumulated in FP64: an FP32 accumulator rounds at every step and its error
+// grows like sqrt(T) relative to |u|, which a narrow output band magnifies.
+//
+// Workgroup (b, m0) stages x[m0 D - (T-1) .. (m0 + opb - 1) D] and the taps
+// in LDS; thread j forms output m0 + j.  One pad slot every 64 samples puts
+// the stride-D reads of a wave on different banks.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int zpad(int i) { return i + (i >> 6); }
+
 template <int KIND>
 __global__ void __launch_bounds__(256)
     k_zoom_front(const void *__restrict__ x, int64_t xs, int64_t N, int64_t D, int64_t LD, int T,
-                 const float2 *__restrict__ g, const float2 *__restrict__ ph,
-                 float2 *__restrict__ u, int64_t blocks_per_trace) {
-  const int64_t b = blockIdx.x / blocks_per_trace;
-  const int64_t m = (blockIdx.x % blocks_per_trace) * 256 + threadIdx.x;
+                 const double2 *__restrict__ g, const double2 *__restrict__ ph, float2 *__restrict__ u,
+                 int64_t bpt, int opb) {
+  using XT = typename std::conditional<KIND == 1, double, float>::type;
+  extern __shared__ double2 zsm[];
+  double2 *gl = zsm;
+  XT *xl = (XT *)(zsm + T);
+  const int64_t b = blockIdx.x / bpt;
+  const int64_t m0 = (blockIdx.x % bpt) * opb;
+  const int64_t n0 = m0 * D - (T - 1);
+  const int span = (opb - 1) * (int)D + T;
+  const XT *xb = (const XT *)x + b * xs;
+  for (int i = threadIdx.x; i < T; i += blockDim.x) gl[i] = g[i];
+  for (int i = threadIdx.x; i < span; i += blockDim.x) {
+    const int64_t n = n0 + i;
+    xl[zpad(i)] = (n >= 0 && n < N) ? xb[n] : (XT)0;
+  }
+  __syncthreads();
+  const int j = threadIdx.x;
+  const int64_t m = m0 + j;
+  if (j >= opb || m >= LD) return;
+  const int top = j * (int)D + T - 1;  // tile index of x[mD]
+  double ar = 0.0, ai = 0.0;
+  for (int t = 0; t < T; ++t) {
+    const double xv = (double)xl[zpad(top - t)];
+    ar = fma(gl[t].x, xv, ar);
+    ai = fma(gl[t].y, xv, ai);
+  }
+  const double2 p = ph[m];
+  u[b * LD + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));
+}
+
+// same sums with x and the taps read from global memory (filters too long
+// for the LDS tile)
+template <int KIND>
+__global__ void __launch_bounds__(256)
+    k_zoom_front_global(const void *__restrict__ x, int64_t xs, int64_t N, int64_t D, int64_t LD, int T,
+                        const double2 *__restrict__ g, const double2 *__restrict__ ph, float2 *__restrict__ u,
+                        int64_t bpt) {
+  const int64_t b = blockIdx.x / bpt;
+  const int64_t m = (blockIdx.x % bpt) * 256 + threadIdx.x;
   if (m >= LD) return;
   const int64_t base = m * D;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int tt = 0; tt < T; ++tt) {
-    const int64_t n = base - tt;
+  double ar = 0.0, ai = 0.0;
+  for (int t = 0; t < T; ++t) {
+    const int64_t n = base - t;
     if (n >= 0 && n < N) {
-      const float xv = load_real<KIND>(x, b * xs + n);
-      const float2 gg = g[tt];
-      acc.x = fmaf(gg.x, xv, acc.x);
-      acc.y = fmaf(gg.y, xv, acc.y);
+      const double xv = (double)load_real<KIND>(x, b * xs + n);
+      ar = fma(g[t].x, xv, ar);
+      ai = fma(g[t].y, xv, ai);
     }
   }
-  u[b * LD + m] = cmul(ph[m], acc);
+  const double2 p = ph[m];
+  u[b * LD + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));
 }
 
 // ---------------------------------------------------------------------------
@@ -408,13 +454,36 @@ hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s) {
 }
 
 hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
+  // LDS tile: T FP64 taps plus the samples of opb outputs, within 64 KB
+  constexpr int64_t kTileBytes = 64 * 1024;
+  const int64_t xb = a.in_kind == 1 ? 8 : 4;
+  const int64_t tap_bytes = 16 * (int64_t)a.T;
+  int64_t opb = 0;
+  if (tap_bytes + xb * (a.T + a.T / 64 + 1) <= kTileBytes) {
+    const int64_t xmax = (kTileBytes - tap_bytes) / xb * 64 / 65 - 1;  // samples, pads included
+    opb = (xmax - a.T) / a.D + 1;
+    if (opb > 256) opb = 256;
+  }
+  if (opb >= 1) {
+    const int64_t span = (opb - 1) * a.D + a.T;
+    const size_t shm = (size_t)(tap_bytes + xb * (span + span / 64 + 1));
+    const int64_t bpt = (a.LD + opb - 1) / opb;
+    const dim3 grid((unsigned)(a.B * bpt)), block((unsigned)((opb + 63) / 64 * 64));
+    if (a.in_kind == 1)
+      hipLaunchKernelGGL((k_zoom_front<1>), grid, block, shm, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph, a.u,
+                         bpt, (int)opb);
+    else
+      hipLaunchKernelGGL((k_zoom_front<0>), grid, block, shm, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph, a.u,
+                         bpt, (int)opb);
+    return hipGetLastError();
+  }
   const int64_t bpt = (a.LD + 255) / 256;
   const dim3 grid((unsigned)(a.B * bpt)), block(256);
   if (a.in_kind == 1)
-    hipLaunchKernelGGL((k_zoom_front<1>), grid, block, 0, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph,
+    hipLaunchKernelGGL((k_zoom_front_global<1>), grid, block, 0, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph,
                        a.u, bpt);
   else
-    hipLaunchKernelGGL((k_zoom_front<0>), grid, block, 0, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph,
+    hipLaunchKernelGGL((k_zoom_front_global<0>), grid, block, 0, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph,
                        a.u, bpt);
   return hipGetLastError();
 }

@@ -109,10 +109,13 @@ __global__ void k_fft64_pass(const double2 *in, double2 *out, int64_t L, int R, 
   for (int k = 0; k < R; ++k) out[base + k * ns] = y[k];
 }
 
-__global__ void k_to_float_scaled(const double2 *in, float2 *out, int64_t L, double scale) {
+// out = in * scale, in natural order (L1 = 0) or four-step order: bin
+// i = k1 + L1 k2 goes to out[k1 (L/L1) + k2]
+__global__ void k_to_float_scaled(const double2 *in, float2 *out, int64_t L, double scale, int64_t L1) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L) return;
-  out[i] = make_float2((float)(in[i].x * scale), (float)(in[i].y * scale));
+  const int64_t o = L1 > 0 ? (i % L1) * (L / L1) + i / L1 : i;
+  out[o] = make_float2((float)(in[i].x * scale), (float)(in[i].y * scale));
 }
 
 // ---------------------------------------------------------------------------
@@ -121,7 +124,7 @@ __global__ void k_to_float_scaled(const double2 *in, float2 *out, int64_t L, dou
 // Hamming-windowed sinc low-pass, cut-off nu_c cycles/sample, unit DC gain,
 // then modulated: g[t] = h[t] e^{+j 2 pi nu_N t} so that the mix-down of eq. (7)
 // followed by the filter of eq. (10) is  u[m] = e^{-j 2 pi nu_N m D} sum_t g[t] x[mD-t].
-__global__ void k_zoom_taps(float2 *g, int T, double nu_c, double nu_N) {
+__global__ void k_zoom_taps(double2 *g, int T, double nu_c, double nu_N) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double sum = 0.0;
   for (int t = 0; t < T; ++t) {
@@ -148,15 +151,17 @@ __global__ void k_zoom_taps(float2 *g, int T, double nu_c, double nu_N) {
     double cyc = frac_mul(nu_N, (double)t);
     double s, c;
     sincospi(2.0 * cyc, &s, &c);
-    g[t] = make_float2((float)(h * c), (float)(h * s));
+    g[t] = make_double2(h * c, h * s);
   }
 }
 
 // ph[m] = e^{-j 2 pi nu_N m D}
-__global__ void k_zoom_phasors(float2 *ph, int64_t LD, int64_t D, double nu_N) {
+__global__ void k_zoom_phasors(double2 *ph, int64_t LD, int64_t D, double nu_N) {
   int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= LD) return;
-  ph[m] = unit_cycles(frac_mul(nu_N, (double)(m * D)));
+  double s, c;
+  sincospi(-2.0 * frac_mul(nu_N, (double)(m * D)), &s, &c);
+  ph[m] = make_double2(c, s);
 }
 
 // W_Nfft^m for the split zero-padded FFT
@@ -192,7 +197,7 @@ static int radix_list(int64_t L, int *rs) {
 }
 
 hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, int64_t Mb, int nblk,
-                                  int64_t L, float2 *c_pre, float2 *c_post, float2 *V, hipStream_t s) {
+                                  int64_t L, int L1, float2 *c_pre, float2 *c_post, float2 *V, hipStream_t s) {
   hipError_t e;
   const int64_t N = Ns;
   hipLaunchKernelGGL(k_chirp_pre, dim3(nblocks(Ns * nblk, 256)), dim3(256), 0, s, c_pre, Ns, nblk, Mb, p);
@@ -212,14 +217,15 @@ hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, in
     double2 *t = a; a = b; b = t;
   }
   // V = FFT(v) / L (the 1/L of the inverse FFT folded in)
-  hipLaunchKernelGGL(k_to_float_scaled, dim3(nblocks(L, 256)), dim3(256), 0, s, a, V, L, 1.0 / (double)L);
+  hipLaunchKernelGGL(k_to_float_scaled, dim3(nblocks(L, 256)), dim3(256), 0, s, a, V, L, 1.0 / (double)L,
+                     (int64_t)L1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipFreeAsync(a, s);
   hipFreeAsync(b, s);
   return hipGetLastError();
 }
 
-hipError_t build_zoom_tables(float2 *g, int T, double nu_c, double nu_N, float2 *ph, int64_t LD,
+hipError_t build_zoom_tables(double2 *g, int T, double nu_c, double nu_N, double2 *ph, int64_t LD,
                              int64_t D, hipStream_t s) {
   hipLaunchKernelGGL(k_zoom_taps, dim3(1), dim3(64), 0, s, g, T, nu_c, nu_N);
   hipLaunchKernelGGL(k_zoom_phasors, dim3(nblocks(LD, 256)), dim3(256), 0, s, ph, LD, D, nu_N);

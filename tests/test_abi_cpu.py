@@ -102,6 +102,12 @@ def test_czt_plan_shape(tz):
     assert tz.czt_plan_shape(8193, 8192) == (16384, 1)
     L, blocks = tz.czt_plan_shape(16384, 8192)
     assert L == 16384 and blocks > 1
+    # long traces: one four-step FFT pair of length next_pow2(N + M - 1)
+    assert tz.czt_plan_shape(1 << 20, 1 << 18) == (1 << 21, 1)
+    assert tz.czt_plan_shape(16384, 1 << 18) == (1 << 19, 1)
+    assert tz.czt_plan_shape(40000, 30000) == (1 << 17, 1)
+    with pytest.raises(tz.ThzError):
+        tz.czt_plan_shape(1 << 24, 2)
 
 
 def _raw(tz, fn, *args):

@@ -1,0 +1,161 @@
+"""GPU parity of the four-step long path: Bluestein CZT with N + M - 1 above
+16384 where bin blocks x input segments would transform more points than one
+long FFT pair (L = L1 L2 up to 2^24).
+
+Checked against the FP64 oracle on sampled bins (first, last, middle and
+seeded random ones) to relative L2 <= 1e-6, for float and integer-hertz
+phases, f32 / f64 / complex (zoom) inputs, M below the row length, several
+trace chunks, and the long-scan workload: 256 traces x 2^20 samples at
+Ts = 0.01 ps, CZT M = 2^18 over 0.05 - 0.10 THz and Zoom FFT D = 64 with a
+255-tap FIR.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tz():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_03948_amd as tz
+    tz.lib()
+    return tz
+
+
+def sample_bins(M, rng, n=96):
+    extra = rng.choice(M, min(n, M), replace=False)
+    return np.unique(np.concatenate([[0, M - 1, M // 2], extra])).astype(np.int64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("N,M,dtype", [(40000, 30000, np.float32), (1000000, 1000, np.float32),
+                                       (70001, 60000, np.float64), (131071, 2, np.float32)])
+def test_long_czt_float_phases(tz, orc, N, M, dtype):
+    import torch
+    L, blocks = tz.czt_plan_shape(N, M)
+    say(f"case: long czt N={N} M={M} {np.dtype(dtype).name} plan L={L} blocks={blocks}")
+    assert blocks == 1 and L >= (1 << 17)
+    rng = np.random.default_rng(N + M)
+    x = rng.standard_normal((3, N)).astype(dtype)
+    W = np.exp(-2j * np.pi * 0.37 / (N + M))
+    A = np.exp(2j * np.pi * 0.0123)
+    X = tz.czt(torch.from_numpy(x).cuda(), M, W, A).cpu().numpy()
+    bins = sample_bins(M, rng)
+    ref = orc.czt(x.astype(np.float64), M, W, A, bins)
+    for b in range(3):
+        e = rel(X[b, bins], ref[b])
+        say(f"  trace {b}: rel L2 {e:.3e}")
+        assert e <= TOL
+
+
+def test_long_czt_batch_of_eight_narrow_columns(tz, orc):
+    """M below the row length L2 with a grid of whole column groups (8 traces)."""
+    import torch
+    N, M = 1000000, 1000
+    assert tz.czt_plan_shape(N, M) == (1 << 20, 1)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((8, N)).astype(np.float32)
+    say(f"case: long czt_band_exact N={N} M={M} B=8")
+    fs, f1, f2 = 20_000_000_000_000, 300_000_000_000, 310_000_000_000
+    X = tz.czt_band_exact(torch.from_numpy(x).cuda(), M, fs, f1, f2).cpu().numpy()
+    for b in (0, 5, 7):
+        bins = sample_bins(M, rng, 40)
+        ref = orc.czt_band_exact(x[b:b + 1].astype(np.float64), M, fs, f1, f2, bins)[0]
+        e = rel(X[b, bins], ref)
+        say(f"  trace {b}: rel L2 {e:.3e}")
+        assert e <= TOL
+
+
+def test_long_fft_zeropad_without_fast_factor(tz, orc):
+    """N_fft with no power-of-two factor >= N goes through the long Bluestein plan."""
+    import torch
+    N, nz = 30000, 120015                      # N_fft = 150015 = 3^2 5 3 ... (odd)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, N)).astype(np.float32)
+    say(f"case: long fft_zeropad N={N} N_fft={N + nz}")
+    X = tz.fft_zeropad(torch.from_numpy(x).cuda(), nz).cpu().numpy()
+    bins = sample_bins(N + nz, rng)
+    ref = orc.fft_zeropad(x.astype(np.float64), nz, bins)
+    for b in range(2):
+        assert rel(X[b, bins], ref[b]) <= TOL
+
+
+FS, F1, F2 = 100_000_000_000_000, 50_000_000_000, 100_000_000_000
+N_LONG, M_LONG, B_LONG = 1 << 20, 1 << 18, 256
+
+
+@pytest.fixture(scope="module")
+def long_scans():
+    import torch
+    t0 = time.time()
+    x = synth.echoes(B_LONG, N=N_LONG, fs=float(FS))
+    say(f"long scans generated in {time.time() - t0:.1f} s")
+    return x, torch.from_numpy(x).cuda()
+
+
+def timed(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return out, e0.elapsed_time(e1) / reps
+
+
+def test_long_scans_czt(tz, orc, long_scans):
+    x, xd = long_scans
+    say(f"case: long scans czt B={B_LONG} N={N_LONG} M={M_LONG} plan {tz.czt_plan_shape(N_LONG, M_LONG)}")
+    X, ms = timed(lambda: tz.czt_band_exact(xd, M_LONG, FS, F1, F2))
+    say(f"  {ms:.3f} ms per batch, {B_LONG * M_LONG / ms * 1e3:.3e} bins/s")
+    Xh = X.cpu().numpy()
+    assert np.isfinite(Xh).all()
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for b in (0, 77, 255):
+        bins = sample_bins(M_LONG, rng, 64)
+        ref = orc.czt_band_exact(x[b:b + 1].astype(np.float64), M_LONG, FS, F1, F2, bins)[0]
+        e = rel(Xh[b, bins], ref)
+        worst = max(worst, e)
+        assert e <= TOL, (b, e)
+    say(f"  worst sampled rel L2 {worst:.3e}")
+
+
+def test_long_scans_zoom(tz, orc, long_scans):
+    x, xd = long_scans
+    D, T = 64, 255
+    say(f"case: long scans zoom B={B_LONG} N={N_LONG} M={M_LONG} D={D} T={T} "
+        f"K={tz.zoom_short_length(FS, F1, F2, M_LONG, D)}")
+    X, ms = timed(lambda: tz.zoom_fft(xd, FS, F1, F2, M_LONG, D, taps=T))
+    say(f"  {ms:.3f} ms per batch, {B_LONG * M_LONG / ms * 1e3:.3e} bins/s")
+    Xh = X.cpu().numpy()
+    assert np.isfinite(Xh).all()
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for b in (0, 128, 255):
+        bins = sample_bins(M_LONG, rng, 64)
+        ref = orc.zoom_fft(x[b:b + 1].astype(np.float64), FS, F1, F2, M_LONG, D, taps=T, bins=bins)[0]
+        e = rel(Xh[b, bins], ref)
+        worst = max(worst, e)
+        assert e <= TOL, (b, e)
+    say(f"  worst sampled rel L2 {worst:.3e}")
