@@ -168,26 +168,28 @@ __global__ void k_batch_reset(unsigned *counters, int n) {
 }
 
 // zoom front end for every zoom job (one workgroup per job):
-// u[m] = e^{-j 2 pi nu_N m D} sum_t g[t] x[mD - t]
+// u[m] = e^{-j 2 pi nu_N m D} sum_t g[t] x[mD - t], FP64 taps, phasors and
+// sums (the T-term sum in FP32 would lose accuracy as sqrt(T))
 __global__ void __launch_bounds__(256)
     k_batch_zoom_front(const float *__restrict__ x, float2 *__restrict__ u, const float2 *__restrict__ arena,
                        const ZoomJob *__restrict__ jobs) {
   const ZoomJob j = jobs[blockIdx.x];
-  const float2 *g = arena + j.g_off;
-  const float2 *ph = arena + j.ph_off;
+  const double2 *g = (const double2 *)(arena + j.g_off);
+  const double2 *ph = (const double2 *)(arena + j.ph_off);
   const float *xb = x + j.x_off;
   for (int m = threadIdx.x; m < j.LD; m += 256) {
     const int64_t base = (int64_t)m * j.D;
-    float2 acc = make_float2(0.f, 0.f);
+    double ar = 0.0, ai = 0.0;
     for (int tt = 0; tt < j.T; ++tt) {
       const int64_t n = base - tt;
       if (n >= 0 && n < j.N) {
-        const float xv = xb[n];
-        acc.x = fmaf(g[tt].x, xv, acc.x);
-        acc.y = fmaf(g[tt].y, xv, acc.y);
+        const double xv = (double)xb[n];
+        ar = fma(g[tt].x, xv, ar);
+        ai = fma(g[tt].y, xv, ai);
       }
     }
-    u[j.u_off + m] = cmul(ph[m], acc);
+    const double2 p = ph[m];
+    u[j.u_off + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));
   }
 }
 
@@ -305,9 +307,12 @@ struct ZoomTableJob {
 };
 
 // Hamming-windowed sinc taps (unit DC gain) modulated by e^{j 2 pi nu_N t},
-// and output phasors e^{-j 2 pi nu_N m D}
+// and output phasors e^{-j 2 pi nu_N m D}, both kept in FP64 (two arena
+// slots per value)
 __global__ void k_batch_zoom_tables(float2 *arena, const ZoomTableJob *__restrict__ jobs) {
   const ZoomTableJob j = jobs[blockIdx.x];
+  double2 *g = (double2 *)(arena + j.g_off);
+  double2 *ph = (double2 *)(arena + j.ph_off);
   if (threadIdx.x == 0) {
     double sum = 0.0;
     for (int pass = 0; pass < 2; ++pass)
@@ -326,12 +331,15 @@ __global__ void k_batch_zoom_tables(float2 *arena, const ZoomTableJob *__restric
           h /= sum;
           double s, c;
           sincospi(2.0 * frac_mul(j.nu_N, (double)t), &s, &c);
-          arena[j.g_off + t] = make_float2((float)(h * c), (float)(h * s));
+          g[t] = make_double2(h * c, h * s);
         }
       }
   }
-  for (int m = threadIdx.x; m < j.LD; m += blockDim.x)
-    arena[j.ph_off + m] = unit_cycles(frac_mul(j.nu_N, (double)((int64_t)m * j.D)));
+  for (int m = threadIdx.x; m < j.LD; m += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * frac_mul(j.nu_N, (double)((int64_t)m * j.D)), &s, &c);
+    ph[m] = make_double2(c, s);
+  }
 }
 
 }  // namespace tz
@@ -562,8 +570,8 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
       zt.nu_c = 1.0 / (2.0 * (double)D);
       const double nuN = 0.5 * ((double)j.f1_hz + (double)j.f2_hz) / (double)j.fs_hz;
       zt.nu_N = nuN - floor(nuN);
-      zt.g_off = zj.g_off = take(T);
-      zt.ph_off = zj.ph_off = take(LD);
+      zt.g_off = zj.g_off = take(2 * (int64_t)T);  // double2 = two float2 slots
+      zt.ph_off = zj.ph_off = take(2 * LD);
       b->zjobs.push_back(zj);
       ztjobs.push_back(zt);
       p = zoom_phase(K, j.M);

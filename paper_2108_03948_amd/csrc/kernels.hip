@@ -156,131 +156,150 @@ __global__ void __launch_bounds__(Fft<FL>::NT)
 //
 // With Nh = N_fft/2 and z[m] = x[2m] + j x[2m+1] (m < ceil(N/2)), the
 // Nh-point FFT Z of z gives every bin of the real trace:
-//   X[k] = (Z[k] + conj Z[Nh-k])/2 - j W_{Nfft}^k (Z[k] - conj Z[Nh-k])/2,
-//   0 <= k <= Nh,   X[N_fft - k] = conj X[k]          (indices of Z mod Nh).
-// Z itself is P independent F-point FFTs (Nh = P F, F >= N/2):
+//   X[k] = (Z[k] + conj Z[Nh-k])/2 - j W_{Nfft}^k (Z[k] - conj Z[Nh-k])/2
+// for every k (indices of Z mod Nh, of W mod N_fft), and X[N_fft - k] =
+// conj X[k].  Z itself is P independent F-point FFTs (Nh = P F, F >= N/2):
 //   Z[P q + r] = FFT_F( z[m] W_{Nh}^{r m} )[q],
 // one per wavefront (wave r), so the whole spectrum of the trace sits in the
-// registers of one workgroup with no workgroup barrier during the FFTs.  It
-// is then staged through LDS in two halves, quarters {0,3} and {1,2} of Z (the
-// halves that pair k with Nh-k), and every output row is written as
-// contiguous runs, ascending for X[k] and descending for its mirror.
+// registers of one workgroup with no workgroup barrier during the FFTs.
+//
+// Z is staged through LDS in two halves that pair k with Nh - k: quarters
+// {0, 3}, then quarters {1, 2} plus the three neighbours their bins reach.
+// Lane l of a wave forms bins k, k+1 (k even) of a contiguous run of pairs
+// and writes them with one aligned 16-byte store; the mirror pair
+// (N_fft - k, N_fft - k + 1) = conj (X[k], X[k-1]) is aligned too, with
+// X[k-1] taken from lane l-1 (lane 63 of the previous step for lane 0).
+//
+// Persistent: each workgroup fills its twiddle tables once and then takes
+// traces b = blockIdx.x, + gridDim.x, ...; the samples of the next trace are
+// fetched into the idle FFT registers while the last half of the current
+// spectrum is written, and stores are never waited for at barriers.
 // ---------------------------------------------------------------------------
 template <int F, int P>
 struct PadWaveShape {
   using FF = WaveFft<F>;
   static constexpr int E = FF::E;
   static constexpr int NH = P * F;
-  static constexpr int STAGE = NH / 2 + 1;  // one half of Z plus the shared element Z[3Nh/4]
+  static constexpr int STAGE = NH / 2 + 3;  // half of Z plus three halo elements
   static constexpr int LDS_FFT = P * FF::window();
   static constexpr int LDS_STAGE = STAGE + STAGE / 16 + 1;
   static constexpr int LDS = LDS_FFT > LDS_STAGE ? LDS_FFT : LDS_STAGE;
   static_assert(E % 4 == 0, "quarters of Z must align with register slots");
+  static_assert((NH / 4) % (64 * P) == 0, "each wave takes whole 64-pair steps of one quarter");
 };
 
 template <int F, int P, int KIND>
 __global__ void __launch_bounds__(64 * P)
     k_fftpad_real(const void *__restrict__ x, int64_t xs, int64_t N, const float2 *__restrict__ root_h,
                   const float2 *__restrict__ root_f, const float2 *__restrict__ tw, float2 *__restrict__ X,
-                  int64_t os, int half) {
+                  int64_t os, int half, int64_t B) {
   using Sh = PadWaveShape<F, P>;
   using FF = typename Sh::FF;
   constexpr int E = Sh::E, NH = Sh::NH, NTH = 64 * P;
+  constexpr unsigned Q4 = NH / 4, NF = 2 * NH;
+  constexpr unsigned PPW = Q4 / P;  // pairs per wave and phase
+  constexpr int XB = KIND == 1 ? 8 : 4;
   __shared__ float2 lds[Sh::LDS];
   __shared__ float2 twl[F / 2];
   __shared__ float2 rtl[tw_lds_points<NH>()];
   __shared__ float2 rfl[tw_lds_points<2 * NH>()];
-  const unsigned tid = threadIdx.x;
-  const unsigned r = tid / 64, lane = tid % 64;
-  const int64_t b = blockIdx.x;
-  const TwHalf<F> twd = load_half_twiddles<F>(twl, tw, tid, NTH);
-  const TwLds rtd = load_twiddles<NH>(rtl, root_h, tid, NTH);
-  const TwLds rfd = load_twiddles<2 * NH>(rfl, root_f, tid, NTH);
-  __syncthreads();
+  const TwHalf<F> twd = load_half_twiddles<F>(twl, tw, threadIdx.x, NTH);
+  const TwLds rtd = load_twiddles<NH>(rtl, root_h, threadIdx.x, NTH);
+  const TwLds rfd = load_twiddles<2 * NH>(rfl, root_f, threadIdx.x, NTH);
 
-  // z[m] = x[2m] + j x[2m+1]; samples past N read as 0
-  const Rsrc rx = make_rsrc((const char *)x + b * xs * (KIND == 1 ? 8 : 4), (uint64_t)N * (KIND == 1 ? 8 : 4));
+  // raw samples (x[2m], x[2m+1]) of trace tb in input-slot order
   float2 v[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const unsigned m = lane + 64 * e;
-    const float2 zz = make_float2(ld_real<KIND>(rx, 2 * m), ld_real<KIND>(rx, 2 * m + 1));
-    v[FF::in_slot(e)] = cmul(zz, rtd(r * m));
-  }
-  FF::forward(v, lds + r * FF::window(), lane, twd);
-
-  constexpr unsigned Q4 = NH / 4;
-  const Rsrc rX = make_rsrc(X + b * os, (uint64_t)(half ? NH + 1 : 2 * NH) * 8);
-  // X[k] from Z[k] and Z[Nh-k] (staged at slots sk, sm)
-  auto bin = [&](unsigned k, unsigned sk, unsigned sm) {
-    const float2 a = lds[lds_idx(sk)];
-    const float2 c = cconj(lds[lds_idx(sm)]);
-    const float2 ev = cscale(cadd(a, c), 0.5f);
-    const float2 od = cscale(cmul_mj(csub(a, c)), 0.5f);
-    return cadd(ev, cmul(rfd(k), od));
-  };
-  using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rX, 0, 0, 0));
-  // bins k, k+1 with one 16-byte store, and their mirrors N_fft-k-1, N_fft-k
-  // with another (k = 0 and k + 1 = Nh have no mirror)
-  auto store_pair = [&](unsigned k, float2 x0, float2 x1) {
-    __builtin_amdgcn_raw_buffer_store_b128(
-        __builtin_bit_cast(U4, make_float4(x0.x, x0.y, x1.x, x1.y)), rX, (int)(8 * k), 0, 0);
-    if (!half) {
-      if (k == 0)
-        st_c64(cconj(x1), rX, 8 * (2 * NH - 1));
-      else if (k + 1 == NH)
-        st_c64(cconj(x0), rX, 8 * (2 * NH - k));
-      else
-        __builtin_amdgcn_raw_buffer_store_b128(
-            __builtin_bit_cast(U4, make_float4(x1.x, -x1.y, x0.x, -x0.y)), rX, (int)(8 * (2 * NH - k - 1)), 0, 0);
-    }
-  };
-  // two staging phases: A = quarters {0, 3}, B = quarters {1, 2}
-#pragma unroll
-  for (int ph = 0; ph < 2; ++ph) {
-    __syncthreads();  // FFT windows / previous phase reads are done
+  auto fetch = [&](int64_t tb, unsigned lane_) {
+    const Rsrc rx = make_rsrc((const char *)x + tb * xs * XB, (uint64_t)N * XB);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int quarter = (4 * e) / E;
-      const unsigned q = lane + 64 * e;
-      const unsigned k = P * q + r;
-      const float2 z = v[FF::out_slot(e)];
-      if (ph == 0) {
-        if (quarter == 0) lds[lds_idx(k)] = z;
-        if (quarter == 3) lds[lds_idx(k - NH / 2)] = z;
-      } else {
-        if (quarter == 1 || quarter == 2) lds[lds_idx(k - Q4)] = z;
-        if (quarter == 3 && k == 3 * Q4) lds[lds_idx(NH / 2)] = z;
-      }
+      const unsigned m = lane_ + 64 * e;  // samples past N read as 0
+      v[FF::in_slot(e)] = make_float2(ld_real<KIND>(rx, 2 * m), ld_real<KIND>(rx, 2 * m + 1));
     }
-    __syncthreads();
-    if (ph == 0) {
-      // A: k in [0, Nh/4) U (3Nh/4, Nh], as Nh/4 pairs (k, k+1)
-      for (unsigned i = 2 * tid; i < NH / 2; i += 2 * NTH) {
-        const unsigned k = (i < Q4) ? i : i + NH / 2 + 1;
-        unsigned sk[2], sm[2];
+  };
+  if ((int64_t)blockIdx.x < B) fetch(blockIdx.x, threadIdx.x % 64);
+
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    __syncthreads();  // tables filled / previous trace's staging reads done
+    // thread indices through an opaque zero: everything derived from them
+    // (twiddles, LDS addresses) is formed per trace instead of being hoisted
+    // out of the loop and kept live in registers across it
+    const unsigned tid = threadIdx.x + opaque_zero();
+    const unsigned r = tid / 64, lane = tid % 64;
 #pragma unroll
-        for (int d = 0; d < 2; ++d) {
-          const unsigned kz = (k + d) % NH, mz = (NH - (k + d)) % NH;
-          sk[d] = kz < Q4 ? kz : kz - NH / 2;
-          sm[d] = mz < Q4 ? mz : mz - NH / 2;
-        }
-        store_pair(k, bin(k, sk[0], sm[0]), bin(k + 1, sk[1], sm[1]));
-      }
-    } else {
-      // B: k in [Nh/4, 3Nh/4) as pairs, then the single bin 3Nh/4
-      for (unsigned i = 2 * tid; i < NH / 2; i += 2 * NTH) {
-        const unsigned k = Q4 + i;
-        store_pair(k, bin(k, k - Q4, NH - k - Q4), bin(k + 1, k + 1 - Q4, NH - k - 1 - Q4));
-      }
-      if (tid == 0) {
-        const unsigned k = 3 * Q4;
-        const float2 xk = bin(k, NH / 2, Q4 - Q4);
-        st_c64(xk, rX, 8 * k);
-        if (!half) st_c64(cconj(xk), rX, 8 * (2 * NH - k));
-      }
+    for (int e = 0; e < E; ++e) {
+      const unsigned m = lane + 64 * e;
+      v[FF::in_slot(e)] = cmul(v[FF::in_slot(e)], rtd(r * m));
     }
-  }
+    FF::forward(v, lds + r * FF::window(), lane, twd);
+
+    const Rsrc rX = make_rsrc(X + b * os, (uint64_t)(half ? NH + 1 : NF) * 8);
+    using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rX, 0, 0, 0));
+    auto st2 = [&](unsigned idx, float2 a, float2 c) {
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, make_float4(a.x, a.y, c.x, c.y)), rX,
+                                             (int)(8 * idx), 0, 0);
+    };
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+      // LDS slot of Z[z] in this phase
+      auto slot = [&](unsigned z) -> unsigned {
+        if (ph == 0) return z < Q4 ? z : z - NH / 2;
+        return z == Q4 - 1 ? NH / 2 + 2 : z - Q4;
+      };
+      // X[k], 0 <= k < N_fft, from the staged half of Z
+      auto bin = [&](unsigned k) {
+        const unsigned kz = k & (NH - 1), mz = (NH - kz) & (NH - 1);
+        const float2 a = lds[lds_idx(slot(kz))];
+        const float2 c = cconj(lds[lds_idx(slot(mz))]);
+        const float2 ev = cscale(cadd(a, c), 0.5f);
+        const float2 od = cscale(cmul_mj(csub(a, c)), 0.5f);
+        return cadd(ev, cmul(rfd(k), od));
+      };
+      // bins k, k+1 (k even): direct pair, and the mirror pair conj(X[k], X[k-1])
+      auto emit = [&](unsigned k, float2 x0, float2 x1, float2 xm) {
+        if (half && k == NH) {
+          st_c64(x0, rX, 8 * k);
+          return;
+        }
+        st2(k, x0, x1);
+        if (!half && k >= 2 && k < NH) st2(NF - k, cconj(x0), cconj(xm));
+      };
+      __syncthreads();  // FFT windows / previous phase's reads are done
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int quarter = (4 * e) / E;
+        const unsigned k = P * (lane + 64 * e) + r;
+        const float2 z = v[FF::out_slot(e)];
+        if (ph == 0) {
+          if (quarter == 0 || quarter == 3) lds[lds_idx(slot(k))] = z;
+        } else {
+          if (quarter == 1 || quarter == 2 || (quarter == 3 && k <= 3 * Q4 + 1) ||
+              (quarter == 0 && k == Q4 - 1))
+            lds[lds_idx(slot(k))] = z;
+        }
+      }
+      __syncthreads();
+      if (ph == 1 && b + gridDim.x < B) fetch(b + gridDim.x, lane);  // lands while this half is written
+      // wave r takes pairs [r PPW, (r+1) PPW) of this phase in steps of 64:
+      // phase 0: k = 2p (p < Q4/2), k = 3Q4 + 2 + 2(p - Q4/2); phase 1: k = Q4 + 2p
+      float2 carry = make_float2(0.f, 0.f);
+      for (unsigned it = 0; it < PPW / 64; ++it) {
+        const unsigned p = r * PPW + 64 * it + lane;
+        const unsigned k = ph == 0 ? (p < Q4 / 2 ? 2 * p : 3 * Q4 + 2 + 2 * (p - Q4 / 2)) : Q4 + 2 * p;
+        const float2 x0 = bin(k), x1 = bin(k + 1);
+        float2 xm = make_float2(__shfl_up(x1.x, 1), __shfl_up(x1.y, 1));
+        if (it == 0) {
+          const float2 first = bin((k + NF - 1) & (NF - 1));
+          if (lane == 0) xm = first;
+        } else if (lane == 0) {
+          xm = carry;
+        }
+        carry = make_float2(__shfl(x1.x, 63), __shfl(x1.y, 63));
+        emit(k, x0, x1, xm);
+      }
+      if (ph == 1 && tid == 0) emit(3 * Q4, bin(3 * Q4), bin(3 * Q4 + 1), bin(3 * Q4 - 1));
+    }
+  }  // traces
 }
 
 // ---------------------------------------------------------------------------
@@ -423,15 +442,35 @@ hipError_t launch_fftpad(const PadLaunch &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// workgroups that fill the device once: CUs x resident workgroups per CU,
+// at most `work` (queried once per device and kernel)
+template <class K>
+static unsigned persistent_grid(K kernel, int threads, int64_t work) {
+  static int cache[64];
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int &slots = cache[dev & 63];
+  if (!slots) {
+    int ncu = 0, occ = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0);
+    slots = (ncu > 0 ? ncu : 1) * (occ > 0 ? occ : 1);
+  }
+  return (unsigned)(work < slots ? work : slots);
+}
+
 template <int F, int P>
 static void pad_real_launch(const PadRealLaunch &a, hipStream_t s) {
-  const dim3 grid((unsigned)a.B), block(64 * P);
-  if (a.in_kind == 1)
+  const dim3 block(64 * P);
+  if (a.in_kind == 1) {
+    const dim3 grid(persistent_grid(k_fftpad_real<F, P, 1>, 64 * P, a.B));
     hipLaunchKernelGGL((k_fftpad_real<F, P, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.root_h, a.root_f, a.tw,
-                       a.X, a.os, a.half);
-  else
+                       a.X, a.os, a.half, a.B);
+  } else {
+    const dim3 grid(persistent_grid(k_fftpad_real<F, P, 0>, 64 * P, a.B));
     hipLaunchKernelGGL((k_fftpad_real<F, P, 0>), grid, block, 0, s, a.x, a.xs, a.N, a.root_h, a.root_f, a.tw,
-                       a.X, a.os, a.half);
+                       a.X, a.os, a.half, a.B);
+  }
 }
 
 // (F, P) pairs with a compiled whole-spectrum kernel
