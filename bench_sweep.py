@@ -1,0 +1,141 @@
+"""Resolution sweep: the paper's timing comparison (Section 4, Fig. 11) on one
+MI355X.
+
+For a THz trace of N = 500 samples at T_s = 100 fs (the measured trace of
+Section 3.2; a synthetic pulse here) the plotting resolution df runs from
+20 GHz down to 0.5 GHz in 0.5 GHz steps.  At each df:
+
+  fft_zeropad  N_fft = round(f_s/df) (eq. (3)), i.e. N_fft - N zeros (eq. (5))
+  czt          band 0 - 2.5 THz, M = round((f2 - f1) N_fft / f_s) bins (eq. (25))
+  zoom_fft     same band and M, f_N = 1.25 THz, D = floor(f_s / (1.25 (f2 - f1))),
+               63-tap low-pass; short DFT length K = round(M f_s / (D (f2 - f1)))
+
+Each method is timed (HIP events on the launch stream, plans built before the
+timed region) for one trace, as the paper does, and for a batch of 8192
+traces, and normalised to its own time at 20 GHz; the dashed curves of the
+paper's figure (theoretical cost) are given as L log2 L of the FFTs each
+method runs, normalised the same way.
+
+  python bench_sweep.py [--reps 200] [--batch 8192] [--out FILE.md]
+
+Prints one JSON line per df and, with --out, writes a markdown table.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FS = 10e12            # T_s = 100 fs
+N = 500
+F1, F2 = 0.0, 2.5e12
+TAPS = 63
+
+
+def sweep_points():
+    """df in Hz from 20 GHz down to 0.5 GHz in 0.5 GHz steps."""
+    return [(40 - i) * 0.5e9 for i in range(40)]
+
+
+def shapes(tz, df):
+    """Transform sizes the sweep uses at resolution df."""
+    nfft = int(round(FS / df))
+    M = tz.czt_points_for_resolution(FS, F1, F2, nfft)
+    D = max(1, int(math.floor(FS / (1.25 * (F2 - F1)))))
+    K = tz.zoom_short_length(FS, F1, F2, M, D)
+    return {"df_hz": df, "n_fft": nfft, "n_zeros": nfft - N, "M": M, "D": D, "K": K}
+
+
+def theory(tz, s):
+    """FFT work of each method: sum of L log2 L over the FFTs it runs."""
+    def c(L):
+        return L * math.log2(L)
+    L_czt, _ = tz.czt_plan_shape(N, s["M"])
+    LD = -(-N // s["D"])
+    L_zoom, _ = tz.czt_plan_shape(LD, s["M"])
+    return {"fft": c(s["n_fft"]), "czt": 2 * c(L_czt), "zoom": 2 * c(L_zoom)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=200, help="timed calls per point (single trace)")
+    ap.add_argument("--batch", type=int, default=8192, help="traces in the batched measurement")
+    ap.add_argument("--out", default=None, help="also write a markdown table here")
+    args = ap.parse_args()
+
+    import numpy as np
+    import torch
+
+    import paper_2108_03948_amd as tz
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    x1 = torch.from_numpy(synth.single_trace(N=N, fs=FS, t0=15e-12).astype(np.float32)).to(dev).reshape(1, N)
+    xb = torch.from_numpy(synth.pairs(args.batch // 2, N=N, fs=FS, t0=15e-12)).to(dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3  # us
+
+    rows = []
+    for df in sweep_points():
+        s = shapes(tz, df)
+        W, A = tz.czt_band(FS, F1, F2, s["M"])
+        out = {}
+        for tag, x, reps in (("single", x1, args.reps), ("batch", xb, max(3, args.reps // 20))):
+            Xf = torch.empty((x.shape[0], s["n_fft"]), dtype=torch.complex64, device=dev)
+            Xc = torch.empty((x.shape[0], s["M"]), dtype=torch.complex64, device=dev)
+            Xz = torch.empty_like(Xc)
+            out[tag] = {
+                "fft": timed(lambda: tz.fft_zeropad(x, s["n_zeros"], out=Xf, stream=stream), reps),
+                "czt": timed(lambda: tz.czt(x, s["M"], W, A, out=Xc, stream=stream), reps),
+                "zoom": timed(lambda: tz.zoom_fft(x, FS, F1, F2, s["M"], s["D"], taps=TAPS, out=Xz,
+                                                  stream=stream), reps),
+            }
+            del Xf, Xc, Xz
+        row = dict(s, us=out, theory=theory(tz, s))
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+
+    base = rows[0]
+    for r in rows:
+        r["rel"] = {tag: {m: r["us"][tag][m] / base["us"][tag][m] for m in ("fft", "czt", "zoom")}
+                    for tag in ("single", "batch")}
+        r["rel_theory"] = {m: r["theory"][m] / base["theory"][m] for m in ("fft", "czt", "zoom")}
+    if args.out:
+        cmd = "python bench_sweep.py " + " ".join(sys.argv[1:])
+        lines = ["# Resolution sweep: time per call vs plotting resolution", "",
+                 f"Command:\n\n    {cmd}\n",
+                 f"N = {N} samples at f_s = {FS / 1e12:g} THz, band {F1 / 1e12:g}-{F2 / 1e12:g} THz, "
+                 f"zoom {TAPS} taps; single trace ({args.reps} calls per point) and "
+                 f"{args.batch} traces; times in microseconds, rel = time / time at 20 GHz.", "",
+                 "| df (GHz) | N_fft | M | D | K | fft 1 | czt 1 | zoom 1 | fft B | czt B | zoom B | "
+                 "rel fft B | rel czt B | rel zoom B | theory fft | theory czt | theory zoom |",
+                 "|" + "---|" * 17]
+        for r in rows:
+            u1, ub, rb, th = r["us"]["single"], r["us"]["batch"], r["rel"]["batch"], r["rel_theory"]
+            lines.append(f"| {r['df_hz'] / 1e9:.1f} | {r['n_fft']} | {r['M']} | {r['D']} | {r['K']} | "
+                         f"{u1['fft']:.1f} | {u1['czt']:.1f} | {u1['zoom']:.1f} | "
+                         f"{ub['fft']:.1f} | {ub['czt']:.1f} | {ub['zoom']:.1f} | "
+                         f"{rb['fft']:.2f} | {rb['czt']:.2f} | {rb['zoom']:.2f} | "
+                         f"{th['fft']:.2f} | {th['czt']:.2f} | {th['zoom']:.2f} |")
+        with open(args.out, "w") as f:
+            f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -317,38 +317,65 @@ __global__ void __launch_bounds__(64 * P)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int zpad(int i) { return i + (i >> 6); }
 
-template <int KIND>
-__global__ void __launch_bounds__(256)
+constexpr int kZoomThreads = 256;
+
+// S = split waves per output: 256/S outputs per workgroup (one per lane of S
+// groups); group s sums the taps t = s mod S, so a long filter runs as S
+// shorter dependent chains.
+template <int KIND, int S>
+__global__ void __launch_bounds__(kZoomThreads)
     k_zoom_front(const void *__restrict__ x, int64_t xs, int64_t N, int64_t D, int64_t LD, int T,
                  const double2 *__restrict__ g, const double2 *__restrict__ ph, float2 *__restrict__ u,
                  int64_t bpt, int opb) {
   using XT = typename std::conditional<KIND == 1, double, float>::type;
   extern __shared__ double2 zsm[];
   double2 *gl = zsm;
-  XT *xl = (XT *)(zsm + T);
+  double2 *part = zsm + T;  // [S][256 / S] partial sums
+  XT *xl = (XT *)(part + kZoomThreads);
+  constexpr int nout = kZoomThreads / S;
   const int64_t b = blockIdx.x / bpt;
   const int64_t m0 = (blockIdx.x % bpt) * opb;
   const int64_t n0 = m0 * D - (T - 1);
   const int span = (opb - 1) * (int)D + T;
-  const XT *xb = (const XT *)x + b * xs;
   for (int i = threadIdx.x; i < T; i += blockDim.x) gl[i] = g[i];
+  // unconditional buffer loads: n >= N is past the extent, and n < 0 wraps to
+  // an offset above 2^31 (the host keeps N * sizeof(XT) below that), so both
+  // read as 0 and the loads of a thread can all be in flight at once
+  const Rsrc rx = make_rsrc((const XT *)x + b * xs, (uint64_t)N * sizeof(XT));
+#pragma unroll 8
   for (int i = threadIdx.x; i < span; i += blockDim.x) {
-    const int64_t n = n0 + i;
-    xl[zpad(i)] = (n >= 0 && n < N) ? xb[n] : (XT)0;
+    const unsigned off = (unsigned)((n0 + i) * (int64_t)sizeof(XT));
+    if constexpr (KIND == 1)
+      xl[zpad(i)] = ld_f64(rx, off);
+    else
+      xl[zpad(i)] = ld_f32(rx, off);
   }
   __syncthreads();
-  const int j = threadIdx.x;
-  const int64_t m = m0 + j;
-  if (j >= opb || m >= LD) return;
-  const int top = j * (int)D + T - 1;  // tile index of x[mD]
+  // thread j of group s: output m0 + j, taps t = s, s + S, ...; the lanes of
+  // a wave read stride-D samples, spread over the banks by the pad
+  const int j = threadIdx.x % nout, sidx = threadIdx.x / nout;
+  const int top = j * (int)D + T - 1;  // tile index of x[(m0 + j) D]
   double ar = 0.0, ai = 0.0;
-  for (int t = 0; t < T; ++t) {
-    const double xv = (double)xl[zpad(top - t)];
-    ar = fma(gl[t].x, xv, ar);
-    ai = fma(gl[t].y, xv, ai);
+  if (j < opb) {
+#pragma unroll 4
+    for (int t = sidx; t < T; t += S) {
+      const double xv = (double)xl[zpad(top - t)];
+      ar = fma(gl[t].x, xv, ar);
+      ai = fma(gl[t].y, xv, ai);
+    }
+  }
+  part[threadIdx.x] = make_double2(ar, ai);
+  __syncthreads();
+  const int64_t m = m0 + threadIdx.x;
+  if ((int)threadIdx.x >= opb || m >= LD) return;
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    sr += part[q * nout + threadIdx.x].x;
+    si += part[q * nout + threadIdx.x].y;
   }
   const double2 p = ph[m];
-  u[b * LD + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));
+  u[b * LD + m] = make_float2((float)(p.x * sr - p.y * si), (float)(p.x * si + p.y * sr));
 }
 
 // same sums with x and the taps read from global memory (filters too long
@@ -493,27 +520,31 @@ hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s) {
 }
 
 hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
-  // LDS tile: T FP64 taps plus the samples of opb outputs, within 64 KB
+  // LDS tile: T FP64 taps, the partial sums, and the samples of opb outputs,
+  // within 64 KB
   constexpr int64_t kTileBytes = 64 * 1024;
   const int64_t xb = a.in_kind == 1 ? 8 : 4;
-  const int64_t tap_bytes = 16 * (int64_t)a.T;
+  const int64_t fixed = 16 * (int64_t)a.T + 16 * kZoomThreads;
+  const int S = a.T < 128 ? 1 : (a.T < 256 ? 2 : 4);
   int64_t opb = 0;
-  if (tap_bytes + xb * (a.T + a.T / 64 + 1) <= kTileBytes) {
-    const int64_t xmax = (kTileBytes - tap_bytes) / xb * 64 / 65 - 1;  // samples, pads included
+  if (fixed + xb * (a.T + a.T / 64 + 1) <= kTileBytes && a.N * xb < ((int64_t)1 << 31)) {
+    const int64_t xmax = (kTileBytes - fixed) / xb * 64 / 65 - 1;  // samples, pads included
     opb = (xmax - a.T) / a.D + 1;
-    if (opb > 256) opb = 256;
+    if (opb > kZoomThreads / S) opb = kZoomThreads / S;
   }
   if (opb >= 1) {
     const int64_t span = (opb - 1) * a.D + a.T;
-    const size_t shm = (size_t)(tap_bytes + xb * (span + span / 64 + 1));
+    const size_t shm = (size_t)(fixed + xb * (span + span / 64 + 1));
     const int64_t bpt = (a.LD + opb - 1) / opb;
-    const dim3 grid((unsigned)(a.B * bpt)), block((unsigned)((opb + 63) / 64 * 64));
+    const dim3 grid((unsigned)(a.B * bpt)), block(kZoomThreads);
+    auto go = [&](auto kernel) {
+      hipLaunchKernelGGL(kernel, grid, block, shm, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph, a.u, bpt,
+                         (int)opb);
+    };
     if (a.in_kind == 1)
-      hipLaunchKernelGGL((k_zoom_front<1>), grid, block, shm, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph, a.u,
-                         bpt, (int)opb);
+      S == 1 ? go(k_zoom_front<1, 1>) : (S == 2 ? go(k_zoom_front<1, 2>) : go(k_zoom_front<1, 4>));
     else
-      hipLaunchKernelGGL((k_zoom_front<0>), grid, block, shm, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph, a.u,
-                         bpt, (int)opb);
+      S == 1 ? go(k_zoom_front<0, 1>) : (S == 2 ? go(k_zoom_front<0, 2>) : go(k_zoom_front<0, 4>));
     return hipGetLastError();
   }
   const int64_t bpt = (a.LD + 255) / 256;

@@ -155,3 +155,23 @@ def test_binding_refuses_cpu_tensors(tz):
     import torch
     with pytest.raises(TypeError):
         tz.czt(torch.zeros(4, 16), 8, 1.0, 1.0)
+
+
+def test_resolution_sweep_shapes(tz):
+    """The sweep of the paper's timing comparison (Section 4): N = 500 samples at
+    T_s = 100 fs give the 20 GHz FFT resolution of Section 3.2 with no zeros;
+    each 0.5 GHz step sets N_fft from eq. (3), M from eq. (25) and K from the
+    zoom grid."""
+    import bench_sweep as bs
+    pts = bs.sweep_points()
+    assert len(pts) == 40 and pts[0] == 20e9 and pts[-1] == 0.5e9
+    assert all(abs((a - b) - 0.5e9) < 1 for a, b in zip(pts, pts[1:]))
+    s0, s1 = bs.shapes(tz, pts[0]), bs.shapes(tz, pts[-1])
+    assert (s0["n_fft"], s0["n_zeros"], s0["M"]) == (500, 0, 125)
+    assert (s1["n_fft"], s1["n_zeros"], s1["M"]) == (20000, 19500, 5000)
+    assert s0["D"] == s1["D"] == 3
+    assert s0["K"] == 167 and s1["K"] == 6667
+    # eq. (4): the zero count of each point reaches its resolution from 20 GHz
+    for df in pts[1:]:
+        s = bs.shapes(tz, df)
+        assert abs(bs.FS / s["n_fft"] - df) <= bs.FS / s["n_fft"] ** 2
