@@ -168,9 +168,21 @@ int blue_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb
                int64_t *Llong) {
   const bool seg_ok = czt_shape(N, M, L, Ns, nseg, Mb, nblk);
   if (seg_ok && *nseg == 1 && *nblk == 1) return 1;
+  // smallest four-step length: a power of two (>= 2^17) or 5 * 2^a
   int64_t Lb = next_pow2(N + M - 1);
   if (Lb < ((int64_t)1 << 17)) Lb = (int64_t)1 << 17;
-  const bool long_ok = long_shape(Lb, L1);
+  int l1p = 0, l15 = 0;
+  bool long_ok = long_shape(Lb, &l1p);
+  *L1 = l1p;
+  for (int64_t L5 = (int64_t)320 * 256; L5 <= (int64_t)320 * kMaxL; L5 *= 2)
+    if (L5 >= N + M - 1) {
+      if (long_shape(L5, &l15) && (!long_ok || L5 < Lb)) {
+        Lb = L5;
+        *L1 = l15;
+        long_ok = true;
+      }
+      break;
+    }
   if (long_ok && (!seg_ok || (int64_t)*nseg * *nblk * kMaxL > Lb)) {
     *Llong = Lb;
     return 0;

@@ -141,6 +141,32 @@ struct Dft<4> {
   }
 };
 
+// 5-point DFT: with t1 = x1 + x4, t2 = x2 + x3, t3 = x1 - x4, t4 = x2 - x3,
+//   X1,4 = x0 + c1 t1 + c2 t2 -/+ j (s1 t3 + s2 t4),
+//   X2,3 = x0 + c2 t1 + c1 t2 -/+ j (s2 t3 - s1 t4),
+// c_m = cos(2 pi m/5), s_m = sin(2 pi m/5)
+template <>
+struct Dft<5> {
+  template <int S>
+  __device__ __forceinline__ static void run(float2 *v) {
+    constexpr CS w1 = unit_root(1, 5), w2 = unit_root(2, 5);
+    constexpr float c1 = (float)w1.c, s1 = (float)w1.s, c2 = (float)w2.c, s2 = (float)w2.s;
+    const float2 x0 = v[0];
+    const float2 t1 = cadd(v[S], v[4 * S]), t2 = cadd(v[2 * S], v[3 * S]);
+    const float2 t3 = csub(v[S], v[4 * S]), t4 = csub(v[2 * S], v[3 * S]);
+    const float2 a1 = make_float2(fmaf(c2, t2.x, fmaf(c1, t1.x, x0.x)), fmaf(c2, t2.y, fmaf(c1, t1.y, x0.y)));
+    const float2 a2 = make_float2(fmaf(c1, t2.x, fmaf(c2, t1.x, x0.x)), fmaf(c1, t2.y, fmaf(c2, t1.y, x0.y)));
+    // b1 = s1 t3 + s2 t4, b2 = s2 t3 - s1 t4; -j b = (b.y, -b.x)
+    const float2 b1 = make_float2(fmaf(s1, t3.x, s2 * t4.x), fmaf(s1, t3.y, s2 * t4.y));
+    const float2 b2 = make_float2(fmaf(s2, t3.x, -s1 * t4.x), fmaf(s2, t3.y, -s1 * t4.y));
+    v[0] = cadd(x0, cadd(t1, t2));
+    v[S] = cadd(a1, cmul_mj(b1));
+    v[4 * S] = csub(a1, cmul_mj(b1));
+    v[2 * S] = cadd(a2, cmul_mj(b2));
+    v[3 * S] = csub(a2, cmul_mj(b2));
+  }
+};
+
 // Generic R = R1 * R2 (R1 = 4 when possible, else 2), decimation in time by
 // index mapping: X[k1 + R1 k2] = sum_{n2} W_R2^{n2 k2} W_R^{n2 k1}
 //                                 sum_{n1} v[R2 n1 + n2] W_R1^{n1 k1}.
@@ -202,6 +228,7 @@ struct Radices {
 template <int L>
 struct FftShape;
 // L, threads, elements per thread, radices
+template <> struct FftShape<320>   { static constexpr int NT = 16;  using Plan = Radices<5, 4, 4, 4>; };
 template <> struct FftShape<256>   { static constexpr int NT = 64;  using Plan = Radices<4, 4, 4, 4>; };
 template <> struct FftShape<512>   { static constexpr int NT = 64;  using Plan = Radices<8, 8, 8>; };
 template <> struct FftShape<1024>  { static constexpr int NT = 64;  using Plan = Radices<16, 16, 4>; };
@@ -316,7 +343,7 @@ __device__ __forceinline__ void apply_twiddles(float2 *v, const TwHalf<L> &tw, u
 
 template <int R>
 __device__ __forceinline__ void apply_twiddles(float2 *v, const TwLds &tw, unsigned base) {
-  if constexpr (R <= 4) {
+  if constexpr (R <= 4 || R % 4 != 0) {
 #pragma unroll
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw(base * r));
   } else {

@@ -1,6 +1,7 @@
 // Bluestein CZT for long traces (N + M - 1 > 16384): the length-L FFTs of
-// eq. (15) are split four-step, L = L1 * L2, and run as three kernels per
-// chunk of traces with one L-point workspace per trace.
+// eq. (15) are split four-step, L = L1 * L2 (L1 = 320 = 5 * 4^3, 512 or 1024;
+// L2 a power of two), and run as three kernels per chunk of traces with one
+// L-point workspace per trace.
 //
 // With n = n1 L2 + n2 and k = k1 + L1 k2 (n1, k1 < L1; n2, k2 < L2),
 //   FFT_L(y)[k1 + L1 k2] = sum_n2 W_L2^{n2 k2} W_L^{n2 k1} sum_n1 y[n1 L2 + n2] W_L1^{n1 k1}.
@@ -234,7 +235,12 @@ __global__ void __launch_bounds__(ColFft<L1>::NT)
 // host side
 // ---------------------------------------------------------------------------
 bool long_shape(int64_t L, int *L1) {
-  if (L < (int64_t)512 * 256 || L > (int64_t)1024 * kMaxL || (L & (L - 1))) return false;
+  auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
+  if (L % 320 == 0 && pow2(L / 320) && L / 320 >= 256 && L / 320 <= kMaxL) {
+    *L1 = 320;  // L = 5 * 2^a
+    return true;
+  }
+  if (L < (int64_t)512 * 256 || L > (int64_t)1024 * kMaxL || !pow2(L)) return false;
   *L1 = (L <= (int64_t)512 * kMaxL) ? 512 : 1024;
   return true;
 }
@@ -305,6 +311,7 @@ static hipError_t run_chunks(const LongLaunch &a, hipStream_t s) {
 }
 
 hipError_t launch_czt_long(const LongLaunch &a, hipStream_t s) {
+  if (a.L1 == 320 && a.L2 >= 256 && a.L2 <= kMaxL) return run_chunks<320>(a, s);
   if (a.L1 == 512 && a.L2 >= 256 && a.L2 <= kMaxL) return run_chunks<512>(a, s);
   if (a.L1 == 1024 && a.L2 >= 256 && a.L2 <= kMaxL) return run_chunks<1024>(a, s);
   return hipErrorInvalidValue;

@@ -103,9 +103,11 @@ def test_czt_plan_shape(tz):
     L, blocks = tz.czt_plan_shape(16384, 8192)
     assert L == 16384 and blocks > 1
     # long traces: one four-step FFT pair of length next_pow2(N + M - 1)
-    assert tz.czt_plan_shape(1 << 20, 1 << 18) == (1 << 21, 1)
-    assert tz.czt_plan_shape(16384, 1 << 18) == (1 << 19, 1)
-    assert tz.czt_plan_shape(40000, 30000) == (1 << 17, 1)
+    # (power of two or 5 * 2^a, whichever is smaller)
+    assert tz.czt_plan_shape(1 << 20, 1 << 18) == (5 << 18, 1)
+    assert tz.czt_plan_shape(16384, 1 << 18) == (5 << 16, 1)
+    assert tz.czt_plan_shape(40000, 30000) == (5 << 14, 1)
+    assert tz.czt_plan_shape(70001, 60000) == (1 << 17, 1)
     with pytest.raises(tz.ThzError):
         tz.czt_plan_shape(1 << 24, 2)
 
