@@ -326,7 +326,7 @@ template <int KIND, int S>
 __global__ void __launch_bounds__(kZoomThreads)
     k_zoom_front(const void *__restrict__ x, int64_t xs, int64_t N, int64_t D, int64_t LD, int T,
                  const double2 *__restrict__ g, const double2 *__restrict__ ph, float2 *__restrict__ u,
-                 int64_t bpt, int opb) {
+                 int64_t bpt, int opb, int vec4) {
   using XT = typename std::conditional<KIND == 1, double, float>::type;
   extern __shared__ double2 zsm[];
   double2 *gl = zsm;
@@ -342,13 +342,38 @@ __global__ void __launch_bounds__(kZoomThreads)
   // an offset above 2^31 (the host keeps N * sizeof(XT) below that), so both
   // read as 0 and the loads of a thread can all be in flight at once
   const Rsrc rx = make_rsrc((const XT *)x + b * xs, (uint64_t)N * sizeof(XT));
+  if (KIND == 0 && vec4) {
+    // 16-byte loads of 4 samples from a start floored to a multiple of 4: each
+    // load lies wholly before 0, wholly inside [0, N) or wholly past N, except
+    // the one holding sample N (when N % 4 != 0), loaded sample by sample
+    const int64_t n0a = n0 & ~(int64_t)3;
+    const int nq = (int)((n0 + span - n0a + 3) >> 2);
+    using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rx, 0, 0, 0));
+#pragma unroll 4
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+      const int64_t sn = n0a + 4 * q;
+      float4 w;
+      if (sn < 0 || sn >= N || sn + 3 < N) {
+        w = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(unsigned)(sn * 4), 0, 0));
+      } else {
+        w = make_float4(ld_f32(rx, (unsigned)(sn * 4)), ld_f32(rx, (unsigned)(sn * 4 + 4)),
+                        ld_f32(rx, (unsigned)(sn * 4 + 8)), ld_f32(rx, (unsigned)(sn * 4 + 12)));
+      }
+      const int i0 = (int)(sn - n0);  // tile index of sample sn (may be < 0 for the first load)
+      const float e4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (i0 + c >= 0 && i0 + c < span) xl[zpad(i0 + c)] = (XT)e4[c];
+    }
+  } else {
 #pragma unroll 8
-  for (int i = threadIdx.x; i < span; i += blockDim.x) {
-    const unsigned off = (unsigned)((n0 + i) * (int64_t)sizeof(XT));
-    if constexpr (KIND == 1)
-      xl[zpad(i)] = ld_f64(rx, off);
-    else
-      xl[zpad(i)] = ld_f32(rx, off);
+    for (int i = threadIdx.x; i < span; i += blockDim.x) {
+      const unsigned off = (unsigned)((n0 + i) * (int64_t)sizeof(XT));
+      if constexpr (KIND == 1)
+        xl[zpad(i)] = ld_f64(rx, off);
+      else
+        xl[zpad(i)] = ld_f32(rx, off);
+    }
   }
   __syncthreads();
   // thread j of group s: output m0 + j, taps t = s, s + S, ...; the lanes of
@@ -537,9 +562,11 @@ hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
     const size_t shm = (size_t)(fixed + xb * (span + span / 64 + 1));
     const int64_t bpt = (a.LD + opb - 1) / opb;
     const dim3 grid((unsigned)(a.B * bpt)), block(kZoomThreads);
+    // 16-byte tile loads when every trace starts on a 16-byte boundary
+    const int vec4 = (a.in_kind == 0 && ((uintptr_t)a.x & 15) == 0 && ((a.xs * 4) & 15) == 0) ? 1 : 0;
     auto go = [&](auto kernel) {
       hipLaunchKernelGGL(kernel, grid, block, shm, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph, a.u, bpt,
-                         (int)opb);
+                         (int)opb, vec4);
     };
     if (a.in_kind == 1)
       S == 1 ? go(k_zoom_front<1, 1>) : (S == 2 ? go(k_zoom_front<1, 2>) : go(k_zoom_front<1, 4>));

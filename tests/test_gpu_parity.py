@@ -152,6 +152,20 @@ def test_zoom_shapes(tz, dev, orc, N, M, D, T, band):
     assert_close(Z, orc.zoom_fft(x.astype(np.float64), fs, f1, f2, M, D, taps=T), what="zoom")
 
 
+@pytest.mark.parametrize("N,D,T", [(1001, 6, 63), (1003, 64, 255), (4097, 3, 130), (5, 2, 63)])
+def test_zoom_padded_rows(tz, dev, orc, N, D, T):
+    """Rows on 16-byte boundaries (stride a multiple of 4 samples) with N % 4 != 0:
+    the front end's wide loads, including the one that holds sample N."""
+    rng = np.random.default_rng(N + D)
+    stride = (N + 3) // 4 * 4 + 4
+    big = rng.standard_normal((3, stride)).astype(np.float32)
+    xd = to_dev(big, dev)[:, :N]
+    fs, f1, f2, M = 20e12, 0.3e12, 1.1e12, 300
+    say(f"case: zoom padded rows N={N} stride={stride} D={D} T={T}")
+    Z = tz.zoom_fft(xd, fs, f1, f2, M, D, taps=T).cpu().numpy()
+    assert_close(Z, orc.zoom_fft(big[:, :N].astype(np.float64), fs, f1, f2, M, D, taps=T), what="zoom padded")
+
+
 def test_strides_and_fp64_input(tz, dev, orc):
     import torch
     rng = np.random.default_rng(3)
