@@ -180,7 +180,7 @@ struct PadWaveShape {
   using FF = WaveFft<F>;
   static constexpr int E = FF::E;
   static constexpr int NH = P * F;
-  static constexpr int STAGE = NH / 2 + 3;  // half of Z plus three halo elements
+  static constexpr int STAGE = NH / 2 + 4;  // half of Z, its neighbours and wrap copies, slots from 1
   static constexpr int LDS_FFT = P * FF::window();
   static constexpr int LDS_STAGE = STAGE + STAGE / 16 + 1;
   static constexpr int LDS = LDS_FFT > LDS_STAGE ? LDS_FFT : LDS_STAGE;
@@ -198,14 +198,19 @@ __global__ void __launch_bounds__(64 * P)
   constexpr int E = Sh::E, NH = Sh::NH, NTH = 64 * P;
   constexpr unsigned Q4 = NH / 4, NF = 2 * NH;
   constexpr unsigned PPW = Q4 / P;  // pairs per wave and phase
+  constexpr int IT = (int)PPW / 64;  // 64-pair steps per wave and phase
+  constexpr unsigned NU = NH / 64;   // W_Nh^{64 j} = W_NU^j
   constexpr int XB = KIND == 1 ? 8 : 4;
   __shared__ float2 lds[Sh::LDS];
   __shared__ float2 twl[F / 2];
   __shared__ float2 rtl[tw_lds_points<NH>()];
+  __shared__ float2 rul[NU];
   __shared__ float2 rfl[tw_lds_points<2 * NH>()];
   const TwHalf<F> twd = load_half_twiddles<F>(twl, tw, threadIdx.x, NTH);
   const TwLds rtd = load_twiddles<NH>(rtl, root_h, threadIdx.x, NTH);
   const TwLds rfd = load_twiddles<2 * NH>(rfl, root_f, threadIdx.x, NTH);
+  // W_NU^j / 2: the 1/2 of the combine below rides on the input twiddle
+  for (unsigned i = threadIdx.x; i < NU; i += NTH) rul[i] = cscale(root_h[64 * i], 0.5f);
 
   // raw samples (x[2m], x[2m+1]) of trace tb in input-slot order
   float2 v[E];
@@ -226,78 +231,106 @@ __global__ void __launch_bounds__(64 * P)
     // out of the loop and kept live in registers across it
     const unsigned tid = threadIdx.x + opaque_zero();
     const unsigned r = tid / 64, lane = tid % 64;
+    // z[m] W_Nh^{r m} / 2 with m = lane + 64 e: W_Nh^{r lane} W_NU^{r e} / 2
+    {
+      const float2 wl = rtd(r * lane);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const unsigned m = lane + 64 * e;
-      v[FF::in_slot(e)] = cmul(v[FF::in_slot(e)], rtd(r * m));
+      for (int e = 0; e < E; ++e)
+        v[FF::in_slot(e)] = cmul(v[FF::in_slot(e)], cmul(wl, rul[(r * (unsigned)e) & (NU - 1)]));
     }
-    FF::forward(v, lds + r * FF::window(), lane, twd);
+    FF::forward(v, lds + r * FF::window(), lane, twd);  // Z/2
 
     const Rsrc rX = make_rsrc(X + b * os, (uint64_t)(half ? NH + 1 : NF) * 8);
     using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rX, 0, 0, 0));
-    auto st2 = [&](unsigned idx, float2 a, float2 c) {
+    auto st2 = [&](unsigned voff, float2 a, float2 c) {
       __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, make_float4(a.x, a.y, c.x, c.y)), rX,
-                                             (int)(8 * idx), 0, 0);
+                                             (int)voff, 0, 0);
+    };
+    // X[k] = Z[k]/2 + conj Z[Nh-k]/2 - j W^k (Z[k]/2 - conj Z[Nh-k]/2), from the halves a, c
+    auto comb = [](float2 a, float2 c, float2 w) {
+      const float2 cc = cconj(c);
+      return cadd(cadd(a, cc), cmul(w, cmul_mj(csub(a, cc))));
     };
 #pragma unroll
     for (int ph = 0; ph < 2; ++ph) {
-      // LDS slot of Z[z] in this phase
-      auto slot = [&](unsigned z) -> unsigned {
-        if (ph == 0) return z < Q4 ? z : z - NH / 2;
-        return z == Q4 - 1 ? NH / 2 + 2 : z - Q4;
+      // LDS slot of Z[z]: phase 0 holds quarters 0 and 3 with Z[-1], Z[Nh], Z[Nh+1]
+      // copied to the ends of their runs; phase 1 holds quarters 1 and 2 with
+      // Z[Q4-1], Z[3Q4], Z[3Q4+1]; on each run the slot is z plus a constant
+      auto slot = [&](int zz) -> int {
+        if (ph == 0) return zz < (int)Q4 ? zz + 2 : zz - NH / 2 + 2;
+        return zz - (int)Q4 + 2;
       };
-      // X[k], 0 <= k < N_fft, from the staged half of Z
-      auto bin = [&](unsigned k) {
-        const unsigned kz = k & (NH - 1), mz = (NH - kz) & (NH - 1);
-        const float2 a = lds[lds_idx(slot(kz))];
-        const float2 c = cconj(lds[lds_idx(slot(mz))]);
-        const float2 ev = cscale(cadd(a, c), 0.5f);
-        const float2 od = cscale(cmul_mj(csub(a, c)), 0.5f);
-        return cadd(ev, cmul(rfd(k), od));
-      };
-      // bins k, k+1 (k even): direct pair, and the mirror pair conj(X[k], X[k-1])
-      auto emit = [&](unsigned k, float2 x0, float2 x1, float2 xm) {
-        if (half && k == NH) {
-          st_c64(x0, rX, 8 * k);
-          return;
-        }
-        st2(k, x0, x1);
-        if (!half && k >= 2 && k < NH) st2(NF - k, cconj(x0), cconj(xm));
+      auto bin = [&](unsigned k) {  // any bin 0 <= k < N_fft whose Z pair is staged
+        const int kz = (int)(k & (NH - 1)), mz = (int)((NH - (k & (NH - 1))) & (NH - 1));
+        return comb(lds[lds_idx(slot(kz))], lds[lds_idx(slot(mz))], rfd(k));
       };
       __syncthreads();  // FFT windows / previous phase's reads are done
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int quarter = (4 * e) / E;
-        const unsigned k = P * (lane + 64 * e) + r;
+        const int k = (int)(P * (lane + 64 * e) + r);
         const float2 z = v[FF::out_slot(e)];
         if (ph == 0) {
           if (quarter == 0 || quarter == 3) lds[lds_idx(slot(k))] = z;
+          if (e == 0 && lane == 0 && r <= 1) lds[lds_idx(NH / 2 + 2 + k)] = z;     // Z[Nh], Z[Nh+1]
+          if (e == E - 1 && lane == 63 && r == P - 1) lds[lds_idx(1)] = z;        // Z[-1]
         } else {
-          if (quarter == 1 || quarter == 2 || (quarter == 3 && k <= 3 * Q4 + 1) ||
-              (quarter == 0 && k == Q4 - 1))
+          if (quarter == 1 || quarter == 2 || (quarter == 3 && k <= (int)(3 * Q4 + 1)) ||
+              (quarter == 0 && k == (int)Q4 - 1))
             lds[lds_idx(slot(k))] = z;
         }
       }
       __syncthreads();
       if (ph == 1 && b + gridDim.x < B) fetch(b + gridDim.x, lane);  // lands while this half is written
-      // wave r takes pairs [r PPW, (r+1) PPW) of this phase in steps of 64:
-      // phase 0: k = 2p (p < Q4/2), k = 3Q4 + 2 + 2(p - Q4/2); phase 1: k = Q4 + 2p
+
+      // wave r takes pairs (k, k+1), k even, k = k0 + 128 it (it < IT):
+      // phase 0: k0 = 2 r PPW + 2 lane (r < P/2), 3Q4 + 2 + 2 (r PPW - Q4/2) + 2 lane;
+      // phase 1: k0 = Q4 + 2 r PPW + 2 lane
+      const bool upper = ph == 0 && r >= (unsigned)(P / 2);
+      const unsigned k0 = ph == 0 ? (upper ? 3 * Q4 + 2 + 2 * (r * PPW - Q4 / 2) : 2 * r * PPW) + 2 * lane
+                                  : Q4 + 2 * r * PPW + 2 * lane;
+      const int ca = ph == 0 ? (upper ? 2 - NH / 2 : 2) : 2 - (int)Q4;  // slot - z on the run of Z[k]
+      const int cm = ph == 0 ? (upper ? 2 : 2 - NH / 2) : 2 - (int)Q4;  // ... of Z[Nh-k]
+      // a step moves k by 128 slots, i.e. 136 LDS points, on every run
+      const float2 *pa = lds + lds_idx((int)k0 + ca);                                    // Z[k], Z[k+1]
+      const int mlast = NH - (int)k0 - 128 * (IT - 1) + cm;                              // Z[Nh-k] at the last step
+      const float2 *pm0 = lds + lds_idx(mlast), *pm1 = lds + lds_idx(mlast - 1);        // Z[Nh-k], Z[Nh-k-1]
+      const float2 *ph_ = rfd.hi + (k0 >> 7);                                            // W^{128 (k0/128 + it)}
+      const float2 lo0 = rfd.lo[k0 & 127], lo1 = rfd.lo[(k0 + 1) & 127];
+      const unsigned vdir = 8 * k0, vmir = 8 * (NF - k0);
       float2 carry = make_float2(0.f, 0.f);
-      for (unsigned it = 0; it < PPW / 64; ++it) {
-        const unsigned p = r * PPW + 64 * it + lane;
-        const unsigned k = ph == 0 ? (p < Q4 / 2 ? 2 * p : 3 * Q4 + 2 + 2 * (p - Q4 / 2)) : Q4 + 2 * p;
-        const float2 x0 = bin(k), x1 = bin(k + 1);
-        float2 xm = make_float2(__shfl_up(x1.x, 1), __shfl_up(x1.y, 1));
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const float2 hi = ph_[it];
+        const float2 x0 = comb(pa[136 * it], pm0[136 * (IT - 1 - it)], cmul(lo0, hi));
+        const float2 x1 = comb(pa[136 * it + 1], pm1[136 * (IT - 1 - it)], cmul(lo1, hi));
+        float2 xm = make_float2(__shfl_up(x1.x, 1), __shfl_up(x1.y, 1));  // X[k-1] from lane - 1
         if (it == 0) {
-          const float2 first = bin((k + NF - 1) & (NF - 1));
+          const float2 first = bin((k0 + NF - 1) & (NF - 1));
           if (lane == 0) xm = first;
         } else if (lane == 0) {
           xm = carry;
         }
         carry = make_float2(__shfl(x1.x, 63), __shfl(x1.y, 63));
-        emit(k, x0, x1, xm);
+        // the pair (Nh, Nh+1) is the last of phase 0; in the half spectrum
+        // only X[Nh] is written, and its mirror would repeat the direct store;
+        // the pair (0, 1) (first of phase 0) has no mirror
+        const bool top = ph == 0 && it == IT - 1 && r == (unsigned)(P - 1) && lane == 63;
+        const bool bottom = ph == 0 && it == 0 && r == 0 && lane == 0;
+        if (half && top) {
+          st_c64(x0, rX, 8 * NH);
+        } else {
+          st2(vdir + 1024 * it, x0, x1);
+          // mirror pair conj(X[k], X[k-1]) at N_fft - k
+          if (!half && !top && !bottom) st2(vmir - 1024 * it, cconj(x0), cconj(xm));
+        }
       }
-      if (ph == 1 && tid == 0) emit(3 * Q4, bin(3 * Q4), bin(3 * Q4 + 1), bin(3 * Q4 - 1));
+      if (ph == 1 && tid == 0) {
+        const unsigned k = 3 * Q4;
+        const float2 x0 = bin(k), x1 = bin(k + 1), xm = bin(k - 1);
+        st2(8 * k, x0, x1);
+        if (!half) st2(8 * (NF - k), cconj(x0), cconj(xm));
+      }
     }
   }  // traces
 }
