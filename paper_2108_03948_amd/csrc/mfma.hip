@@ -8,10 +8,11 @@
 // v_mfma_f32_32x32x16_{f16,bf16} per operand pair (K = 16 + 16).  Operands are
 // split into a high and a low part in the 16-bit type, and the product is
 // accumulated in FP32 as  Ah Bh + Ah Bl + Al Bh  (the Al Bl term is below the
-// FP32 rounding of the sum).  Each butterfly's inputs are scaled by a power of
-// two so that their largest component sits near 2^13: FP16's range holds the
-// high part and its low part stays normal; the scale is exact and is undone
-// on the FP32 result.
+// FP32 rounding of the sum).  For FP16 each butterfly's inputs are scaled by a
+// power of two so that their largest component sits near 2^13: FP16's range
+// holds the high part and its low part stays normal; the scale is exact and
+// is undone on the FP32 result.  BF16 shares FP32's exponent range and needs
+// no scaling.
 //
 // Lane layout of the 32x32x16 operations (checked on the device):
 //   A (32 x 16): lane l holds row l%32, k = 8(l/32) + q, q < 8;
@@ -88,18 +89,25 @@ struct MfmaFft {
   // y = F16 x for this lane's butterfly: x[q] are inputs 8h+q, results are
   // outputs out_k(h, c), c < 8
   __device__ __forceinline__ void butterfly(float2 (&x)[8], float2 (&y)[8]) const {
-    float mx = 0.f;
+    // FP16 needs the inputs brought near 2^13 (its range, and a normal low
+    // part); BF16 has the FP32 exponent range and is split as it is
+    constexpr bool kScale = PREC == TZ_SPLIT_FP16;
+    float up = 1.f, down = 1.f;
+    if constexpr (kScale) {
+      float mx = 0.f;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fmaxf(fabsf(x[q].x), fabsf(x[q].y)));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));  // partner lane holds the other 8 inputs
-    int ex = 0;
-    (void)frexpf(mx, &ex);
-    const int sh = (mx > 0.f) ? 13 - ex : 0;  // largest component near 2^13
-    const float up = ldexpf(1.f, sh), down = ldexpf(1.f, -sh);
+      for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fmaxf(fabsf(x[q].x), fabsf(x[q].y)));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));  // partner lane holds the other 8 inputs
+      int ex = 0;
+      (void)frexpf(mx, &ex);
+      const int sh = (mx > 0.f) ? 13 - ex : 0;  // largest component near 2^13
+      up = ldexpf(1.f, sh);
+      down = ldexpf(1.f, -sh);
+    }
     V brh, brl, bih, bil;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const float xr = x[q].x * up, xi = x[q].y * up;
+      const float xr = kScale ? x[q].x * up : x[q].x, xi = kScale ? x[q].y * up : x[q].y;
       const S hr = (S)xr, hi = (S)xi;
       brh[q] = hr;
       brl[q] = (S)(xr - (float)hr);
@@ -115,8 +123,13 @@ struct MfmaFft {
     c = SP::mfma(a2l, bih, c);
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
-      y[cc] = make_float2(c[cc] * down, c[8 + cc] * down);          // outputs 4h + cc
-      y[4 + cc] = make_float2(c[4 + cc] * down, c[12 + cc] * down);  // outputs 8 + 4h + cc
+      if constexpr (kScale) {
+        y[cc] = make_float2(c[cc] * down, c[8 + cc] * down);          // outputs 4h + cc
+        y[4 + cc] = make_float2(c[4 + cc] * down, c[12 + cc] * down);  // outputs 8 + 4h + cc
+      } else {
+        y[cc] = make_float2(c[cc], c[8 + cc]);
+        y[4 + cc] = make_float2(c[4 + cc], c[12 + cc]);
+      }
     }
   }
 
