@@ -2,6 +2,8 @@
 
   python bench_profiles.py stats <kernel_stats.csv> <out.md> "<command>"
   python bench_profiles.py traffic <fetch_counter.csv> <write_counter.csv> <out.json> "<cmd>"
+  python bench_profiles.py kernel-traffic <fetch_counter.csv> <write_counter.csv> <kernel_stats.csv>
+         <calibration.json> <out.md> "<cmd>" <name-substring> ...
 
 Byte counters are scaled by what the same counters read for the 1 GiB device
 copy that ``bench.py --calib-copy`` runs first (dispatch with the largest grid
@@ -60,9 +62,36 @@ def traffic(fetch_csv, write_csv, out, cmd, source_hash):
     json.dump(res, open(out, "w"), indent=1)
 
 
+def kernel_traffic(fetch_csv, write_csv, stats_csv, calib_json, out, cmd, keys):
+    """Per-dispatch HBM bytes of the named kernels (counters scaled by the
+    copy calibration recorded in calib_json) against their average durations."""
+    cal = json.load(open(calib_json))["calibration"]
+    f = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = _per_dispatch(write_csv, "WRITE_SIZE")
+    dur = {r["Name"].split("(")[0]: float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    lines = ["# HBM traffic per dispatch", "", f"Command (counters, one run per counter):\n\n    {cmd}\n",
+             f"Scaled by the 1 GiB copy calibration of `profiles/traffic.json` (FETCH x{cal['fetch_scale']:.3f}, "
+             f"WRITE x{cal['write_scale']:.3f}); durations from the kernel-trace run of the same command.", "",
+             "| kernel | dispatches | fetch (MB) | write (MB) | average (us) | GB/s |", "|---|---|---|---|---|---|"]
+    names = sorted({x[0].split("(")[0] for x in f if any(k in x[0] for k in keys)})
+    for name in names:
+        fv = [x[2] for x in f if x[0].split("(")[0] == name]
+        wv = [x[2] for x in w if x[0].split("(")[0] == name]
+        if not fv or not wv or name not in dur:
+            continue
+        fb = sum(fv) / len(fv) * 1024 * cal["fetch_scale"]
+        wb = sum(wv) / len(wv) * 1024 * cal["write_scale"]
+        us = dur[name] / 1e3
+        lines.append(f"| `{name}` | {len(fv)} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {us:.1f} | "
+                     f"{(fb + wb) / (us * 1e-6) / 1e9:.0f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "kernel-traffic":
+        kernel_traffic(*sys.argv[2:8], sys.argv[8:])
     else:
         sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
         import bench

@@ -171,9 +171,10 @@ __global__ void __launch_bounds__(Fft<FL>::NT)
 // X[k-1] taken from lane l-1 (lane 63 of the previous step for lane 0).
 //
 // Persistent: each workgroup fills its twiddle tables once and then takes
-// traces b = blockIdx.x, + gridDim.x, ...; the samples of the next trace are
-// fetched into the idle FFT registers while the last half of the current
-// spectrum is written, and stores are never waited for at barriers.
+// traces b = blockIdx.x, + gridDim.x, ...; stores are never waited for at
+// barriers, so the writes of one trace drain while the next is loaded and
+// transformed.  (Fetching the next trace during the last half of the writes
+// was measured slower: holding its samples forces register spills.)
 // ---------------------------------------------------------------------------
 template <int F, int P>
 struct PadWaveShape {
@@ -214,6 +215,7 @@ __global__ void __launch_bounds__(64 * P)
 
   // raw samples (x[2m], x[2m+1]) of trace tb in input-slot order
   float2 v[E];
+  // (loaded at the top of each trace)
   auto fetch = [&](int64_t tb, unsigned lane_) {
     const Rsrc rx = make_rsrc((const char *)x + tb * xs * XB, (uint64_t)N * XB);
 #pragma unroll
@@ -222,7 +224,6 @@ __global__ void __launch_bounds__(64 * P)
       v[FF::in_slot(e)] = make_float2(ld_real<KIND>(rx, 2 * m), ld_real<KIND>(rx, 2 * m + 1));
     }
   };
-  if ((int64_t)blockIdx.x < B) fetch(blockIdx.x, threadIdx.x % 64);
 
   for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
     __syncthreads();  // tables filled / previous trace's staging reads done
@@ -231,6 +232,7 @@ __global__ void __launch_bounds__(64 * P)
     // out of the loop and kept live in registers across it
     const unsigned tid = threadIdx.x + opaque_zero();
     const unsigned r = tid / 64, lane = tid % 64;
+    fetch(b, lane);
     // z[m] W_Nh^{r m} / 2 with m = lane + 64 e: W_Nh^{r lane} W_NU^{r e} / 2
     {
       const float2 wl = rtd(r * lane);
@@ -281,14 +283,16 @@ __global__ void __launch_bounds__(64 * P)
         }
       }
       __syncthreads();
-      if (ph == 1 && b + gridDim.x < B) fetch(b + gridDim.x, lane);  // lands while this half is written
 
       // wave r takes pairs (k, k+1), k even, k = k0 + 128 it (it < IT):
       // phase 0: k0 = 2 r PPW + 2 lane (r < P/2), 3Q4 + 2 + 2 (r PPW - Q4/2) + 2 lane;
-      // phase 1: k0 = Q4 + 2 r PPW + 2 lane
+      // phase 1: k0 = Q4 + 2 r PPW + 2 lane.  The lane index passes through an
+      // opaque zero here so that these addresses are formed after the FFT
+      // rather than hoisted above it and held in registers across it.
+      const unsigned lane_ = lane + opaque_zero();
       const bool upper = ph == 0 && r >= (unsigned)(P / 2);
-      const unsigned k0 = ph == 0 ? (upper ? 3 * Q4 + 2 + 2 * (r * PPW - Q4 / 2) : 2 * r * PPW) + 2 * lane
-                                  : Q4 + 2 * r * PPW + 2 * lane;
+      const unsigned k0 = ph == 0 ? (upper ? 3 * Q4 + 2 + 2 * (r * PPW - Q4 / 2) : 2 * r * PPW) + 2 * lane_
+                                  : Q4 + 2 * r * PPW + 2 * lane_;
       const int ca = ph == 0 ? (upper ? 2 - NH / 2 : 2) : 2 - (int)Q4;  // slot - z on the run of Z[k]
       const int cm = ph == 0 ? (upper ? 2 : 2 - NH / 2) : 2 - (int)Q4;  // ... of Z[Nh-k]
       // a step moves k by 128 slots, i.e. 136 LDS points, on every run
@@ -324,6 +328,9 @@ __global__ void __launch_bounds__(64 * P)
           // mirror pair conj(X[k], X[k-1]) at N_fft - k
           if (!half && !top && !bottom) st2(vmir - 1024 * it, cconj(x0), cconj(xm));
         }
+        // one step's loads in flight at a time: the other quarter of Z is
+        // still held in registers for the next phase
+        __builtin_amdgcn_sched_barrier(0);
       }
       if (ph == 1 && tid == 0) {
         const unsigned k = 3 * Q4;
