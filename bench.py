@@ -254,6 +254,25 @@ def main():
                       "bins_per_s": B * M / (ms * 1e-3)}
         log(f"bench: czt {prec} {ms:.3f} ms ({ms_czt / ms:.2f}x fp32), rel L2 {mfma[prec]['rel_l2_sampled']:.2e}")
 
+    # frequency response of the 4096 reference/sample pairs, fused
+    Ht = torch.empty((B // 2, M), dtype=torch.complex64, device=dev)
+    for _ in range(2):
+        tz.czt_transfer(x, M, W, A, out=Ht, stream=stream)
+    reps = max(5, args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        tz.czt_transfer(x, M, W, A, out=Ht, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_tr = e0.elapsed_time(e1) / reps
+    Xo = oracle.czt(x_np[:2].astype(np.float64), M, W, A)
+    werr = float(np.linalg.norm(Xo[0] * (Ht[0].cpu().numpy() - Xo[1] / Xo[0])) / np.linalg.norm(Xo[1]))
+    transfer = {"ms": ms_tr, "pairs": B // 2, "H_bins_per_s": (B // 2) * M / (ms_tr * 1e-3),
+                "weighted_rel_l2_sampled": werr}
+    log(f"bench: czt_transfer {ms_tr:.3f} ms for {B // 2} pairs, weighted rel L2 {werr:.2e}")
+
     out = {
         "metric": METRIC,
         "value": B * M / (ms_per_step * 1e-3),
@@ -278,6 +297,7 @@ def main():
         "czt_only": {"value": B * M / (ms_czt * 1e-3), "ms": ms_czt},
         "kernels": kernels,
         "mfma_vs_fp32": mfma,
+        "transfer": transfer,
         "czt_rel_l2_sampled": err,
     }
     if not args.no_cpu:

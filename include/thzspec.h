@@ -135,6 +135,22 @@ tz_status czt_band_exact(const void *x, int64_t N, int64_t M, int64_t fs_hz,
 tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2,
                    int64_t M, int64_t D, void *X, const tz_opts *opts);
 
+/*
+ * Frequency response of sample/reference pairs (Section 1: the response of
+ * the material under test is derived by comparing the sample trace with the
+ * reference trace), on the CZT contour of czt() (eq. (11)):
+ *   H[p][k] = X_s[k] / X_r[k],  X_r = CZT of row 2p, X_s = CZT of row 2p+1,
+ *   k < M, p < B/2, with B = opts->batch traces (even; TZ_EINVAL otherwise).
+ * Row p of H starts at complex element p * out_stride (0 means M).  Both CZTs
+ * of a pair run in one workgroup and only H is written; the postmultiply of
+ * eq. (13) cancels in the ratio.  A bin where X_r is exactly 0 gives IEEE
+ * inf / nan.  Single-pass shapes only (N + M - 1 <= 16384, FP32 input f32 or
+ * f64, TZ_FP32); other shapes return TZ_EUNSUPPORTED.  Errors otherwise as
+ * czt().
+ */
+tz_status czt_transfer(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *H,
+                       const tz_opts *opts);
+
 /* ---------------------------------------------------------------------- */
 /* Host-only helpers (pure functions, no device work).                     */
 

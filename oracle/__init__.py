@@ -121,6 +121,17 @@ def czt(x, M: int, W: complex, A: complex, bins=None) -> np.ndarray:
     return out
 
 
+def transfer(x, M: int, W: complex, A: complex, bins=None) -> np.ndarray:
+    """Frequency response of sample/reference pairs (Section 1: the material's
+    response is the sample's spectrum relative to the reference's), on the CZT
+    contour of eq. (11): rows 2p (reference) and 2p+1 (sample) of x give
+    H[p][k] = X_{2p+1}[k] / X_{2p}[k], each X the direct FP64 sum of czt()."""
+    X = czt(x, M, W, A, bins)
+    if X.shape[0] % 2:
+        raise ValueError("transfer needs reference/sample row pairs")
+    return X[1::2] / X[0::2]
+
+
 def czt_band_exact(x, M: int, fs_hz: int, f1_hz: int, f2_hz: int, bins=None) -> np.ndarray:
     """CZT over [f1, f2) with M bins, eqs. (22)-(24), integer-hertz band with
     exact rational phases.  Real x [B, N]."""

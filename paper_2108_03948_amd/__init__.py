@@ -61,7 +61,8 @@ class tz_job(ctypes.Structure):
 
 # every symbol declared in include/thzspec.h
 EXPORTS = (
-    "tz_opts_init", "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_band", "fft_zero_count",
+    "tz_opts_init", "fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "zoom_fft", "czt_band",
+    "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "tz_batch_create",
     "tz_batch_launch", "tz_batch_destroy", "tz_batch_describe", "tz_last_error", "tz_version",
     "tz_release_plans",
@@ -86,6 +87,7 @@ def lib() -> ctypes.CDLL:
         L.tz_opts_init.restype = None
         L.fft_zeropad.argtypes = [vp, i64, i64, vp, po]
         L.czt.argtypes = [vp, i64, i64, tz_c64, tz_c64, vp, po]
+        L.czt_transfer.argtypes = [vp, i64, i64, tz_c64, tz_c64, vp, po]
         L.czt_band_exact.argtypes = [vp, i64, i64, i64, i64, i64, vp, po]
         L.zoom_fft.argtypes = [vp, i64, dbl, dbl, dbl, i64, i64, vp, po]
         L.czt_band.argtypes = [dbl, dbl, dbl, i64, ctypes.POINTER(tz_c64), ctypes.POINTER(tz_c64)]
@@ -105,7 +107,7 @@ def lib() -> ctypes.CDLL:
         L.tz_last_error.restype = ctypes.c_char_p
         L.tz_version.restype = ctypes.c_char_p
         L.tz_release_plans.restype = None
-        for f in ("fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_band", "czt_plan_shape",
+        for f in ("fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "zoom_fft", "czt_band", "czt_plan_shape",
                   "tz_batch_create", "tz_batch_launch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -199,6 +201,26 @@ def czt(x, M: int, W: complex, A: complex, *, out=None, precision="fp32", stream
     with _torch().cuda.device(x.device):
         _check(lib().czt(x.data_ptr(), x.shape[1], int(M), tz_c64(W.real, W.imag), tz_c64(A.real, A.imag),
                          out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def czt_transfer(x, M: int, W: complex, A: complex, *, out=None, stream=None):
+    """H[p][k] = CZT(x[2p+1])[k] / CZT(x[2p])[k]: frequency response of
+    reference/sample row pairs, one [B/2, M] complex64 row per pair."""
+    torch = _torch()
+    x = _traces(x)
+    if x.shape[0] % 2:
+        raise ValueError("x must hold reference/sample row pairs (even number of rows)")
+    M = int(M)
+    if out is None:
+        out = torch.empty((x.shape[0] // 2, M), dtype=torch.complex64, device=x.device)
+    elif out.dtype != torch.complex64 or not out.is_cuda or out.shape != (x.shape[0] // 2, M) or out.stride(1) != 1:
+        raise ValueError("out must be a complex64 GPU tensor [B/2, M] with unit inner stride")
+    o = _opts(x, out.stride(0), stream=stream)
+    W, A = complex(W), complex(A)
+    with torch.cuda.device(x.device):
+        _check(lib().czt_transfer(x.data_ptr(), x.shape[1], M, tz_c64(W.real, W.imag), tz_c64(A.real, A.imag),
+                                  out.data_ptr(), ctypes.byref(o)))
     return out
 
 

@@ -439,6 +439,46 @@ tz_status czt(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *X, 
   return run_blue(d, *pl, x, c.in_kind, X, c, c.stream);
 }
 
+tz_status czt_transfer(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *H, const tz_opts *o) {
+  if (M < 1) return fail(TZ_EINVAL, "M must be >= 1 (got %lld)", (long long)M);
+  if (!finite_nonzero(W) || !finite_nonzero(A)) return fail(TZ_EINVAL, "W and A must be finite and non-zero");
+  Common c;
+  tz_status st = check_common(x, N, H, o, M, &c);
+  if (st) return st;
+  if (c.B % 2) return fail(TZ_EINVAL, "batch must hold reference/sample pairs (got %lld traces)", (long long)c.B);
+  if (!unit(W) || !unit(A))
+    return fail(TZ_EUNSUPPORTED, "GPU path evaluates the unit circle only (|A| = |W| = 1)");
+  if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "czt_transfer runs in FP32 only");
+  PhaseParams p{};
+  p.rational = 0;
+  p.a = frac01(atan2(A.im, A.re) / (2.0 * M_PI));
+  p.w = frac01(-atan2(W.im, W.re) / (2.0 * M_PI));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  std::shared_ptr<BluePlan> pl;
+  if ((st = get_blue(d, N, M, p, c.stream, &pl))) return st;
+  if (pl->L1 || pl->nseg != 1 || pl->nblk != 1)
+    return fail(TZ_EUNSUPPORTED, "czt_transfer needs N + M - 1 <= 16384 (N=%lld, M=%lld)", (long long)N,
+                (long long)M);
+  const float2 *tw = nullptr;
+  if ((st = get_twiddles(d, pl->L, c.stream, &tw))) return st;
+  TransferLaunch a;
+  a.x = x;
+  a.in_kind = c.in_kind;
+  a.xs = c.xs;
+  a.N = N;
+  a.c_pre = pl->c_pre.as<float2>();
+  a.V = pl->V.as<float2>();
+  a.tw = tw;
+  a.H = (float2 *)H;
+  a.os = c.os;
+  a.M = M;
+  a.L = pl->L;
+  a.pairs = c.B / 2;
+  TZ_HIP(launch_czt_transfer(a, c.stream), "czt_transfer launch");
+  return TZ_OK;
+}
+
 tz_status czt_band_exact(const void *x, int64_t N, int64_t M, int64_t fs_hz, int64_t f1_hz, int64_t f2_hz,
                          void *X, const tz_opts *o) {
   if (M < 1) return fail(TZ_EINVAL, "M must be >= 1 (got %lld)", (long long)M);

@@ -96,6 +96,20 @@ hipError_t launch_czt(const CztLaunch &a, hipStream_t s);
 bool czt_mfma_supported(int L, int nseg, int nblk, int in_kind);
 hipError_t launch_czt_mfma(const CztLaunch &a, hipStream_t s);
 
+// Transfer function of row pairs (2p, 2p+1): single-pass Bluestein plan
+// (one segment, one block), H [B/2][os] complex f32.
+struct TransferLaunch {
+  const void *x;
+  int in_kind;  // 0 = f32, 1 = f64
+  int64_t xs, N;
+  const float2 *c_pre, *V, *tw;
+  float2 *H;
+  int64_t os, M;
+  int L;
+  int64_t pairs;
+};
+hipError_t launch_czt_transfer(const TransferLaunch &a, hipStream_t s);
+
 // Four-step Bluestein CZT for long traces (one segment, one bin block):
 // L = L1 L2 with L1 in {512, 1024} and 256 <= L2 <= 16384.  work holds
 // chunk * L complex values; traces run chunk at a time.

@@ -105,6 +105,67 @@ __global__ void __launch_bounds__(Fft<L>::NT)
 }
 
 // ---------------------------------------------------------------------------
+// Frequency response of sample/reference pairs (Section 1): workgroup p runs
+// the Bluestein transform of row 2p (reference) and keeps its result in
+// registers, then that of row 2p+1 (sample), and writes only
+//   H[k] = X_s[k] / X_r[k] = conj(g_s[k] / g_r[k]),
+// g the conjugated inverse FFT of each trace (the postmultiply W^{k^2/2}
+// cancels in the ratio).
+// ---------------------------------------------------------------------------
+// a / b, both scaled by 1/max(|Re b|, |Im b|) so that |b|^2 neither
+// overflows nor underflows
+__device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
+  const float s = 1.f / fmaxf(fabsf(b.x), fabsf(b.y));
+  const float2 as = cscale(a, s), bs = cscale(b, s);
+  const float d = 1.f / (bs.x * bs.x + bs.y * bs.y);
+  return make_float2((as.x * bs.x + as.y * bs.y) * d, (as.y * bs.x - as.x * bs.y) * d);
+}
+
+template <int L, int KIND>
+__global__ void __launch_bounds__(Fft<L>::NT)
+    k_czt_transfer(const void *__restrict__ x, int64_t xs, int64_t N, const float2 *__restrict__ c_pre,
+                   const float2 *__restrict__ V, const float2 *__restrict__ tw, float2 *__restrict__ H,
+                   int64_t os, int64_t M) {
+  using F = Fft<L>;
+  constexpr int NT = F::NT, E = F::E;
+  constexpr int XB = KIND == 1 ? 8 : 4;
+  __shared__ float2 lds[lds_points<L>()];
+  __shared__ float2 twl[tw_lds_points<L>()];
+  const unsigned t = threadIdx.x;
+  const int64_t p = blockIdx.x;
+  const TwLds twd = load_twiddles<L>(twl, tw, t, NT);
+  __syncthreads();
+  const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
+  const Rsrc rp = make_rsrc(c_pre, (uint64_t)N * 8);
+  const Rsrc rH = make_rsrc(H + p * os, (uint64_t)M * 8);  // bins past M are dropped
+  float2 gr[E], v[E];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const Rsrc rx = make_rsrc((const char *)x + (2 * p + s) * xs * XB, (uint64_t)N * XB);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const unsigned n = t + NT * e;  // samples past N read as 0
+      v[F::in_slot(e)] = cscale(ld_c64(rp, 8 * n), ld_real<KIND>(rx, n));
+    }
+    F::forward(v, lds, t, twd);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const unsigned k = t + NT * e;
+      v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * (k + opaque_zero()))));
+    }
+    F::out_to_in(v);
+    F::forward(v, lds, t, twd);
+    if (s == 0) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) gr[e] = v[F::out_slot(e)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) st_c64(cconj(cdiv(v[F::out_slot(e)], gr[e])), rH, 8 * (t + NT * e));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Zero-padded FFT (eqs. (2)-(5)), N_fft = P * F with F >= N:
 //   X[P q + r] = sum_{n<N} (x[n] W_{Nfft}^{r n}) W_F^{q n},   r < P, q < F.
 // For P = 1 this is one F-point FFT of the zero-padded trace.  Workgroup
@@ -503,6 +564,31 @@ hipError_t launch_czt(const CztLaunch &a, hipStream_t s) {
     case 4096: czt_dispatch_kind<4096>(a, s); break;
     case 8192: czt_dispatch_kind<8192>(a, s); break;
     case 16384: czt_dispatch_kind<16384>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int L>
+static void transfer_dispatch(const TransferLaunch &a, hipStream_t s) {
+  const dim3 grid((unsigned)a.pairs), block(Fft<L>::NT);
+  if (a.in_kind == 1)
+    hipLaunchKernelGGL((k_czt_transfer<L, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.V, a.tw, a.H,
+                       a.os, a.M);
+  else
+    hipLaunchKernelGGL((k_czt_transfer<L, 0>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.V, a.tw, a.H,
+                       a.os, a.M);
+}
+
+hipError_t launch_czt_transfer(const TransferLaunch &a, hipStream_t s) {
+  switch (a.L) {
+    case 256: transfer_dispatch<256>(a, s); break;
+    case 512: transfer_dispatch<512>(a, s); break;
+    case 1024: transfer_dispatch<1024>(a, s); break;
+    case 2048: transfer_dispatch<2048>(a, s); break;
+    case 4096: transfer_dispatch<4096>(a, s); break;
+    case 8192: transfer_dispatch<8192>(a, s); break;
+    case 16384: transfer_dispatch<16384>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

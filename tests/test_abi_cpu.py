@@ -135,11 +135,18 @@ def test_invalid_arguments_rejected_before_device_work(tz):
         (L.zoom_fft, (fake, 100, 20e12, 2e12, 1e12, 64, 4, fake, ctypes.byref(o)), "f2 > f1"),
         (L.zoom_fft, (fake, 100, 20e12, 1e12, 2e12, 64, 0, fake, ctypes.byref(o)), "D must be"),
         (L.czt_band_exact, (fake, 10, 10, 0, 1, 2, fake, ctypes.byref(o)), "fs >= 1"),
+        (L.czt_transfer, (fake, 10, 0, w, one, fake, ctypes.byref(o)), "M must be"),
     ]
     for fn, args, msg in cases:
         st, err = _raw(tz, fn, *args)
         assert st == tz.TZ_EINVAL, (fn.__name__, st, err)
         assert msg in err, (fn.__name__, err)
+    # the transfer function takes reference/sample pairs
+    o1 = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(o1))
+    o1.batch = 3
+    st, err = _raw(tz, L.czt_transfer, fake, 10, 10, w, one, fake, ctypes.byref(o1))
+    assert st == tz.TZ_EINVAL and "pairs" in err
     # a spiral contour is valid input but outside the GPU path
     o2 = tz.tz_opts()
     L.tz_opts_init(ctypes.byref(o2))

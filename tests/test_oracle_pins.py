@@ -285,3 +285,38 @@ def test_zoom_K_rounding(orc):
     assert orc.zoom_K(100e12, 0.05e12, 0.10e12, 1 << 18, 64) == 8_192_000
     assert orc.zoom_K(8.0, 0.0, 2.0, 5, 2) == 10  # 10.0 exactly
     assert orc.zoom_K(10.0, 0.0, 4.0, 1, 1) == 3  # 2.5 rounds half away from zero
+
+
+# ---------------------------------------------------------------------------
+# frequency response of sample/reference pairs (Section 1)
+# ---------------------------------------------------------------------------
+def test_transfer_integer_delay_closed_form(orc):
+    """A sample that is the reference delayed by d samples and scaled by g
+    (reference zero over its last d samples) has X_s(nu) = g e^{-j 2 pi nu d}
+    X_r(nu) exactly, so H[k] = g e^{-j 2 pi (a + k w) d} on the contour
+    A = e^{j 2 pi a}, W = e^{-j 2 pi w}."""
+    rng = np.random.default_rng(21)
+    N, d, g, M = 900, 37, 0.63, 400
+    xr = np.zeros(N)
+    xr[: N - d] = rng.standard_normal(N - d)
+    xs = np.zeros(N)
+    xs[d:] = g * xr[: N - d]
+    a, w = 0.0123, 0.37 / 1000
+    A, W = np.exp(2j * np.pi * a), np.exp(-2j * np.pi * w)
+    H = orc.transfer(np.stack([xr, xs]), M, W, A)[0]
+    k = np.arange(M)
+    ref = g * np.exp(-2j * np.pi * (a + k * w) * d)
+    assert np.max(np.abs(H - ref)) < 1e-9
+
+
+def test_transfer_identity_and_pair_order(orc):
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal((2, 300))
+    W, A = np.exp(-2j * np.pi * 0.0011), np.exp(2j * np.pi * 0.07)
+    one = orc.transfer(np.stack([x[0], x[0]]), 120, W, A)
+    assert np.max(np.abs(one - 1.0)) < 1e-12
+    H = orc.transfer(x, 120, W, A)
+    Hinv = orc.transfer(x[::-1].copy(), 120, W, A)
+    assert np.max(np.abs(H * Hinv - 1.0)) < 1e-10
+    with pytest.raises(ValueError):
+        orc.transfer(x[:1], 120, W, A)
