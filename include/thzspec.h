@@ -100,8 +100,14 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X,
  * through FFT / pointwise product / inverse FFT, chirp postmultiply.
  *   X[k] = sum_{n<N} x[n] A^{-n} W^{k n},  k = 0 .. M-1.
  * A = A0 e^{j theta0} is the start point and W = W0 e^{-j phi0} the ratio
- * between contour points (eqs. (16)-(17)).  The GPU path evaluates the unit
- * circle (|A| = |W| = 1 within 1e-12); other contours give TZ_EUNSUPPORTED.
+ * between contour points (eqs. (16)-(17)).  Off the unit circle (spirals,
+ * A0 or W0 != 1) the chirp tables carry the magnitudes A0^{-n} W0^{n^2/2} and
+ * W0^{-m^2/2}, computed in FP64 and rescaled by their exact maxima so that no
+ * FFT operand exceeds |x|.  Because FP32 FFT rounding follows the largest
+ * operands, the GPU path takes spirals whose two magnitude profiles together
+ * span at most e^6 over the transform (relative L2 error then stays within
+ * the FP32 bar), with N + M - 1 within one FFT pair (no bin blocks), in
+ * TZ_FP32 only; steeper spirals return TZ_EUNSUPPORTED.
  * Errors: TZ_EINVAL for NULL pointers, N < 1, M < 1, zero or non-finite
  * A or W.
  */

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -125,9 +126,11 @@ Device &device_state(int dev) {
 }
 
 std::string phase_key(const PhaseParams &p) {
-  char buf[160];
+  char buf[200];
   if (p.rational)
     snprintf(buf, sizeof buf, "r%lld/%lld/%lld", (long long)p.pa, (long long)p.pw, (long long)p.q);
+  else if (p.ma != 0.0 || p.mw != 0.0)
+    snprintf(buf, sizeof buf, "s%a/%a/%a/%a", p.a, p.w, p.ma, p.mw);
   else
     snprintf(buf, sizeof buf, "f%a/%a", p.a, p.w);
   return buf;
@@ -268,6 +271,50 @@ bool unit(tz_c64 z) { return fabs(hypot(z.re, z.im) - 1.0) <= 1e-12; }
 bool finite_nonzero(tz_c64 z) { return isfinite(z.re) && isfinite(z.im) && (z.re != 0.0 || z.im != 0.0); }
 
 double frac01(double v) { return v - floor(v); }
+
+// Off-unit-circle contour (|A| = e^ma, |W| = e^mw): the log magnitudes of
+// the premultiply, f(n) = -n ma + n^2 mw / 2 (n < N), and of the conjugate
+// chirp, h(m) = -m^2 mw / 2 (-N < m < M), are parabolas; their maxima alpha
+// and beta are divided out so that no FFT operand exceeds |x|, and the
+// postmultiply carries e^{k^2 mw / 2 + alpha + beta}.  An FFT convolution's
+// rounding is set by its largest operands, so outputs that depend on the
+// small end of these magnitudes lose relative accuracy roughly as e^{S/2},
+// S the sum of the two spreads (max - min of f and of h): the GPU path takes
+// contours with S <= 6 (every table magnitude then lies within e^{+-18}).
+// Spirals need one bin block and one input segment (single-pass or
+// four-step plan).
+constexpr double kSpiralSpread = 6.0;
+
+tz_status spiral_scaling(int64_t N, int64_t M, double ma, double mw, PhaseParams *p) {
+  if (!isfinite(ma) || !isfinite(mw)) return fail(TZ_EINVAL, "|A| and |W| must be finite and non-zero");
+  int L, nseg, nblk, l1;
+  int64_t Ns, Mb, Ll;
+  if (blue_shape(N, M, &L, &Ns, &nseg, &Mb, &nblk, &l1, &Ll) == 1 && (nseg != 1 || nblk != 1))
+    return fail(TZ_EUNSUPPORTED, "spiral contours need N + M - 1 within one FFT pair (no bin blocks)");
+  auto f = [&](double n) { return -n * ma + 0.5 * n * n * mw; };
+  const double nl = (double)(N - 1);
+  double fmax = std::max(f(0.0), f(nl)), fmin = std::min(f(0.0), f(nl));
+  if (mw != 0.0) {
+    const double nv = std::min(std::max(ma / mw, 0.0), nl);  // vertex of f
+    for (double n : {floor(nv), ceil(nv)}) {
+      fmax = std::max(fmax, f(n));
+      fmin = std::min(fmin, f(n));
+    }
+  }
+  const double mmax = (double)std::max(N - 1, M - 1);
+  const double hend = -0.5 * mmax * mmax * mw;  // h at the widest lag; h(0) = 0
+  const double hmax = std::max(0.0, hend), hmin = std::min(0.0, hend);
+  const double spread = (fmax - fmin) + (hmax - hmin);
+  if (spread > kSpiralSpread)
+    return fail(TZ_EUNSUPPORTED,
+                "spiral contour too steep for FP32 tables: chirp magnitudes spread over e^%.1f (limit e^%.0f)",
+                spread, kSpiralSpread);
+  p->ma = ma;
+  p->mw = mw;
+  p->alpha = fmax;
+  p->beta = hmax;
+  return TZ_OK;
+}
 
 // four-step path: chunks of traces through the plan's per-stream workspace
 tz_status run_long(Device &d, BluePlan &pl, const void *x, int in_kind, void *X, const Common &c, int64_t M,
@@ -426,12 +473,14 @@ tz_status czt(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *X, 
   Common c;
   tz_status st = check_common(x, N, X, o, M, &c);
   if (st) return st;
-  if (!unit(W) || !unit(A))
-    return fail(TZ_EUNSUPPORTED, "GPU path evaluates the unit circle only (|A| = |W| = 1)");
   PhaseParams p{};
   p.rational = 0;
   p.a = frac01(atan2(A.im, A.re) / (2.0 * M_PI));
   p.w = frac01(-atan2(W.im, W.re) / (2.0 * M_PI));
+  if (!unit(W) || !unit(A)) {
+    if ((st = spiral_scaling(N, M, log(hypot(A.re, A.im)), log(hypot(W.re, W.im)), &p))) return st;
+    if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "spiral contours run in FP32 only");
+  }
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
   std::shared_ptr<BluePlan> pl;

@@ -11,6 +11,9 @@ struct PhaseParams {
   int rational;
   double a, w;
   int64_t pa, pw, q;
+  // off the unit circle (|A| = e^ma, |W| = e^mw): tables carry magnitudes,
+  // pre scaled by e^-alpha, conjugate chirp by e^-beta, post by e^(alpha+beta)
+  double ma, mw, alpha, beta;
 };
 
 // largest single-workgroup FFT length

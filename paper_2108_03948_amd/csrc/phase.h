@@ -76,4 +76,14 @@ static __device__ __forceinline__ float2 unit_cycles(double cyc) {
   return make_float2((float)c, (float)s);
 }
 
+// e^{logmag} e^{-j 2 pi cyc}, formed in double and rounded once
+static __device__ __forceinline__ float2 scaled_cycles(double cyc, double logmag) {
+  double s, c;
+  sincospi(-2.0 * cyc, &s, &c);
+  const double m = exp(logmag);
+  return make_float2((float)(m * c), (float)(m * s));
+}
+
+static __device__ __forceinline__ bool spiral(const PhaseParams &p) { return p.ma != 0.0 || p.mw != 0.0; }
+
 }  // namespace tz

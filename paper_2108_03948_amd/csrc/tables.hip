@@ -22,7 +22,9 @@ __global__ void k_chirp_pre(float2 *c_pre, int64_t N, int nblk, int64_t Mb, Phas
     cyc += shift_cycles(p, blk * Mb, n);
     cyc -= floor(cyc);
   }
-  c_pre[i] = unit_cycles(cyc);
+  // (spiral contours come with one block and one segment)
+  const double dn = (double)n;
+  c_pre[i] = spiral(p) ? scaled_cycles(cyc, -dn * p.ma + 0.5 * dn * dn * p.mw - p.alpha) : unit_cycles(cyc);
 }
 
 // c_post[s][blk][k'] = W^{k'^2/2} A^{-s Ns} W^{(blk Mb + k') s Ns}
@@ -43,7 +45,8 @@ __global__ void k_chirp_post(float2 *c_post, int64_t Ns, int nseg, int64_t Mb, i
     }
     cyc -= floor(cyc);
   }
-  c_post[i] = unit_cycles(cyc);
+  const double dk = (double)k;
+  c_post[i] = spiral(p) ? scaled_cycles(cyc, 0.5 * dk * dk * p.mw + p.alpha + p.beta) : unit_cycles(cyc);
 }
 
 // v[l] = W^{-l^2/2} for l < Mb and v[L-l] = W^{-l^2/2} for 1 <= l < N; else 0
@@ -60,7 +63,9 @@ __global__ void k_chirp_conj(double2 *v, int64_t L, int64_t N, int64_t Mb, Phase
   double cyc = chirp_cycles(p, l, false);  // w l^2/2: W^{+l^2/2} = e^{-j 2 pi cyc}
   double s, c;
   sincospi(2.0 * cyc, &s, &c);                 // conjugate: e^{+j 2 pi cyc}
-  v[i] = make_double2(c, s);
+  // |W^{-l^2/2}| = e^{-mw l^2/2}, scaled by e^{-beta}
+  const double m = spiral(p) ? exp(-0.5 * (double)l * (double)l * p.mw - p.beta) : 1.0;
+  v[i] = make_double2(m * c, m * s);
 }
 
 // FFT twiddles tw[m] = e^{-j 2 pi m / L}

@@ -147,11 +147,14 @@ def test_invalid_arguments_rejected_before_device_work(tz):
     o1.batch = 3
     st, err = _raw(tz, L.czt_transfer, fake, 10, 10, w, one, fake, ctypes.byref(o1))
     assert st == tz.TZ_EINVAL and "pairs" in err
-    # a spiral contour is valid input but outside the GPU path
+    # a spiral contour whose chirp magnitudes span too wide a range for FP32
+    # is valid input but outside the GPU path (refused before any device work)
     o2 = tz.tz_opts()
     L.tz_opts_init(ctypes.byref(o2))
-    st, err = _raw(tz, L.czt, fake, 10, 10, tz.tz_c64(1.01, 0.0), one, fake, ctypes.byref(o2))
-    assert st == tz.TZ_EUNSUPPORTED and "unit circle" in err
+    st, err = _raw(tz, L.czt, fake, 5000, 5000, tz.tz_c64(1.01, 0.0), one, fake, ctypes.byref(o2))
+    assert st == tz.TZ_EUNSUPPORTED and "too steep" in err
+    st, err = _raw(tz, L.czt, fake, 100000, 100, tz.tz_c64(1.0 + 1e-9, 1e-6), one, fake, ctypes.byref(o2))
+    assert st == tz.TZ_EUNSUPPORTED and "bin blocks" in err
     # strides smaller than a row
     o3 = tz.tz_opts()
     L.tz_opts_init(ctypes.byref(o3))

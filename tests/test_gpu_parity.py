@@ -257,3 +257,32 @@ def test_split_precision_rejects_other_shapes(tz, dev):
     with pytest.raises(tz.ThzError) as e:
         tz.czt(x, 100, np.exp(-0.01j), 1.0, precision="split_fp16")   # L = 256
     assert e.value.status == tz.TZ_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# spiral contours (|A| or |W| != 1, eqs. (16)-(17))
+# ---------------------------------------------------------------------------
+# spreads of the two magnitude profiles (f, h): 2.5, 1.5, 3.4, 1.25, 5, 1.6
+@pytest.mark.parametrize("N,M,A0,W0", [(1000, 800, 1.0005, 0.999998), (300, 300, 0.998, 1.00001),
+                                       (4096, 4096, 1.0, 1.0000002), (2000, 2000, 0.9995, 0.9999995),
+                                       (1000, 1000, 1.0, 1.000005), (40000, 30000, 1.0, 1.0 + 1e-9)])
+def test_czt_spiral(tz, dev, orc, N, M, A0, W0):
+    rng = np.random.default_rng(N + M)
+    x = rng.standard_normal((3, N)).astype(np.float32)
+    W = W0 * np.exp(-2j * np.pi * 0.37 / max(N, M))
+    A = A0 * np.exp(2j * np.pi * 0.0123)
+    say(f"case: spiral czt N={N} M={M} A0={A0} W0={W0} plan {tz.czt_plan_shape(N, M)}")
+    X = tz.czt(to_dev(x, dev), M, W, A).cpu().numpy()
+    if N * M <= 2_000_000:
+        assert_close(X, orc.czt(x.astype(np.float64), M, W, A), what="spiral czt")
+    else:
+        bins = np.unique(np.concatenate([[0, M - 1], np.random.default_rng(1).choice(M, 80, replace=False)]))
+        ref = orc.czt(x.astype(np.float64), M, W, A, bins)
+        assert_close(X[:, bins], ref, what="spiral czt sampled")
+
+
+def test_czt_spiral_too_steep(tz, dev):
+    x = to_dev(np.ones((1, 3000), np.float32), dev)
+    with pytest.raises(tz.ThzError) as e:
+        tz.czt(x, 3000, 1.001 * np.exp(-0.001j), 1.0)       # spread ~ e^9000
+    assert e.value.status == tz.TZ_EUNSUPPORTED
