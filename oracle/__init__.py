@@ -53,7 +53,7 @@ def _load():
             lib.orc_czt.argtypes = [_pd, ctypes.c_int, _i64, _i64, _i64, _dbl, _dbl, _dbl, _dbl, _pi, _i64, _pd]
             lib.orc_czt_band_exact.argtypes = [_pd, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _pi, _i64, _pd]
             lib.orc_zoom_taps.argtypes = [_i64, _dbl, _pd]
-            lib.orc_zoom_frontend.argtypes = [_pd, _i64, _i64, _i64, _dbl, _dbl, _dbl, _i64, _pd, _i64, _pd]
+            lib.orc_zoom_frontend.argtypes = [_pd, ctypes.c_int, _i64, _i64, _i64, _dbl, _dbl, _dbl, _i64, _pd, _i64, _pd]
             lib.orc_zoom_short_dft.argtypes = [_pd, _i64, _i64, _i64, _i64, _pi, _i64, _pd]
             lib.orc_zoom_K.argtypes = [_dbl, _dbl, _dbl, _i64, _i64]
             lib.orc_zoom_K.restype = _i64
@@ -160,14 +160,17 @@ def zoom_K(fs: float, f1: float, f2: float, M: int, D: int) -> int:
 
 def zoom_frontend(x, fs: float, f1: float, f2: float, D: int, h) -> np.ndarray:
     """Zoom steps eqs. (6), (7), (10): mix f_N to DC, low-pass, keep every D-th
-    output.  Returns u [B, ceil(N/D)] complex."""
+    output.  x real or complex [B, N]; returns u [B, ceil(N/D)] complex."""
     lib = _load()
-    x = _as_real(x)
-    B, N = x.shape
+    x = _traces(x)
+    is_c = np.iscomplexobj(x)
+    xa = np.ascontiguousarray(x, dtype=np.complex128 if is_c else np.float64)
+    B, N = xa.shape
     h = np.ascontiguousarray(h, dtype=np.float64)
     LD = (N + D - 1) // D
     u = np.zeros((B, LD), dtype=np.complex128)
-    lib.orc_zoom_frontend(_p(x), N, B, N, float(fs), float(f1), float(f2), int(D), _p(h), h.size,
+    lib.orc_zoom_frontend(xa.view(np.float64).ctypes.data_as(_pd) if is_c else _p(xa), int(is_c), N, B, N,
+                          float(fs), float(f1), float(f2), int(D), _p(h), h.size,
                           u.view(np.float64).ctypes.data_as(_pd))
     return u
 
@@ -192,3 +195,49 @@ def zoom_fft(x, fs: float, f1: float, f2: float, M: int, D: int, taps: int = 63,
     u = zoom_frontend(x, fs, f1, f2, D, h)
     K = zoom_K(fs, f1, f2, M, D)
     return zoom_short_dft(u, K, M, bins)
+
+
+def _along(x, axis: int, fn):
+    """Apply fn (a map of [rows, n] to [rows, m]) to every line of x along axis."""
+    y = np.moveaxis(np.asarray(x), axis, -1)
+    lead = y.shape[:-1]
+    z = fn(y.reshape(-1, y.shape[-1]))
+    return np.moveaxis(z.reshape(lead + (z.shape[-1],)), -1, axis)
+
+
+def czt_nd(x, axes) -> np.ndarray:
+    """Multi-dimensional CZT, the 2-D and 3-D transforms Section 5 names:
+    X[k_0..k_{d-1}] = sum_n x[n_0..n_{d-1}] prod_a A_a^-n_a W_a^(k_a n_a).
+    Each factor of the kernel depends on one index pair, so the d-fold sum is
+    the one-dimensional CZT of eq. (11) taken along every axis in turn.
+    x [B, N_0, ..., N_{d-1}] real or complex; axes = [(M_a, W_a, A_a), ...]
+    for a = 0..d-1; returns [B, M_0, ..., M_{d-1}] complex."""
+    x = np.asarray(x)
+    d = len(axes)
+    if x.ndim != d + 1:
+        raise ValueError("x must be [B] + one dimension per axis")
+    y = x
+    for a, (M, W, A) in enumerate(axes):
+        y = _along(y, a + 1, lambda r, M=M, W=W, A=A: czt(r, M, W, A))
+    return y
+
+
+def zoom_fft_nd(x, axes, taps: int = 63) -> np.ndarray:
+    """Multi-dimensional Zoom FFT (Section 2.2 along every axis, for the 2-D
+    and 3-D transforms of Section 5): the mix, low-pass, decimation and short
+    DFT of each axis act on that axis' index alone, so the transform is the
+    one-dimensional Zoom FFT taken along every axis in turn (real input on
+    the first, complex on the later ones).  axes = [(fs, f1, f2, M, D, fc),
+    ...] with fc the cut-off in Hz (None = fs / (2 D)); x [B, N_0, ...];
+    returns [B, M_0, ...] complex."""
+    x = np.asarray(x)
+    d = len(axes)
+    if x.ndim != d + 1:
+        raise ValueError("x must be [B] + one dimension per axis")
+    y = x
+    for a, ax in enumerate(axes):
+        fs, f1, f2, M, D = ax[:5]
+        fc = ax[5] if len(ax) > 5 else None
+        y = _along(y, a + 1, lambda r, fs=fs, f1=f1, f2=f2, M=M, D=D, fc=fc:
+                   zoom_fft(r, fs, f1, f2, M, D, taps, fc))
+    return y

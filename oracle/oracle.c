@@ -156,8 +156,9 @@ void orc_zoom_taps(int64_t T, double nu_c, double *h)
  * Eq. (7) is printed without the sample index and 2 pi; the shift that moves
  * f_N to DC is the one taken.  Eq. (10) prints the tap sum up to N-1; the sum
  * runs over the T filter taps.  u is written to u_out as [B][ceil(N/D)]
- * complex.                                                                   */
-void orc_zoom_frontend(const double *x, int64_t xs, int64_t B, int64_t N,
+ * complex.  x is real, or interleaved complex when x_complex != 0 (xs then
+ * counts complex samples): the later axes of a multi-dimensional zoom.      */
+void orc_zoom_frontend(const double *x, int x_complex, int64_t xs, int64_t B, int64_t N,
                        double fs, double f1, double f2, int64_t D,
                        const double *h, int64_t T, double *u_out)
 {
@@ -165,14 +166,15 @@ void orc_zoom_frontend(const double *x, int64_t xs, int64_t B, int64_t N,
     const int64_t LD = (N + D - 1) / D;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t b = 0; b < B; ++b) {
-        const double *xb = x + b * xs;
+        const double *xb = x + b * xs * (x_complex ? 2 : 1);
         double complex *y = (double complex *)malloc(sizeof(double complex) * (size_t)N);
         for (int64_t n = 0; n < N; ++n) {
+            const double complex xn = x_complex ? xb[2 * n] + I * xb[2 * n + 1] : xb[n];
             /* angle 2 pi f_N n / f_s, with the integer part of f_N n / f_s
              * removed first (fmod is exact) */
             double cyc = fmod(fN * (double)n / fs, 1.0);
             double a = 2.0 * M_PI * cyc;
-            y[n] = xb[n] * (cos(a) - I * sin(a));
+            y[n] = xn * (cos(a) - I * sin(a));
         }
         for (int64_t m = 0; m < LD; ++m) {
             double complex acc = 0.0;

@@ -320,3 +320,115 @@ def test_transfer_identity_and_pair_order(orc):
     assert np.max(np.abs(H * Hinv - 1.0)) < 1e-10
     with pytest.raises(ValueError):
         orc.transfer(x[:1], 120, W, A)
+
+
+# ---------------------------------------------------------------------------
+# multi-dimensional transforms (the 2-D / 3-D case of Section 5)
+# ---------------------------------------------------------------------------
+def _unit(rng):
+    return np.exp(2j * np.pi * rng.uniform(0, 1))
+
+
+@pytest.mark.parametrize("shape", [(2, 6, 10), (1, 4, 6, 10), (3, 7, 1)])
+def test_czt_nd_dft_special_case(orc, shape):
+    # A = 1, W = e^{-j 2 pi / N_a}, M_a = N_a on every axis is the d-D DFT;
+    # unequal axis lengths make a swapped or transposed axis fail
+    x = np.random.default_rng(len(shape)).standard_normal(shape)
+    axes = [(n, np.exp(-2j * np.pi / n), 1.0) for n in shape[1:]]
+    X = orc.czt_nd(x, axes)
+    assert X.shape == shape
+    assert rel(X, np.fft.fftn(x, axes=tuple(range(1, len(shape))))) < 1e-13
+
+
+def _brute_nd(x, axes):
+    """Direct d-fold sum of x[n] prod_a A_a^-n_a W_a^(k_a n_a), Python loops."""
+    B = x.shape[0]
+    Ns = x.shape[1:]
+    Ms = tuple(ax[0] for ax in axes)
+    out = np.zeros((B,) + Ms, complex)
+    for b in range(B):
+        for k in np.ndindex(*Ms):
+            acc = 0j
+            for n in np.ndindex(*Ns):
+                term = complex(x[(b,) + n])
+                for a, (M, W, A) in enumerate(axes):
+                    term *= complex(A) ** (-n[a]) * complex(W) ** (k[a] * n[a])
+                acc += term
+            out[(b,) + k] = acc
+    return out
+
+
+def test_czt_nd_brute_force(orc):
+    rng = np.random.default_rng(31)
+    x2 = rng.standard_normal((2, 3, 5))
+    ax2 = [(4, _unit(rng), _unit(rng)), (2, 1.02 * _unit(rng), 0.97 * _unit(rng))]
+    assert rel(orc.czt_nd(x2, ax2), _brute_nd(x2, ax2)) < 1e-13
+    x3 = rng.standard_normal((1, 2, 3, 4)) + 1j * rng.standard_normal((1, 2, 3, 4))
+    ax3 = [(3, _unit(rng), _unit(rng)), (2, _unit(rng), _unit(rng)), (5, _unit(rng), _unit(rng))]
+    assert rel(orc.czt_nd(x3, ax3), _brute_nd(x3, ax3)) < 1e-13
+
+
+def test_czt_nd_impulse_closed_form(orc):
+    rng = np.random.default_rng(32)
+    N0, N1, n0, n1 = 9, 14, 4, 11
+    x = np.zeros((1, N0, N1))
+    x[0, n0, n1] = 1.0
+    (W0, A0), (W1, A1) = (_unit(rng), _unit(rng)), (_unit(rng), _unit(rng))
+    M0, M1 = 7, 12
+    X = orc.czt_nd(x, [(M0, W0, A0), (M1, W1, A1)])[0]
+    k0, k1 = np.meshgrid(np.arange(M0), np.arange(M1), indexing="ij")
+    ref = A0 ** (-n0) * W0 ** (k0 * n0) * A1 ** (-n1) * W1 ** (k1 * n1)
+    assert np.abs(X - ref).max() < 1e-12
+
+
+def test_czt_nd_separable_product(orc):
+    rng = np.random.default_rng(33)
+    a, b = rng.standard_normal(40), rng.standard_normal(27)
+    ax = [(30, _unit(rng), _unit(rng)), (35, _unit(rng), _unit(rng))]
+    X = orc.czt_nd(np.outer(a, b)[None], ax)[0]
+    ref = np.outer(orc.czt(a, *ax[0])[0], orc.czt(b, *ax[1])[0])
+    assert rel(X, ref) < 1e-13
+
+
+def test_zoom_frontend_complex_is_linear(orc):
+    # the complex-input front end (later axes of a d-D zoom) equals the real
+    # one on the real and imaginary parts: u(xr + j xi) = u(xr) + j u(xi)
+    rng = np.random.default_rng(34)
+    xr, xi = rng.standard_normal((2, 500)), rng.standard_normal((2, 500))
+    fs, f1, f2, D = 20e12, 0.3e12, 1.1e12, 5
+    h = orc.zoom_taps(31, 1 / (2 * D))
+    u = orc.zoom_frontend(xr + 1j * xi, fs, f1, f2, D, h)
+    ref = orc.zoom_frontend(xr, fs, f1, f2, D, h) + 1j * orc.zoom_frontend(xi, fs, f1, f2, D, h)
+    assert rel(u, ref) < 1e-14
+
+
+def test_zoom_nd_D1_T1_is_czt_on_zoom_grids(orc):
+    # with D = 1 and one tap every axis reduces to the DTFT on its zoom grid:
+    # scipy's CZT along each axis in turn
+    rng = np.random.default_rng(35)
+    x = rng.standard_normal((2, 40, 24))
+    axes = [(20e12, 0.4e12, 1.3e12, 30, 1), (10e12, 1.0e12, 2.5e12, 20, 1)]
+    X = orc.zoom_fft_nd(x, axes, taps=1)
+    ref = x.astype(complex)
+    for a, (fs, f1, f2, M, D) in enumerate(axes):
+        K = orc.zoom_K(fs, f1, f2, M, D)
+        fN = 0.5 * (f1 + f2)
+        A = np.exp(2j * np.pi * (fN / fs - (M // 2) / K))
+        ref = ss.czt(ref, M, np.exp(-2j * np.pi / K), A, axis=a + 1)
+    assert X.shape == (2, 30, 20)
+    assert rel(X, ref) < 1e-10
+
+
+def test_zoom_nd_tone_lands_in_predicted_bins(orc):
+    # a separable 2-D tone on the zoom grid of each axis peaks at
+    # (M_0 // 2 + j_0, M_1 // 2 + j_1)
+    ax = [(20e12, 0.2e12, 1.8e12, 128, 4), (16e12, 0.5e12, 1.5e12, 96, 6)]
+    N0, N1 = 512, 600
+    lines = []
+    for (fs, f1, f2, M, D), j, N in zip(ax, (13, -9), (N0, N1)):
+        K = orc.zoom_K(fs, f1, f2, M, D)
+        f0 = 0.5 * (f1 + f2) + j * fs / (D * K)
+        lines.append(np.cos(2 * np.pi * f0 * np.arange(N) / fs))
+    X = orc.zoom_fft_nd(np.outer(*lines)[None], [a + (None,) for a in ax], taps=63)[0]
+    k0, k1 = np.unravel_index(int(np.argmax(np.abs(X))), X.shape)
+    assert (k0, k1) == (128 // 2 + 13, 96 // 2 - 9)
