@@ -158,6 +158,57 @@ tz_status czt_transfer(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, 
                        const tz_opts *opts);
 
 /* ---------------------------------------------------------------------- */
+/* Multi-dimensional transforms (the 2-D and 3-D case Section 5 names as
+ * the setting where CZT and Zoom FFT pay off).  x holds B = opts->batch
+ * arrays x[N_0][N_1]...[N_{d-1}] (last index contiguous), consecutive arrays
+ * opts->in_stride elements apart (0 means N_0 ... N_{d-1}); X receives
+ * X[M_0]...[M_{d-1}] complex64 per array, opts->out_stride complex elements
+ * apart (0 means M_0 ... M_{d-1}).  Input TZ_F32 or TZ_F64, arithmetic
+ * TZ_FP32 only.  The transforms are separable: the one-dimensional
+ * transform of each axis is applied along that axis in turn (the axis
+ * parameters, one entry per dimension, describe axis 0 first).  Scratch:
+ * two buffers of the largest intermediate, held per stream by the library
+ * until tz_release_plans().                                               */
+#define TZ_MAX_DIMS 3
+
+/* One axis of czt_nd: N samples in, M bins out on the contour A W^-k. */
+typedef struct {
+    int64_t N, M;
+    tz_c64 W, A;
+} tz_czt_axis;
+
+/*
+ * d-dimensional CZT, 1 <= ndim <= TZ_MAX_DIMS:
+ *   X[k_0..k_{d-1}] = sum_n x[n_0..n_{d-1}] prod_a A_a^{-n_a} W_a^{k_a n_a}
+ * (eq. (11) along every axis).  Each axis accepts what czt() accepts
+ * (spirals included).
+ * Errors: TZ_EINVAL for NULL pointers, ndim out of range, N_a < 1, M_a < 1,
+ * zero or non-finite A_a or W_a, strides below the array sizes;
+ * TZ_EUNSUPPORTED for split precision and for an axis czt() refuses.
+ */
+tz_status czt_nd(const void *x, int ndim, const tz_czt_axis *axes, void *X,
+                 const tz_opts *opts);
+
+/* One axis of zoom_fft_nd: the arguments of zoom_fft() for that axis, and
+ * its low-pass cut-off fc in hertz (0 means f_s / (2 D)). */
+typedef struct {
+    int64_t N, M, D;
+    double fs, f1, f2, fc;
+} tz_zoom_axis;
+
+/*
+ * d-dimensional Zoom FFT, 1 <= ndim <= TZ_MAX_DIMS: the Zoom FFT of
+ * zoom_fft() (mix, T-tap low-pass, decimation by D_a, K_a-point short DFT on
+ * M_a bins centred on the band) applied along every axis; opts->fir_taps
+ * gives T for all axes and opts->fir_cutoff_hz must be 0 (cut-offs are per
+ * axis).
+ * Errors: TZ_EINVAL as zoom_fft() for any axis, NULL pointers, ndim out of
+ * range, a non-zero fir_cutoff_hz; TZ_EUNSUPPORTED for split precision.
+ */
+tz_status zoom_fft_nd(const void *x, int ndim, const tz_zoom_axis *axes, void *X,
+                      const tz_opts *opts);
+
+/* ---------------------------------------------------------------------- */
 /* Host-only helpers (pure functions, no device work).                     */
 
 /* W and A for M bins over [f1, f2) at rate f_s, eqs. (22)-(23).

@@ -205,31 +205,33 @@ def _along(x, axis: int, fn):
     return np.moveaxis(z.reshape(lead + (z.shape[-1],)), -1, axis)
 
 
-def czt_nd(x, axes) -> np.ndarray:
+def czt_nd(x, axes, bins=None) -> np.ndarray:
     """Multi-dimensional CZT, the 2-D and 3-D transforms Section 5 names:
     X[k_0..k_{d-1}] = sum_n x[n_0..n_{d-1}] prod_a A_a^-n_a W_a^(k_a n_a).
     Each factor of the kernel depends on one index pair, so the d-fold sum is
     the one-dimensional CZT of eq. (11) taken along every axis in turn.
     x [B, N_0, ..., N_{d-1}] real or complex; axes = [(M_a, W_a, A_a), ...]
-    for a = 0..d-1; returns [B, M_0, ..., M_{d-1}] complex."""
+    for a = 0..d-1; returns [B, M_0, ..., M_{d-1}] complex.  bins = one
+    index list per axis evaluates only that grid of bins."""
     x = np.asarray(x)
     d = len(axes)
     if x.ndim != d + 1:
         raise ValueError("x must be [B] + one dimension per axis")
     y = x
     for a, (M, W, A) in enumerate(axes):
-        y = _along(y, a + 1, lambda r, M=M, W=W, A=A: czt(r, M, W, A))
+        b = None if bins is None else bins[a]
+        y = _along(y, a + 1, lambda r, M=M, W=W, A=A, b=b: czt(r, M, W, A, b))
     return y
 
 
-def zoom_fft_nd(x, axes, taps: int = 63) -> np.ndarray:
+def zoom_fft_nd(x, axes, taps: int = 63, bins=None) -> np.ndarray:
     """Multi-dimensional Zoom FFT (Section 2.2 along every axis, for the 2-D
     and 3-D transforms of Section 5): the mix, low-pass, decimation and short
     DFT of each axis act on that axis' index alone, so the transform is the
     one-dimensional Zoom FFT taken along every axis in turn (real input on
     the first, complex on the later ones).  axes = [(fs, f1, f2, M, D, fc),
     ...] with fc the cut-off in Hz (None = fs / (2 D)); x [B, N_0, ...];
-    returns [B, M_0, ...] complex."""
+    returns [B, M_0, ...] complex (bins: as czt_nd)."""
     x = np.asarray(x)
     d = len(axes)
     if x.ndim != d + 1:
@@ -238,6 +240,7 @@ def zoom_fft_nd(x, axes, taps: int = 63) -> np.ndarray:
     for a, ax in enumerate(axes):
         fs, f1, f2, M, D = ax[:5]
         fc = ax[5] if len(ax) > 5 else None
-        y = _along(y, a + 1, lambda r, fs=fs, f1=f1, f2=f2, M=M, D=D, fc=fc:
-                   zoom_fft(r, fs, f1, f2, M, D, taps, fc))
+        b = None if bins is None else bins[a]
+        y = _along(y, a + 1, lambda r, fs=fs, f1=f1, f2=f2, M=M, D=D, fc=fc, b=b:
+                   zoom_fft(r, fs, f1, f2, M, D, taps, fc, b))
     return y

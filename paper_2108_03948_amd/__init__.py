@@ -15,7 +15,8 @@ import os
 import threading
 
 __all__ = [
-    "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_band", "fft_zero_count",
+    "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_transfer", "czt_nd", "zoom_fft_nd", "czt_band",
+    "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "lib", "ThzError",
     "Batch", "release_plans", "version",
 ]
@@ -59,9 +60,23 @@ class tz_job(ctypes.Structure):
     ]
 
 
+class tz_czt_axis(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("W", tz_c64), ("A", tz_c64)]
+
+
+class tz_zoom_axis(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("M", ctypes.c_int64), ("D", ctypes.c_int64), ("fs", ctypes.c_double),
+        ("f1", ctypes.c_double), ("f2", ctypes.c_double), ("fc", ctypes.c_double),
+    ]
+
+
+TZ_MAX_DIMS = 3
+
 # every symbol declared in include/thzspec.h
 EXPORTS = (
-    "tz_opts_init", "fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "zoom_fft", "czt_band",
+    "tz_opts_init", "fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "zoom_fft", "czt_nd",
+    "zoom_fft_nd", "czt_band",
     "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "tz_batch_create",
     "tz_batch_launch", "tz_batch_destroy", "tz_batch_describe", "tz_last_error", "tz_version",
@@ -90,6 +105,8 @@ def lib() -> ctypes.CDLL:
         L.czt_transfer.argtypes = [vp, i64, i64, tz_c64, tz_c64, vp, po]
         L.czt_band_exact.argtypes = [vp, i64, i64, i64, i64, i64, vp, po]
         L.zoom_fft.argtypes = [vp, i64, dbl, dbl, dbl, i64, i64, vp, po]
+        L.czt_nd.argtypes = [vp, ctypes.c_int, ctypes.POINTER(tz_czt_axis), vp, po]
+        L.zoom_fft_nd.argtypes = [vp, ctypes.c_int, ctypes.POINTER(tz_zoom_axis), vp, po]
         L.czt_band.argtypes = [dbl, dbl, dbl, i64, ctypes.POINTER(tz_c64), ctypes.POINTER(tz_c64)]
         L.fft_zero_count.argtypes = [dbl, i64, dbl]
         L.fft_zero_count.restype = i64
@@ -247,6 +264,71 @@ def zoom_fft(x, fs: float, f1: float, f2: float, M: int, D: int, *, taps: int = 
         _check(lib().zoom_fft(x.data_ptr(), x.shape[1], float(fs), float(f1), float(f2), int(M), int(D),
                               out.data_ptr(), ctypes.byref(o)))
     return out
+
+
+def _arrays(x, ndim: int):
+    """x as [B, N_0, ..., N_{d-1}] with each array packed (last index fastest)."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("x must be a torch tensor on the GPU")
+    if not 1 <= ndim <= TZ_MAX_DIMS:
+        raise ValueError(f"1 to {TZ_MAX_DIMS} axes")
+    if x.dim() == ndim:
+        x = x.unsqueeze(0)
+    if x.dim() != ndim + 1:
+        raise ValueError(f"x must be [N_0, ...] or [B, N_0, ...] with {ndim} array dimensions")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
+    if not x[0].is_contiguous():
+        x = x.contiguous()
+    return x
+
+
+def _nd_call(fn, x, Ms, axes_arr, out, taps, stream):
+    torch = _torch()
+    B = x.shape[0]
+    shape = (B,) + tuple(Ms)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=x.device)
+    elif out.dtype != torch.complex64 or not out.is_cuda or tuple(out.shape) != shape or not out[0].is_contiguous():
+        raise ValueError(f"out must be a complex64 GPU tensor {list(shape)} with packed arrays")
+    o = _opts(x, taps=taps, stream=stream)
+    o.in_stride = x.stride(0) if B > 1 else x[0].numel()
+    o.out_stride = out.stride(0) if B > 1 else out[0].numel()
+    with torch.cuda.device(x.device):
+        _check(fn(x.data_ptr(), len(Ms), axes_arr, out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def czt_nd(x, axes, *, out=None, stream=None):
+    """X[k_0..k_{d-1}] = sum_n x[n] prod_a A_a^-n_a W_a^(k_a n_a) for every
+    array of x [B, N_0, ..., N_{d-1}] (or one array [N_0, ...]);
+    axes = [(M_a, W_a, A_a), ...], axis 0 first.  Returns [B, M_0, ...]."""
+    ndim = len(axes)
+    x = _arrays(x, ndim)
+    arr = (tz_czt_axis * ndim)()
+    Ms = []
+    for a, (M, W, A) in enumerate(axes):
+        W, A = complex(W), complex(A)
+        arr[a] = tz_czt_axis(x.shape[a + 1], int(M), tz_c64(W.real, W.imag), tz_c64(A.real, A.imag))
+        Ms.append(int(M))
+    return _nd_call(lib().czt_nd, x, Ms, arr, out, 0, stream)
+
+
+def zoom_fft_nd(x, axes, *, taps: int = 63, out=None, stream=None):
+    """Zoom FFT along every axis of x [B, N_0, ..., N_{d-1}];
+    axes = [(fs, f1, f2, M, D[, fc]), ...], axis 0 first (fc = cut-off in Hz,
+    default fs / (2 D)).  Returns [B, M_0, ...]."""
+    ndim = len(axes)
+    x = _arrays(x, ndim)
+    arr = (tz_zoom_axis * ndim)()
+    Ms = []
+    for a, ax in enumerate(axes):
+        fs, f1, f2, M, D = ax[:5]
+        fc = ax[5] if len(ax) > 5 and ax[5] is not None else 0.0
+        arr[a] = tz_zoom_axis(x.shape[a + 1], int(M), int(D), float(fs), float(f1), float(f2), float(fc))
+        Ms.append(int(M))
+    return _nd_call(lib().zoom_fft_nd, x, Ms, arr, out, int(taps), stream)
 
 
 # ---------------------------------------------------------------------------

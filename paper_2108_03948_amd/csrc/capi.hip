@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -95,7 +96,7 @@ struct BluePlan {
 
 struct ZoomPlan {
   std::shared_ptr<BluePlan> blue;
-  int64_t LD, K, D;
+  int64_t N, LD, K, D;
   int T;
   DevMem g, ph;
   Workspace u;
@@ -114,6 +115,7 @@ struct Device {
   std::map<std::string, std::shared_ptr<BluePlan>> blue;
   std::map<std::string, std::shared_ptr<ZoomPlan>> zoom;
   std::map<std::string, std::shared_ptr<PadPlan>> pad;
+  Workspace nd_t, nd_u;  // intermediates of the multi-dimensional transforms
 };
 
 std::mutex g_mu;
@@ -390,6 +392,151 @@ tz_status run_blue(Device &d, BluePlan &pl, const void *x, int in_kind, void *X,
   return TZ_OK;
 }
 
+// zoom arguments shared by zoom_fft and zoom_fft_nd; K = round(M fs / (D (f2 - f1)))
+tz_status check_zoom(double fs, double f1, double f2, int64_t M, int64_t D, int T, double fc, int64_t *K) {
+  if (M < 1 || D < 1) return fail(TZ_EINVAL, "M and D must be >= 1");
+  if (!isfinite(fs) || !isfinite(f1) || !isfinite(f2) || fs <= 0.0 || f2 <= f1)
+    return fail(TZ_EINVAL, "need finite fs > 0 and f2 > f1");
+  if (T < 1) return fail(TZ_EINVAL, "fir_taps must be >= 1");
+  if (!(fc > 0.0) || !isfinite(fc)) return fail(TZ_EINVAL, "fir_cutoff_hz must be > 0");
+  *K = zoom_short_length(fs, f1, f2, M, D);
+  if (*K < 1) return fail(TZ_EINVAL, "short-DFT length K = round(M fs / (D (f2 - f1))) is < 1");
+  return TZ_OK;
+}
+
+// zoom plan: FIR taps modulated to the band centre, mixing phasors, and the
+// short DFT as a CZT of the decimated sequence
+tz_status get_zoom(Device &d, int64_t N, double fs, double f1, double f2, int64_t M, int64_t D, int T, double fc,
+                   int64_t K, hipStream_t s, std::shared_ptr<ZoomPlan> *out) {
+  const int64_t LD = (N + D - 1) / D;
+  const double nuN = 0.5 * (f1 + f2) / fs;
+  char kb[200];
+  snprintf(kb, sizeof kb, "%lld/%lld/%lld/%d/%a/%a/%lld", (long long)N, (long long)M, (long long)D, T,
+           nuN - floor(nuN), fc / fs, (long long)K);
+  auto &zp = d.zoom[kb];
+  if (!zp) {
+    auto pl = std::make_shared<ZoomPlan>();
+    pl->N = N;
+    pl->LD = LD;
+    pl->K = K;
+    pl->D = D;
+    pl->T = T;
+    // short DFT: X[k] = sum_m u[m] e^{-j 2 pi (k - floor(M/2)) m / K}: a CZT with
+    // W = e^{-j 2 pi / K} and A = e^{-j 2 pi floor(M/2) / K} (rational, q = K)
+    const PhaseParams p = zoom_phase(K, M);
+    tz_status st = get_blue(d, LD, M, p, s, &pl->blue);
+    if (st) return st;
+    TZ_HIP(pl->g.alloc(sizeof(double2) * T), "zoom taps");
+    TZ_HIP(pl->ph.alloc(sizeof(double2) * LD), "zoom phasors");
+    TZ_HIP(build_zoom_tables(pl->g.as<double2>(), T, fc / fs, nuN - floor(nuN), pl->ph.as<double2>(), LD, D, s),
+           "zoom tables");
+    TZ_HIP(hipStreamSynchronize(s), "zoom tables");
+    zp = pl;
+  }
+  *out = zp;
+  return TZ_OK;
+}
+
+// front end (mix, FIR, decimate) into the plan's per-stream u, then the
+// short DFT into X; x holds c.B rows c.xs elements apart
+tz_status run_zoom(Device &d, ZoomPlan &z, const void *x, int in_kind, void *X, const Common &c) {
+  void *u = nullptr;
+  tz_status st = z.u.get(c.stream, sizeof(float2) * (size_t)z.LD * (size_t)c.B, &u);
+  if (st) return st;
+  ZoomFrontLaunch f;
+  f.x = x;
+  f.in_kind = in_kind;
+  f.xs = c.xs;
+  f.N = z.N;
+  f.D = z.D;
+  f.LD = z.LD;
+  f.T = z.T;
+  f.g = z.g.as<double2>();
+  f.ph = z.ph.as<double2>();
+  f.u = (float2 *)u;
+  f.B = c.B;
+  TZ_HIP(launch_zoom_front(f, c.stream), "zoom front-end launch");
+  Common c2 = c;
+  c2.xs = z.LD;
+  return run_blue(d, *z.blue, u, 2, X, c2, c.stream);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-dimensional transforms.  Pass p applies the 1-D transform of axis
+// d-1-p along the contiguous last axis of the current layout and a batched
+// transpose then moves the new last axis to the front:
+//   [..., N_a] -> transform -> [..., M_a] -> transpose -> [M_a, ...],
+// so after d passes the layout is [M_0, ..., M_{d-1}].  Arrays run in chunks
+// whose two intermediates stay near kNdChunkBytes each, so that a pass's
+// output and its transposed copy are read back from the last-level cache.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNdChunkBytes = (int64_t)64 << 20;
+
+// run(axis, in, in_kind, rows, in_row_stride, out, out_row_stride)
+using AxisRun = std::function<tz_status(int, const void *, int, int64_t, int64_t, float2 *, int64_t)>;
+
+tz_status run_nd(Device &d, int ndim, const int64_t *Ns, const int64_t *Ms, const void *x, void *X,
+                 const Common &c, const AxisRun &run) {
+  const int64_t esz = c.in_kind == 1 ? 8 : 4;
+  if (ndim == 1) return run(0, x, c.in_kind, c.B, c.xs, (float2 *)X, c.os);
+  int64_t NN = 1, maxsz = 0, sh[TZ_MAX_DIMS];
+  for (int i = 0; i < ndim; ++i) NN *= Ns[i];
+  for (int i = 0; i < ndim; ++i) sh[i] = Ns[i];
+  for (int p = 0; p < ndim; ++p) {
+    const int a = ndim - 1 - p;
+    int64_t R = 1;
+    for (int i = 0; i < ndim - 1; ++i) R *= sh[i];
+    maxsz = std::max(maxsz, R * Ms[a]);
+    for (int i = ndim - 1; i > 0; --i) sh[i] = sh[i - 1];
+    sh[0] = Ms[a];
+  }
+  int64_t nb = kNdChunkBytes / (8 * maxsz);
+  nb = std::max<int64_t>(1, std::min(nb, c.B));
+  // transpose workgroups: nb ceil(R/64) ceil(C/64) <= nb (R C / 4096 + (R + C) / 64 + 1), R C <= maxsz
+  if (nb * (maxsz / 4096 + maxsz / 32 + 1) >= ((int64_t)1 << 32))
+    return fail(TZ_EUNSUPPORTED, "multi-dimensional intermediate of %lld elements is too large", (long long)maxsz);
+  void *tp = nullptr, *up = nullptr;
+  tz_status st = d.nd_t.get(c.stream, sizeof(float2) * (size_t)(nb * maxsz), &tp);
+  if (st) return st;
+  if ((st = d.nd_u.get(c.stream, sizeof(float2) * (size_t)(nb * maxsz), &up))) return st;
+  float2 *T = (float2 *)tp, *U = (float2 *)up;
+  for (int64_t b0 = 0; b0 < c.B; b0 += nb) {
+    const int64_t n = std::min(nb, c.B - b0);
+    for (int i = 0; i < ndim; ++i) sh[i] = Ns[i];
+    const void *in = (const char *)x + b0 * c.xs * esz;
+    int kind = c.in_kind;
+    for (int p = 0; p < ndim; ++p) {
+      const int a = ndim - 1 - p;
+      const int64_t Na = sh[ndim - 1];
+      int64_t R = 1;
+      for (int i = 0; i < ndim - 1; ++i) R *= sh[i];
+      if (p == 0 && c.xs != NN && n > 1) {
+        // arrays not packed: each array's lines are uniform on their own
+        for (int64_t i = 0; i < n; ++i)
+          if ((st = run(a, (const char *)x + (b0 + i) * c.xs * esz, kind, R, Na, T + i * R * Ms[a], Ms[a])))
+            return st;
+      } else if ((st = run(a, in, kind, n * R, Na, T, Ms[a]))) {
+        return st;
+      }
+      const bool last = p == ndim - 1;
+      TransposeLaunch t;
+      t.y = T;
+      t.ys = R * Ms[a];
+      t.R = R;
+      t.C = Ms[a];
+      t.out = last ? (float2 *)X + b0 * c.os : U;
+      t.os = last ? c.os : R * Ms[a];
+      t.nb = n;
+      TZ_HIP(launch_transpose(t, c.stream), "transpose launch");
+      in = U;
+      kind = 2;
+      for (int i = ndim - 1; i > 0; --i) sh[i] = sh[i - 1];
+      sh[0] = Ms[a];
+    }
+  }
+  return TZ_OK;
+}
+
 int current_device() {
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -639,64 +786,110 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
 
 tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, int64_t M, int64_t D, void *X,
                    const tz_opts *o) {
-  if (M < 1 || D < 1) return fail(TZ_EINVAL, "M and D must be >= 1");
-  if (!isfinite(fs) || !isfinite(f1) || !isfinite(f2) || fs <= 0.0 || f2 <= f1)
-    return fail(TZ_EINVAL, "need finite fs > 0 and f2 > f1");
   const int T = (o && o->fir_taps) ? o->fir_taps : 63;
-  if (T < 1) return fail(TZ_EINVAL, "fir_taps must be >= 1");
   const double fc = (o && o->fir_cutoff_hz != 0.0) ? o->fir_cutoff_hz : fs / (2.0 * (double)D);
-  if (!(fc > 0.0) || !isfinite(fc)) return fail(TZ_EINVAL, "fir_cutoff_hz must be > 0");
-  const int64_t K = zoom_short_length(fs, f1, f2, M, D);
-  if (K < 1) return fail(TZ_EINVAL, "short-DFT length K = round(M fs / (D (f2 - f1))) is < 1");
-  Common c;
-  tz_status st = check_common(x, N, X, o, M, &c);
+  int64_t K = 0;
+  tz_status st = check_zoom(fs, f1, f2, M, D, T, fc, &K);
   if (st) return st;
+  Common c;
+  if ((st = check_common(x, N, X, o, M, &c))) return st;
   if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "zoom_fft runs in FP32 only");
-  const int64_t LD = (N + D - 1) / D;
-  const double nuN = 0.5 * (f1 + f2) / fs;
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
-  char kb[200];
-  snprintf(kb, sizeof kb, "%lld/%lld/%lld/%d/%a/%a/%lld", (long long)N, (long long)M, (long long)D, T,
-           nuN - floor(nuN), fc / fs, (long long)K);
-  auto &zp = d.zoom[kb];
-  if (!zp) {
-    auto pl = std::make_shared<ZoomPlan>();
-    pl->LD = LD;
-    pl->K = K;
-    pl->D = D;
-    pl->T = T;
-    // short DFT: X[k] = sum_m u[m] e^{-j 2 pi (k - floor(M/2)) m / K}: a CZT with
-    // W = e^{-j 2 pi / K} and A = e^{-j 2 pi floor(M/2) / K} (rational, q = K)
-    const PhaseParams p = zoom_phase(K, M);
-    if ((st = get_blue(d, LD, M, p, c.stream, &pl->blue))) return st;
-    TZ_HIP(pl->g.alloc(sizeof(double2) * T), "zoom taps");
-    TZ_HIP(pl->ph.alloc(sizeof(double2) * LD), "zoom phasors");
-    TZ_HIP(build_zoom_tables(pl->g.as<double2>(), T, fc / fs, nuN - floor(nuN), pl->ph.as<double2>(), LD, D,
-                             c.stream),
-           "zoom tables");
-    TZ_HIP(hipStreamSynchronize(c.stream), "zoom tables");
-    zp = pl;
+  std::shared_ptr<ZoomPlan> zp;
+  if ((st = get_zoom(d, N, fs, f1, f2, M, D, T, fc, K, c.stream, &zp))) return st;
+  return run_zoom(d, *zp, x, c.in_kind, X, c);
+}
+
+tz_status czt_nd(const void *x, int ndim, const tz_czt_axis *axes, void *X, const tz_opts *o) {
+  if (ndim < 1 || ndim > TZ_MAX_DIMS) return fail(TZ_EINVAL, "ndim must be 1 .. %d (got %d)", TZ_MAX_DIMS, ndim);
+  if (!axes) return fail(TZ_EINVAL, "axes must not be NULL");
+  int64_t Ns[TZ_MAX_DIMS], Ms[TZ_MAX_DIMS], NN = 1, MM = 1;
+  for (int a = 0; a < ndim; ++a) {
+    Ns[a] = axes[a].N;
+    Ms[a] = axes[a].M;
+    if (Ns[a] < 1 || Ms[a] < 1)
+      return fail(TZ_EINVAL, "axis %d: N and M must be >= 1 (got %lld, %lld)", a, (long long)Ns[a],
+                  (long long)Ms[a]);
+    if (!finite_nonzero(axes[a].W) || !finite_nonzero(axes[a].A))
+      return fail(TZ_EINVAL, "axis %d: W and A must be finite and non-zero", a);
+    if (Ns[a] > ((int64_t)1 << 31) || Ms[a] > ((int64_t)1 << 31))
+      return fail(TZ_EINVAL, "axis %d: N and M must be <= 2^31", a);
+    NN *= Ns[a];
+    MM *= Ms[a];
+    if (NN > ((int64_t)1 << 40) || MM > ((int64_t)1 << 40))
+      return fail(TZ_EINVAL, "arrays larger than 2^40 elements");
   }
-  ZoomPlan &z = *zp;
-  void *u = nullptr;
-  if ((st = z.u.get(c.stream, sizeof(float2) * (size_t)LD * (size_t)c.B, &u))) return st;
-  ZoomFrontLaunch f;
-  f.x = x;
-  f.in_kind = c.in_kind;
-  f.xs = c.xs;
-  f.N = N;
-  f.D = D;
-  f.LD = LD;
-  f.T = T;
-  f.g = z.g.as<double2>();
-  f.ph = z.ph.as<double2>();
-  f.u = (float2 *)u;
-  f.B = c.B;
-  TZ_HIP(launch_zoom_front(f, c.stream), "zoom front-end launch");
-  Common c2 = c;
-  c2.xs = LD;
-  return run_blue(d, *z.blue, u, 2, X, c2, c.stream);
+  Common c;
+  tz_status st = check_common(x, NN, X, o, MM, &c);
+  if (st) return st;
+  if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "multi-dimensional transforms run in FP32 only");
+  PhaseParams ps[TZ_MAX_DIMS];
+  for (int a = 0; a < ndim; ++a) {
+    const tz_c64 W = axes[a].W, A = axes[a].A;
+    PhaseParams p{};
+    p.a = frac01(atan2(A.im, A.re) / (2.0 * M_PI));
+    p.w = frac01(-atan2(W.im, W.re) / (2.0 * M_PI));
+    if (!unit(W) || !unit(A))
+      if ((st = spiral_scaling(Ns[a], Ms[a], log(hypot(A.re, A.im)), log(hypot(W.re, W.im)), &p))) return st;
+    ps[a] = p;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  std::shared_ptr<BluePlan> pl[TZ_MAX_DIMS];
+  for (int a = 0; a < ndim; ++a)
+    if ((st = get_blue(d, Ns[a], Ms[a], ps[a], c.stream, &pl[a]))) return st;
+  return run_nd(d, ndim, Ns, Ms, x, X, c,
+                [&](int a, const void *in, int kind, int64_t rows, int64_t is, float2 *out, int64_t os) {
+                  Common ca = c;
+                  ca.B = rows;
+                  ca.xs = is;
+                  ca.os = os;
+                  return run_blue(d, *pl[a], in, kind, out, ca, c.stream);
+                });
+}
+
+tz_status zoom_fft_nd(const void *x, int ndim, const tz_zoom_axis *axes, void *X, const tz_opts *o) {
+  if (ndim < 1 || ndim > TZ_MAX_DIMS) return fail(TZ_EINVAL, "ndim must be 1 .. %d (got %d)", TZ_MAX_DIMS, ndim);
+  if (!axes) return fail(TZ_EINVAL, "axes must not be NULL");
+  if (o && o->fir_cutoff_hz != 0.0)
+    return fail(TZ_EINVAL, "zoom_fft_nd takes its cut-offs per axis (tz_zoom_axis.fc); fir_cutoff_hz must be 0");
+  const int T = (o && o->fir_taps) ? o->fir_taps : 63;
+  int64_t Ns[TZ_MAX_DIMS], Ms[TZ_MAX_DIMS], Ks[TZ_MAX_DIMS], NN = 1, MM = 1;
+  double fcs[TZ_MAX_DIMS];
+  tz_status st;
+  for (int a = 0; a < ndim; ++a) {
+    const tz_zoom_axis &z = axes[a];
+    Ns[a] = z.N;
+    Ms[a] = z.M;
+    if (z.N < 1) return fail(TZ_EINVAL, "axis %d: N must be >= 1 (got %lld)", a, (long long)z.N);
+    fcs[a] = z.fc != 0.0 ? z.fc : z.fs / (2.0 * (double)z.D);
+    if ((st = check_zoom(z.fs, z.f1, z.f2, z.M, z.D, T, fcs[a], &Ks[a]))) return st;
+    if (Ns[a] > ((int64_t)1 << 31) || Ms[a] > ((int64_t)1 << 31))
+      return fail(TZ_EINVAL, "axis %d: N and M must be <= 2^31", a);
+    NN *= Ns[a];
+    MM *= Ms[a];
+    if (NN > ((int64_t)1 << 40) || MM > ((int64_t)1 << 40))
+      return fail(TZ_EINVAL, "arrays larger than 2^40 elements");
+  }
+  Common c;
+  if ((st = check_common(x, NN, X, o, MM, &c))) return st;
+  if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "multi-dimensional transforms run in FP32 only");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  std::shared_ptr<ZoomPlan> zp[TZ_MAX_DIMS];
+  for (int a = 0; a < ndim; ++a) {
+    const tz_zoom_axis &z = axes[a];
+    if ((st = get_zoom(d, z.N, z.fs, z.f1, z.f2, z.M, z.D, T, fcs[a], Ks[a], c.stream, &zp[a]))) return st;
+  }
+  return run_nd(d, ndim, Ns, Ms, x, X, c,
+                [&](int a, const void *in, int kind, int64_t rows, int64_t is, float2 *out, int64_t os) {
+                  Common ca = c;
+                  ca.B = rows;
+                  ca.xs = is;
+                  ca.os = os;
+                  return run_zoom(d, *zp[a], in, kind, out, ca);
+                });
 }
 
 // ---------------------------------------------------------------------------

@@ -165,7 +165,7 @@ hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s);
 // Zoom front end: u[b][m] = ph[m] sum_t g[t] x[b][mD - t], m < LD.
 struct ZoomFrontLaunch {
   const void *x;
-  int in_kind;
+  int in_kind;  // 0 = f32 real, 1 = f64 real, 2 = complex f32
   int64_t xs, N, D, LD;
   int T;
   const double2 *g, *ph;  // FP64 modulated taps and mixing phasors
@@ -173,6 +173,17 @@ struct ZoomFrontLaunch {
   int64_t B;
 };
 hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s);
+
+// Batched complex transpose: out[b][c][r] = y[b][r][c] (r < R, c < C), nb
+// matrices ys and os elements apart.  The host keeps nb * ceil(R/64) *
+// ceil(C/64) below 2^32.
+struct TransposeLaunch {
+  const float2 *y;
+  int64_t ys, R, C;
+  float2 *out;
+  int64_t os, nb;
+};
+hipError_t launch_transpose(const TransposeLaunch &a, hipStream_t s);
 
 bool fft_length_supported(int64_t L);
 

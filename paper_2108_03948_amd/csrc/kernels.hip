@@ -428,7 +428,10 @@ __global__ void __launch_bounds__(kZoomThreads)
     k_zoom_front(const void *__restrict__ x, int64_t xs, int64_t N, int64_t D, int64_t LD, int T,
                  const double2 *__restrict__ g, const double2 *__restrict__ ph, float2 *__restrict__ u,
                  int64_t bpt, int opb, int vec4) {
-  using XT = typename std::conditional<KIND == 1, double, float>::type;
+  // KIND 0 / 1: real f32 / f64 samples; KIND 2: complex f32 (later axes of
+  // a multi-dimensional zoom)
+  using XT = typename std::conditional<KIND == 1, double,
+                                       typename std::conditional<KIND == 2, float2, float>::type>::type;
   extern __shared__ double2 zsm[];
   double2 *gl = zsm;
   double2 *part = zsm + T;  // [S][256 / S] partial sums
@@ -443,7 +446,9 @@ __global__ void __launch_bounds__(kZoomThreads)
   // an offset above 2^31 (the host keeps N * sizeof(XT) below that), so both
   // read as 0 and the loads of a thread can all be in flight at once
   const Rsrc rx = make_rsrc((const XT *)x + b * xs, (uint64_t)N * sizeof(XT));
-  if (KIND == 0 && vec4) {
+  bool tiled = false;
+  if constexpr (KIND == 0) tiled = vec4 != 0;
+  if (tiled) {
     // 16-byte loads of 4 samples from a start floored to a multiple of 4: each
     // load lies wholly before 0, wholly inside [0, N) or wholly past N, except
     // the one holding sample N (when N % 4 != 0), loaded sample by sample
@@ -464,7 +469,9 @@ __global__ void __launch_bounds__(kZoomThreads)
       const float e4[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        if (i0 + c >= 0 && i0 + c < span) xl[zpad(i0 + c)] = (XT)e4[c];
+        if (i0 + c >= 0 && i0 + c < span) {
+          if constexpr (KIND == 0) xl[zpad(i0 + c)] = e4[c];
+        }
     }
   } else {
 #pragma unroll 8
@@ -472,6 +479,8 @@ __global__ void __launch_bounds__(kZoomThreads)
       const unsigned off = (unsigned)((n0 + i) * (int64_t)sizeof(XT));
       if constexpr (KIND == 1)
         xl[zpad(i)] = ld_f64(rx, off);
+      else if constexpr (KIND == 2)
+        xl[zpad(i)] = ld_c64(rx, off);
       else
         xl[zpad(i)] = ld_f32(rx, off);
     }
@@ -485,9 +494,15 @@ __global__ void __launch_bounds__(kZoomThreads)
   if (j < opb) {
 #pragma unroll 4
     for (int t = sidx; t < T; t += S) {
-      const double xv = (double)xl[zpad(top - t)];
-      ar = fma(gl[t].x, xv, ar);
-      ai = fma(gl[t].y, xv, ai);
+      if constexpr (KIND == 2) {
+        const float2 xv = xl[zpad(top - t)];
+        ar = fma(gl[t].x, (double)xv.x, fma(-gl[t].y, (double)xv.y, ar));
+        ai = fma(gl[t].x, (double)xv.y, fma(gl[t].y, (double)xv.x, ai));
+      } else {
+        const double xv = (double)xl[zpad(top - t)];
+        ar = fma(gl[t].x, xv, ar);
+        ai = fma(gl[t].y, xv, ai);
+      }
     }
   }
   part[threadIdx.x] = make_double2(ar, ai);
@@ -519,9 +534,15 @@ __global__ void __launch_bounds__(256)
   for (int t = 0; t < T; ++t) {
     const int64_t n = base - t;
     if (n >= 0 && n < N) {
-      const double xv = (double)load_real<KIND>(x, b * xs + n);
-      ar = fma(g[t].x, xv, ar);
-      ai = fma(g[t].y, xv, ai);
+      if constexpr (KIND == 2) {
+        const float2 xv = ((const float2 *)x)[b * xs + n];
+        ar = fma(g[t].x, (double)xv.x, fma(-g[t].y, (double)xv.y, ar));
+        ai = fma(g[t].x, (double)xv.y, fma(g[t].y, (double)xv.x, ai));
+      } else {
+        const double xv = (double)load_real<KIND>(x, b * xs + n);
+        ar = fma(g[t].x, xv, ar);
+        ai = fma(g[t].y, xv, ai);
+      }
     }
   }
   const double2 p = ph[m];
@@ -674,7 +695,7 @@ hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
   // LDS tile: T FP64 taps, the partial sums, and the samples of opb outputs,
   // within 64 KB
   constexpr int64_t kTileBytes = 64 * 1024;
-  const int64_t xb = a.in_kind == 1 ? 8 : 4;
+  const int64_t xb = a.in_kind == 0 ? 4 : 8;
   const int64_t fixed = 16 * (int64_t)a.T + 16 * kZoomThreads;
   const int S = a.T < 128 ? 1 : (a.T < 256 ? 2 : 4);
   int64_t opb = 0;
@@ -696,6 +717,8 @@ hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
     };
     if (a.in_kind == 1)
       S == 1 ? go(k_zoom_front<1, 1>) : (S == 2 ? go(k_zoom_front<1, 2>) : go(k_zoom_front<1, 4>));
+    else if (a.in_kind == 2)
+      S == 1 ? go(k_zoom_front<2, 1>) : (S == 2 ? go(k_zoom_front<2, 2>) : go(k_zoom_front<2, 4>));
     else
       S == 1 ? go(k_zoom_front<0, 1>) : (S == 2 ? go(k_zoom_front<0, 2>) : go(k_zoom_front<0, 4>));
     return hipGetLastError();
@@ -705,9 +728,51 @@ hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
   if (a.in_kind == 1)
     hipLaunchKernelGGL((k_zoom_front_global<1>), grid, block, 0, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph,
                        a.u, bpt);
+  else if (a.in_kind == 2)
+    hipLaunchKernelGGL((k_zoom_front_global<2>), grid, block, 0, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph,
+                       a.u, bpt);
   else
     hipLaunchKernelGGL((k_zoom_front_global<0>), grid, block, 0, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph,
                        a.u, bpt);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched complex transpose: out[b][c][r] = y[b][r][c] for r < R, c < C, the
+// matrices ys (input) and os (output) elements apart.  Each workgroup moves
+// one 64 x 64 tile through LDS, so that every wave reads and writes 512-byte
+// row segments; the pad column spreads the column reads over the banks.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 64;
+
+__global__ void __launch_bounds__(256)
+    k_transpose_c64(const float2 *__restrict__ y, int64_t ys, int64_t R, int64_t C, float2 *__restrict__ out,
+                    int64_t os, int64_t tr, int64_t tc) {
+  __shared__ float2 tile[kTile][kTile + 1];
+  const int64_t per = tr * tc;
+  const int64_t b = blockIdx.x / per, rem = blockIdx.x - b * per;
+  const int64_t r0 = rem / tc * kTile, c0 = rem % tc * kTile;
+  const int lx = threadIdx.x & (kTile - 1), ly = threadIdx.x / kTile;
+  const float2 *src = y + b * ys;
+#pragma unroll
+  for (int i = ly; i < kTile; i += 256 / kTile) {
+    const int64_t r = r0 + i, c = c0 + lx;
+    if (r < R && c < C) tile[i][lx] = src[r * C + c];
+  }
+  __syncthreads();
+  float2 *dst = out + b * os;
+#pragma unroll
+  for (int i = ly; i < kTile; i += 256 / kTile) {
+    const int64_t c = c0 + i, r = r0 + lx;
+    if (c < C && r < R) dst[c * R + r] = tile[lx][i];
+  }
+}
+
+hipError_t launch_transpose(const TransposeLaunch &a, hipStream_t s) {
+  const int64_t tr = (a.R + kTile - 1) / kTile, tc = (a.C + kTile - 1) / kTile;
+  const dim3 grid((unsigned)(a.nb * tr * tc)), block(256);
+  hipLaunchKernelGGL(k_transpose_c64, grid, block, 0, s, a.y, a.ys, a.R, a.C, a.out, a.os, tr, tc);
   return hipGetLastError();
 }
 

@@ -203,6 +203,41 @@ def echoes(B: int = 256, N: int = 1 << 20, fs: float = 100 * THZ, seed: int = 10
     return out.astype(dtype, copy=False)
 
 
+def raster(B: int, pixels, N: int, fs: float = 20 * THZ, t0: float = 15 * PS, seed: int = 1005,
+           snr_db: float = 60.0, dtype=np.float32) -> np.ndarray:
+    """THz images for the multi-dimensional transforms: B reflection raster
+    scans over `pixels` = (nx,) or (ny, nx) positions, [B, *pixels, N].  Each
+    pixel's trace is the reference pulse delayed by a surface-height map and
+    scaled by a reflectance map.  Per scan, with pixel coordinates p in
+    [0, 1) per axis: delay t0 + sum of 4 Gaussian bumps (centres U[0, 1],
+    widths U[0.05, 0.3], heights U[-1, 1] ps); reflectance
+    0.6 + 0.4 cos(2 pi (k . p + phi)) with k ~ U[2, 12] per axis (a grating)
+    and phi ~ U[0, 1); noise at snr_db per trace."""
+    rng = np.random.default_rng(seed)
+    pixels = tuple(int(v) for v in pixels)
+    d = len(pixels)
+    cen = rng.uniform(0.0, 1.0, (B, 4, d))
+    wid = rng.uniform(0.05, 0.3, (B, 4))
+    hgt = rng.uniform(-1.0, 1.0, (B, 4)) * PS
+    kv = rng.uniform(2.0, 12.0, (B, d))
+    phi = rng.uniform(0.0, 1.0, B)
+    noise_seeds = rng.integers(0, 2**63 - 1, B)
+    grids = np.meshgrid(*[np.arange(n) / n for n in pixels], indexing="ij")
+    P = np.stack([g.ravel() for g in grids], axis=-1)  # [npix, d]
+    t = np.arange(N) / fs
+    out = np.empty((B, P.shape[0], N), dtype=dtype)
+    for b in range(B):
+        r2 = ((P[:, None, :] - cen[b][None, :, :]) ** 2).sum(-1)  # [npix, 4]
+        tau = t0 + (hgt[b] * np.exp(-r2 / (2 * wid[b] ** 2))).sum(-1)
+        refl = 0.6 + 0.4 * np.cos(2 * np.pi * (P @ kv[b] + phi[b]))
+        nr = np.random.default_rng(noise_seeds[b])
+        for lo in range(0, P.shape[0], 256):
+            hi = min(P.shape[0], lo + 256)
+            rows = refl[lo:hi, None] * pulse(t[None, :] - tau[lo:hi, None])
+            out[b, lo:hi] = add_noise(rows, nr, snr_db)
+    return out.reshape((B,) + pixels + (N,))
+
+
 def uneven(B: int = 20000, fs: float = 20 * THZ, t0: float = 15 * PS, seed: int = 1003,
            Nmin: int = 512, Nmax: int = 16384, Mmin: int = 256, Mmax: int = 8192,
            taps: int = 63, snr_db: float = 60.0, dtype=np.float32):

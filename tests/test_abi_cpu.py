@@ -163,6 +163,68 @@ def test_invalid_arguments_rejected_before_device_work(tz):
     assert st == tz.TZ_EINVAL and "in_stride" in err
 
 
+def test_nd_invalid_arguments_rejected_before_device_work(tz):
+    L = tz.lib()
+    o = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(o))
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation
+    one = tz.tz_c64(1.0, 0.0)
+    w = tz.tz_c64(math.cos(0.1), -math.sin(0.1))
+
+    def czt_axes(*spec):
+        arr = (tz.tz_czt_axis * max(1, len(spec)))()
+        for i, (N, M, W) in enumerate(spec):
+            arr[i] = tz.tz_czt_axis(N, M, W, one)
+        return arr
+
+    def zoom_axes(*spec):
+        arr = (tz.tz_zoom_axis * len(spec))()
+        for i, sp in enumerate(spec):
+            arr[i] = tz.tz_zoom_axis(*sp)
+        return arr
+
+    good = czt_axes((16, 8, w), (12, 6, w))
+    cases = [
+        (L.czt_nd, (fake, 0, good, fake, ctypes.byref(o)), "ndim"),
+        (L.czt_nd, (fake, 4, czt_axes(*[(4, 4, w)] * 4), fake, ctypes.byref(o)), "ndim"),
+        (L.czt_nd, (fake, 2, None, fake, ctypes.byref(o)), "axes"),
+        (L.czt_nd, (None, 2, good, fake, ctypes.byref(o)), "NULL"),
+        (L.czt_nd, (fake, 2, czt_axes((16, 8, w), (12, 0, w)), fake, ctypes.byref(o)), "axis 1"),
+        (L.czt_nd, (fake, 2, czt_axes((0, 8, w), (12, 6, w)), fake, ctypes.byref(o)), "axis 0"),
+        (L.czt_nd, (fake, 2, czt_axes((16, 8, tz.tz_c64(0.0, 0.0)), (12, 6, w)), fake, ctypes.byref(o)),
+         "non-zero"),
+        (L.zoom_fft_nd, (fake, 2, zoom_axes((64, 16, 2, 20e12, 1e12, 2e12, 0.0), (64, 16, 0, 20e12, 1e12, 2e12, 0.0)),
+                         fake, ctypes.byref(o)), "D must be"),
+        (L.zoom_fft_nd, (fake, 1, zoom_axes((64, 16, 2, 20e12, 2e12, 1e12, 0.0)), fake, ctypes.byref(o)),
+         "f2 > f1"),
+        (L.zoom_fft_nd, (fake, 1, zoom_axes((64, 16, 2, 20e12, 1e12, 2e12, -1.0)), fake, ctypes.byref(o)),
+         "cutoff"),
+    ]
+    for fn, args, msg in cases:
+        st, err = _raw(tz, fn, *args)
+        assert st == tz.TZ_EINVAL, (fn.__name__, st, err)
+        assert msg in err, (fn.__name__, err)
+    # the cut-off is per axis
+    oc = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(oc))
+    oc.fir_cutoff_hz = 1e12
+    st, err = _raw(tz, L.zoom_fft_nd, fake, 1, zoom_axes((64, 16, 2, 20e12, 1e12, 2e12, 0.0)), fake,
+                   ctypes.byref(oc))
+    assert st == tz.TZ_EINVAL and "per axis" in err
+    # arrays closer together than their size
+    os_ = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(os_))
+    os_.batch, os_.in_stride = 3, 16 * 12 - 1
+    st, err = _raw(tz, L.czt_nd, fake, 2, good, fake, ctypes.byref(os_))
+    assert st == tz.TZ_EINVAL and "in_stride" in err
+    # split precision is refused
+    op = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(op))
+    op.precision = tz.TZ_SPLIT_BF16
+    st, err = _raw(tz, L.czt_nd, fake, 2, good, fake, ctypes.byref(op))
+    assert st == tz.TZ_EUNSUPPORTED and "FP32" in err
+
+
 def test_binding_refuses_cpu_tensors(tz):
     import torch
     with pytest.raises(TypeError):

@@ -432,3 +432,18 @@ def test_zoom_nd_tone_lands_in_predicted_bins(orc):
     X = orc.zoom_fft_nd(np.outer(*lines)[None], [a + (None,) for a in ax], taps=63)[0]
     k0, k1 = np.unravel_index(int(np.argmax(np.abs(X))), X.shape)
     assert (k0, k1) == (128 // 2 + 13, 96 // 2 - 9)
+
+
+def test_nd_bins_subset_is_the_full_grid_subset(orc):
+    # evaluating a grid of bins per axis (used for sampled checks of large
+    # arrays) picks exactly those entries of the full transform
+    rng = np.random.default_rng(36)
+    x = rng.standard_normal((2, 30, 40))
+    ax = [(25, _unit(rng), _unit(rng)), (33, _unit(rng), _unit(rng))]
+    b0, b1 = np.array([0, 7, 24]), np.array([32, 1, 5, 5])
+    full = orc.czt_nd(x, ax)
+    assert np.array_equal(orc.czt_nd(x, ax, bins=[b0, b1]), full[:, b0][:, :, b1])
+    zax = [(20e12, 0.4e12, 1.3e12, 30, 2, None), (10e12, 1.0e12, 2.5e12, 20, 1, None)]
+    zfull = orc.zoom_fft_nd(x, zax, taps=15)
+    assert np.array_equal(orc.zoom_fft_nd(x, zax, taps=15, bins=[b0, b1[:2] % 20]),
+                          zfull[:, b0][:, :, b1[:2] % 20])
