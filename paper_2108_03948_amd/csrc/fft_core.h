@@ -234,7 +234,7 @@ template <> struct FftShape<512>   { static constexpr int NT = 64;  using Plan =
 template <> struct FftShape<1024>  { static constexpr int NT = 64;  using Plan = Radices<16, 16, 4>; };
 template <> struct FftShape<2048>  { static constexpr int NT = 128; using Plan = Radices<16, 16, 8>; };
 template <> struct FftShape<4096>  { static constexpr int NT = 256; using Plan = Radices<16, 16, 16>; };
-template <> struct FftShape<8192>  { static constexpr int NT = 512; using Plan = Radices<16, 16, 16, 2>; };
+template <> struct FftShape<8192>  { static constexpr int NT = 512; using Plan = Radices<16, 2, 16, 16>; };
 template <> struct FftShape<16384> { static constexpr int NT = 1024; using Plan = Radices<16, 16, 16, 4>; };
 
 // A zero the optimiser cannot see through (empty asm on an SGPR).  Adding it

@@ -32,8 +32,10 @@ __device__ __forceinline__ float load_real(const void *__restrict__ x, int64_t i
 // With one segment and one block this is exactly eq. (15).  The inverse FFT
 // is the forward FFT of the conjugate, conjugated (1/L sits in V).
 // ---------------------------------------------------------------------------
+// SEG = false asks for four waves per SIMD (128 VGPRs): L = 8192 then runs
+// two workgroups per CU instead of one
 template <int L, int KIND, bool SEG>
-__global__ void __launch_bounds__(Fft<L>::NT)
+__global__ void __launch_bounds__(Fft<L>::NT, SEG ? 1 : 4)
     k_czt(const void *__restrict__ x, int64_t xs, int64_t N, int64_t Ns, int nseg,
           const float2 *__restrict__ c_pre, const float2 *__restrict__ c_post,
           const float2 *__restrict__ V, const float2 *__restrict__ tw, float2 *__restrict__ X,
@@ -86,7 +88,10 @@ __global__ void __launch_bounds__(Fft<L>::NT)
       v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * k)));
     }
     F::out_to_in(v);
-    F::forward(v, lds, t, twd);
+    // from L = 8192 up, a fresh copy of the thread index: the second
+    // transform recomputes its LDS addresses instead of keeping those of the
+    // first one live (fewer registers; shorter transforms run faster without)
+    F::forward(v, lds, L >= 8192 ? (int)(t + opaque_zero()) : (int)t, twd);
     const Rsrc rq = make_rsrc(c_post + ((int64_t)s * nblk + blk) * Mb, (uint64_t)kmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {

@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(ColFft<L1>::NT)
 // rows: Hc[b][k1][n2] = W_L^{k1 n2} FFT_L2( conj( V[k1 + L1 k2] FFT_L2( W_L^{k1 n2} Z[b][k1][.] ) ) )
 // ---------------------------------------------------------------------------
 template <int L1, int L2>
-__global__ void __launch_bounds__(Fft<L2>::NT)
+__global__ void __launch_bounds__(Fft<L2>::NT, 4)
     k_long_rows(float2 *__restrict__ Z, const float2 *__restrict__ Vt, const float2 *__restrict__ tw_row,
                 const float2 *__restrict__ tbig, int64_t nb) {
   using F = Fft<L2>;
@@ -184,7 +184,9 @@ __global__ void __launch_bounds__(Fft<L2>::NT)
     v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rv, 8 * k2)));
   }
   F::out_to_in(v);
-  F::forward(v, lds, t, twd);
+  // from L2 = 8192 up the second transform recomputes its LDS addresses
+  // (fewer live registers; four waves per SIMD fit)
+  F::forward(v, lds, L2 >= 8192 ? (int)(t + opaque_zero()) : (int)t, twd);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const unsigned n2 = t + NT * e;
