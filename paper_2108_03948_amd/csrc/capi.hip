@@ -170,8 +170,8 @@ tz_status get_roots(Device &d, int64_t Nfft, hipStream_t s, const float2 **out) 
 // blocks x segments of the single-pass form would transform more points than
 // one long FFT pair.
 int blue_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb, int *nblk, int *L1,
-               int64_t *Llong) {
-  const bool seg_ok = czt_shape(N, M, L, Ns, nseg, Mb, nblk);
+               int64_t *Llong, bool fast = false) {
+  const bool seg_ok = czt_shape(N, M, L, Ns, nseg, Mb, nblk, fast);
   if (seg_ok && *nseg == 1 && *nblk == 1) return 1;
   // smallest four-step length: a power of two (>= 2^17) or 5 * 2^a
   int64_t Lb = next_pow2(N + M - 1);
@@ -188,17 +188,19 @@ int blue_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb
       }
       break;
     }
-  if (long_ok && (!seg_ok || (int64_t)*nseg * *nblk * kMaxL > Lb)) {
+  if (long_ok && (!seg_ok || (int64_t)*nseg * *nblk * *L > Lb)) {
     *Llong = Lb;
     return 0;
   }
   return seg_ok ? 1 : -1;
 }
 
+// fast: bin blocks on a shorter FFT where they run faster (FP32 unit-circle
+// callers); otherwise one block whenever N + M - 1 fits one FFT
 tz_status get_blue(Device &d, int64_t N, int64_t M, const PhaseParams &p, hipStream_t s,
-                   std::shared_ptr<BluePlan> *out) {
+                   std::shared_ptr<BluePlan> *out, bool fast = false) {
   char kb[96];
-  snprintf(kb, sizeof kb, "%lld/%lld/", (long long)N, (long long)M);
+  snprintf(kb, sizeof kb, "%lld/%lld/%c/", (long long)N, (long long)M, fast ? 'f' : 'o');
   std::string key = std::string(kb) + phase_key(p);
   auto it = d.blue.find(key);
   if (it != d.blue.end()) {
@@ -210,7 +212,7 @@ tz_status get_blue(Device &d, int64_t N, int64_t M, const PhaseParams &p, hipStr
   pl->M = M;
   int L1 = 0;
   int64_t Llong = 0;
-  const int seg = blue_shape(N, M, &pl->L, &pl->Ns, &pl->nseg, &pl->Mb, &pl->nblk, &L1, &Llong);
+  const int seg = blue_shape(N, M, &pl->L, &pl->Ns, &pl->nseg, &pl->Mb, &pl->nblk, &L1, &Llong, fast);
   if (seg < 0)
     return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld: N + M - 1 exceeds the longest FFT (2^24)", (long long)N,
                 (long long)M);
@@ -424,7 +426,7 @@ tz_status get_zoom(Device &d, int64_t N, double fs, double f1, double f2, int64_
     // short DFT: X[k] = sum_m u[m] e^{-j 2 pi (k - floor(M/2)) m / K}: a CZT with
     // W = e^{-j 2 pi / K} and A = e^{-j 2 pi floor(M/2) / K} (rational, q = K)
     const PhaseParams p = zoom_phase(K, M);
-    tz_status st = get_blue(d, LD, M, p, s, &pl->blue);
+    tz_status st = get_blue(d, LD, M, p, s, &pl->blue, true);
     if (st) return st;
     TZ_HIP(pl->g.alloc(sizeof(double2) * T), "zoom taps");
     TZ_HIP(pl->ph.alloc(sizeof(double2) * LD), "zoom phasors");
@@ -631,7 +633,8 @@ tz_status czt(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *X, 
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
   std::shared_ptr<BluePlan> pl;
-  if ((st = get_blue(d, N, M, p, c.stream, &pl))) return st;
+  const bool fast = c.precision == TZ_FP32 && p.ma == 0.0 && p.mw == 0.0;
+  if ((st = get_blue(d, N, M, p, c.stream, &pl, fast))) return st;
   return run_blue(d, *pl, x, c.in_kind, X, c, c.stream);
 }
 
@@ -686,7 +689,7 @@ tz_status czt_band_exact(const void *x, int64_t N, int64_t M, int64_t fs_hz, int
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
   std::shared_ptr<BluePlan> pl;
-  if ((st = get_blue(d, N, M, p, c.stream, &pl))) return st;
+  if ((st = get_blue(d, N, M, p, c.stream, &pl, c.precision == TZ_FP32))) return st;
   return run_blue(d, *pl, x, c.in_kind, X, c, c.stream);
 }
 
@@ -733,7 +736,7 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
       p.pw = 1;
       p.a = 0.0;
       p.w = 1.0 / (double)nfft;
-      if ((st = get_blue(d, N, nfft, p, c.stream, &pl->blue))) return st;
+      if ((st = get_blue(d, N, nfft, p, c.stream, &pl->blue, true))) return st;
     }
     pp = pl;
   }
@@ -838,7 +841,8 @@ tz_status czt_nd(const void *x, int ndim, const tz_czt_axis *axes, void *X, cons
   Device &d = device_state(current_device());
   std::shared_ptr<BluePlan> pl[TZ_MAX_DIMS];
   for (int a = 0; a < ndim; ++a)
-    if ((st = get_blue(d, Ns[a], Ms[a], ps[a], c.stream, &pl[a]))) return st;
+    if ((st = get_blue(d, Ns[a], Ms[a], ps[a], c.stream, &pl[a], ps[a].ma == 0.0 && ps[a].mw == 0.0)))
+      return st;
   return run_nd(d, ndim, Ns, Ms, x, X, c,
                 [&](int a, const void *in, int kind, int64_t rows, int64_t is, float2 *out, int64_t os) {
                   Common ca = c;
@@ -935,7 +939,7 @@ tz_status czt_plan_shape(int64_t N, int64_t M, int64_t *L, int64_t *blocks) {
   if (N < 1 || M < 1 || !L || !blocks) return fail(TZ_EINVAL, "need N, M >= 1 and non-NULL outputs");
   int l, nseg, nblk, l1;
   int64_t ns, mb, llong;
-  const int k = blue_shape(N, M, &l, &ns, &nseg, &mb, &nblk, &l1, &llong);
+  const int k = blue_shape(N, M, &l, &ns, &nseg, &mb, &nblk, &l1, &llong, true);
   if (k < 0)
     return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld: N + M - 1 exceeds the longest FFT (2^24)", (long long)N,
                 (long long)M);

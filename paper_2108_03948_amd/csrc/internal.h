@@ -26,17 +26,48 @@ inline int64_t next_pow2(int64_t v) {
   return p;
 }
 
+// Relative time of one workgroup FFT pair of length L: about the same per
+// point up to 4096, about 1.35x per point at 8192 and 2.1x at 16384 (the
+// register and LDS pressure of the longest single-workgroup transforms).
+inline double fft_pair_cost(int64_t L) { return (double)L * (L <= 4096 ? 1.0 : (L <= 8192 ? 1.35 : 2.1)); }
+
+// Bin blocks of one segment on an FFT shorter than *L that cost less than
+// `cost`: blocks of at least 256 bins (narrower ones re-read the input too
+// often), at most 256 of them.  Updates *L, *Mb, *nblk when one is cheaper.
+inline void shorter_blocks(int64_t N, int64_t M, double cost, int *L, int64_t *Mb, int *nblk) {
+  const int64_t top = *L;
+  for (int64_t l = kMinL; l < top; l <<= 1) {
+    const int64_t mb = l - N + 1;
+    if (mb < 256) continue;
+    const int64_t nb = (M + mb - 1) / mb;
+    if (nb > 256) continue;
+    const double c = (double)nb * fft_pair_cost(l);
+    if (c < cost) {
+      cost = c;
+      *L = (int)l;
+      *Mb = mb;
+      *nblk = (int)nb;
+    }
+  }
+}
+
 // FFT length, bin blocks and input segments of the Bluestein path.
 // One workgroup FFT of length L <= kMaxL must hold Ns samples and Mb bins
-// without wrap-around: Ns + Mb - 1 <= L.  Returns false when more than 256
-// block x segment pieces would be needed.
-inline bool czt_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb, int *nblk) {
+// without wrap-around: Ns + Mb - 1 <= L.  Without `fast` the plan has one
+// block and one segment whenever N + M - 1 <= kMaxL (what the split-precision
+// kernel, spiral contours and the transfer kernel need); with `fast` bin
+// blocks on a shorter FFT are taken when fft_pair_cost says they run faster
+// (any L >= Ns + Mb - 1 gives the same bins).  Returns false when more than
+// 256 block x segment pieces would be needed.
+inline bool czt_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int64_t *Mb, int *nblk,
+                      bool fast = false) {
   if (N + M - 1 <= kMaxL) {
     *L = (int)(next_pow2(N + M - 1) < kMinL ? kMinL : next_pow2(N + M - 1));
     *Ns = N;
     *nseg = 1;
     *Mb = M;
     *nblk = 1;
+    if (fast) shorter_blocks(N, M, fft_pair_cost(*L), L, Mb, nblk);
     return true;
   }
   int64_t best = -1, bNs = 0, bMb = 0;
@@ -52,13 +83,31 @@ inline bool czt_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int6
     }
     if (ns >= N) break;
   }
-  if (best < 0 || best > 256) return false;
-  *L = kMaxL;
-  *Ns = bNs;
-  *nseg = (int)((N + bNs - 1) / bNs);
-  *Mb = bMb;
-  *nblk = (int)((M + bMb - 1) / bMb);
-  return true;
+  const bool ok = best >= 0 && best <= 256;
+  if (ok) {
+    *L = kMaxL;
+    *Ns = bNs;
+    *nseg = (int)((N + bNs - 1) / bNs);
+    *Mb = bMb;
+    *nblk = (int)((M + bMb - 1) / bMb);
+  }
+  if (fast) {
+    // segments accumulate in registers (a slower kernel): weigh them 1.3x
+    const double cost = ok ? (double)best * fft_pair_cost(kMaxL) * (*nseg > 1 ? 1.3 : 1.0) : 1e300;
+    int l = kMaxL;
+    int64_t mb = 0;
+    int nb = 0;
+    shorter_blocks(N, M, cost, &l, &mb, &nb);
+    if (l != kMaxL) {
+      *L = l;
+      *Ns = N;
+      *nseg = 1;
+      *Mb = mb;
+      *nblk = nb;
+      return true;
+    }
+  }
+  return ok;
 }
 
 // phase parameters of a CZT over [f1, f2) with M bins, integer hertz:

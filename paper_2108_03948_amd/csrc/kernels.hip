@@ -52,7 +52,10 @@ __global__ void __launch_bounds__(Fft<L>::NT, SEG ? 1 : 4)
   const int64_t b = blockIdx.x / nblk;
   const int blk = blockIdx.x % nblk;
   const int64_t k0 = (int64_t)blk * Mb;
-  const int64_t kmax = (M - k0 < Mb) ? (M - k0) : Mb;  // bins of this block
+  // a block wholly past the bins asked for (M below the plan's bin count)
+  // has nothing to write: the whole workgroup leaves before any barrier
+  if (k0 >= M) return;
+  const int64_t kmax = (M - k0 < Mb) ? (M - k0) : Mb;  // bins of this block, >= 1
   const auto twd = [&]() {
     if constexpr (kHalf)
       return load_half_twiddles<L>(twl, tw, t, NT);

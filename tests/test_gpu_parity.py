@@ -121,6 +121,41 @@ def test_czt_segments_and_blocks(tz, dev, orc, N, M):
     assert_close(X, orc.czt(x.astype(np.float64), M, W, A), what=f"czt seg N={N} M={M}")
 
 
+@pytest.mark.parametrize("N,M", [(683, 4096), (1000, 8000), (200, 16000), (100, 100000), (3000, 15000)])
+def test_czt_bin_blocks_on_shorter_ffts(tz, dev, orc, N, M):
+    """Shapes whose FP32 plan splits the bins into blocks on a shorter FFT
+    (the Bluestein length is free as long as it holds N + Mb - 1 points)."""
+    rng = np.random.default_rng(N + 3 * M)
+    x = rng.standard_normal((3, N)).astype(np.float32)
+    W = np.exp(-2j * np.pi * 0.37 / M)
+    A = np.exp(2j * np.pi * 0.0123)
+    L, blocks = tz.czt_plan_shape(N, M)
+    say(f"case: czt N={N} M={M} plan L={L} blocks={blocks}")
+    assert blocks > 1 and L < 16384
+    X = tz.czt(to_dev(x, dev), M, W, A).cpu().numpy()
+    assert_close(X, orc.czt(x.astype(np.float64), M, W, A), what=f"czt blocks N={N} M={M}")
+
+
+def test_fft_zeropad_half_spectrum_with_bin_blocks_stays_in_rows(tz, dev, orc):
+    """N_fft = 30001 has no power-of-two factor >= N: its bins come from a
+    blocked Bluestein plan, of which TZ_HALF needs the first 15001 only.
+    Blocks past them write nothing: the padding between output rows keeps
+    its sentinel."""
+    import torch
+    N, nz = 1000, 29001
+    nout = (N + nz) // 2 + 1
+    rng = np.random.default_rng(77)
+    x = rng.standard_normal((3, N)).astype(np.float32)
+    full = torch.full((3, nout + 4096), complex(7.0, -7.0), dtype=torch.complex64, device=dev)
+    out = full[:, :nout]
+    say(f"case: fft_zeropad half N={N} Nfft={N + nz} plan {tz.czt_plan_shape(N, N + nz)}, padded rows")
+    tz.fft_zeropad(to_dev(x, dev), nz, half=True, out=out)
+    f = full.cpu().numpy()
+    assert np.all(f[:, nout:] == np.complex64(complex(7.0, -7.0)))
+    assert_close(f[:, :nout], orc.fft_zeropad(x.astype(np.float64), nz, np.arange(nout)),
+                 what="fft half, blocked plan")
+
+
 @pytest.mark.parametrize("N,nz,half", [(1, 0, False), (100, 156, False), (1000, 1048, False),
                                        (1024, 15360, False), (300, 212, True), (1000, 537, False),
                                        (4096, 61440, True), (5000, 11384, False), (2048, 30720, False),
