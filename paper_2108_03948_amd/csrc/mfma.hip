@@ -206,7 +206,7 @@ struct MfmaFft {
 // Bluestein CZT with split-precision radix-16 passes (single bin block,
 // single segment, real input).  Same tables and algebra as k_czt.
 template <int L, int PREC, int KIND>
-__global__ void __launch_bounds__(L / 16)
+__global__ void __launch_bounds__(L / 16, 4)
     k_czt_mfma(const void *__restrict__ x, int64_t xs, int64_t N, const float2 *__restrict__ c_pre,
                const float2 *__restrict__ c_post, const float2 *__restrict__ V, const float2 *__restrict__ tw,
                float2 *__restrict__ X, int64_t os, int64_t M) {
@@ -259,19 +259,22 @@ __global__ void __launch_bounds__(L / 16)
 #pragma unroll
   for (int e = 0; e < E; ++e) lds[lds_idx(t + NT * e)] = v[MF::out_slot(e)];
   __syncthreads();
+  // fresh copies of the thread indices: the second transform recomputes its
+  // LDS addresses instead of keeping those of the first one live
+  const int t2 = (int)(t + opaque_zero()), wave2 = t2 / 64, lane2 = t2 % 64, h2 = lane2 / 32;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
-    const int j = 64 * wave + 32 * g + lane % 32;
+    const int j = 64 * wave2 + 32 * g + lane2 % 32;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) xin[g][q] = lds[lds_idx(j + (8 * h + q) * Q)];
+    for (int q = 0; q < 8; ++q) xin[g][q] = lds[lds_idx(j + (8 * h2 + q) * Q)];
   }
-  mf.template pass<0>(xin, v, lds, wave, lane, twd);
-  mf.template pass<1>(xin, v, lds, wave, lane, twd);
-  mf.template pass<2>(xin, v, lds, wave, lane, twd);
+  mf.template pass<0>(xin, v, lds, wave2, lane2, twd);
+  mf.template pass<1>(xin, v, lds, wave2, lane2, twd);
+  mf.template pass<2>(xin, v, lds, wave2, lane2, twd);
   mf.trailing(v, twd);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const unsigned k = (unsigned)(t + NT * e);
+    const unsigned k = (unsigned)(t2 + NT * e);
     st_c64(cmul(cconj(v[MF::out_slot(e)]), ld_c64(rq, 8 * k)), rX, 8 * k);
   }
 }
