@@ -17,7 +17,7 @@ import os
 import sys
 
 KERNEL_KEYS = {"czt": "k_czt<8192, 0", "fft_zeropad": "k_fftpad", "zoom_front": "k_zoom_front",
-               "zoom_short_dft": "k_czt<8192, 2"}
+               "zoom_short_dft": "k_czt<2048, 2"}
 
 
 def stats(path, out, cmd):

@@ -420,18 +420,26 @@ __global__ void __launch_bounds__(64 * P)
 // accumulated in FP64: an FP32 accumulator rounds at every step and its error
 // grows like sqrt(T) relative to |u|, which a narrow output band magnifies.
 //
-// Workgroup (b, m0) stages x[m0 D - (T-1) .. (m0 + opb - 1) D] and the taps
-// in LDS; thread j forms output m0 + j.  One pad slot every 64 samples puts
-// the stride-D reads of a wave on different banks.
+// Workgroup (b, m0) stages x[m0 D - (T-1) .. (m0 + opb - 1) D] in LDS;
+// thread j forms output m0 + j.  The lanes of a wave read samples D apart:
+// when D is a multiple of 8 (many lanes on one bank) one pad slot every 64
+// samples spreads them over the banks (PAD); otherwise the tile is linear and
+// the per-tap offsets fold into the LDS instructions.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int zpad(int i) { return i + (i >> 6); }
+template <bool PAD>
+__device__ __forceinline__ int zpad(int i) {
+  if constexpr (PAD)
+    return i + (i >> 6);
+  else
+    return i;
+}
 
 constexpr int kZoomThreads = 256;
 
 // S = split waves per output: 256/S outputs per workgroup (one per lane of S
 // groups); group s sums the taps t = s mod S, so a long filter runs as S
 // shorter dependent chains.
-template <int KIND, int S>
+template <int KIND, int S, bool PAD>
 __global__ void __launch_bounds__(kZoomThreads)
     k_zoom_front(const void *__restrict__ x, int64_t xs, int64_t N, int64_t D, int64_t LD, int T,
                  const double2 *__restrict__ g, const double2 *__restrict__ ph, float2 *__restrict__ u,
@@ -441,15 +449,13 @@ __global__ void __launch_bounds__(kZoomThreads)
   using XT = typename std::conditional<KIND == 1, double,
                                        typename std::conditional<KIND == 2, float2, float>::type>::type;
   extern __shared__ double2 zsm[];
-  double2 *gl = zsm;
-  double2 *part = zsm + T;  // [S][256 / S] partial sums
+  double2 *part = zsm;  // [S][256 / S] partial sums
   XT *xl = (XT *)(part + kZoomThreads);
   constexpr int nout = kZoomThreads / S;
   const int64_t b = blockIdx.x / bpt;
   const int64_t m0 = (blockIdx.x % bpt) * opb;
   const int64_t n0 = m0 * D - (T - 1);
   const int span = (opb - 1) * (int)D + T;
-  for (int i = threadIdx.x; i < T; i += blockDim.x) gl[i] = g[i];
   // unconditional buffer loads: n >= N is past the extent, and n < 0 wraps to
   // an offset above 2^31 (the host keeps N * sizeof(XT) below that), so both
   // read as 0 and the loads of a thread can all be in flight at once
@@ -462,54 +468,65 @@ __global__ void __launch_bounds__(kZoomThreads)
     // the one holding sample N (when N % 4 != 0), loaded sample by sample
     const int64_t n0a = n0 & ~(int64_t)3;
     const int nq = (int)((n0 + span - n0a + 3) >> 2);
-    using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rx, 0, 0, 0));
-#pragma unroll 4
-    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
-      const int64_t sn = n0a + 4 * q;
-      float4 w;
-      if (sn < 0 || sn >= N || sn + 3 < N) {
-        w = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(unsigned)(sn * 4), 0, 0));
-      } else {
-        w = make_float4(ld_f32(rx, (unsigned)(sn * 4)), ld_f32(rx, (unsigned)(sn * 4 + 4)),
-                        ld_f32(rx, (unsigned)(sn * 4 + 8)), ld_f32(rx, (unsigned)(sn * 4 + 12)));
-      }
-      const int i0 = (int)(sn - n0);  // tile index of sample sn (may be < 0 for the first load)
-      const float e4[4] = {w.x, w.y, w.z, w.w};
+    constexpr int kBatch = 4;  // loads of a thread in flight before any is used
+    for (int q0 = threadIdx.x; q0 < nq; q0 += kBatch * kZoomThreads) {
+      float4 w[kBatch];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (i0 + c >= 0 && i0 + c < span) {
-          if constexpr (KIND == 0) xl[zpad(i0 + c)] = e4[c];
-        }
+      for (int u = 0; u < kBatch; ++u) {
+        const int64_t sn = n0a + 4 * (int64_t)(q0 + u * kZoomThreads);  // past nq: n >= N, reads 0
+        w[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(unsigned)(sn * 4), 0, 0));
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int q = q0 + u * kZoomThreads;
+        if (q >= nq) break;
+        const int64_t sn = n0a + 4 * (int64_t)q;
+        if (sn < N && sn + 3 >= N)  // the quad holding sample N - 1 and the end
+          w[u] = make_float4(ld_f32(rx, (unsigned)(sn * 4)), ld_f32(rx, (unsigned)(sn * 4 + 4)),
+                             ld_f32(rx, (unsigned)(sn * 4 + 8)), ld_f32(rx, (unsigned)(sn * 4 + 12)));
+        const int i0 = (int)(sn - n0);  // tile index of sample sn (may be < 0 for the first load)
+        const float e4[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (i0 + c >= 0 && i0 + c < span) {
+            if constexpr (KIND == 0) xl[zpad<PAD>(i0 + c)] = e4[c];
+          }
+      }
     }
   } else {
 #pragma unroll 8
     for (int i = threadIdx.x; i < span; i += blockDim.x) {
       const unsigned off = (unsigned)((n0 + i) * (int64_t)sizeof(XT));
       if constexpr (KIND == 1)
-        xl[zpad(i)] = ld_f64(rx, off);
+        xl[zpad<PAD>(i)] = ld_f64(rx, off);
       else if constexpr (KIND == 2)
-        xl[zpad(i)] = ld_c64(rx, off);
+        xl[zpad<PAD>(i)] = ld_c64(rx, off);
       else
-        xl[zpad(i)] = ld_f32(rx, off);
+        xl[zpad<PAD>(i)] = ld_f32(rx, off);
     }
   }
   __syncthreads();
   // thread j of group s: output m0 + j, taps t = s, s + S, ...; the lanes of
-  // a wave read stride-D samples, spread over the banks by the pad
-  const int j = threadIdx.x % nout, sidx = threadIdx.x / nout;
+  // a wave read stride-D samples, spread over the banks by the pad.  A group
+  // spans whole waves (256 / S >= 64 lanes), so the tap index is the same
+  // across a wave and the taps come through scalar loads (one read per wave
+  // instead of one LDS read per lane)
+  const int j = threadIdx.x % nout;
+  const int sidx = __builtin_amdgcn_readfirstlane(threadIdx.x / nout);
   const int top = j * (int)D + T - 1;  // tile index of x[(m0 + j) D]
   double ar = 0.0, ai = 0.0;
   if (j < opb) {
 #pragma unroll 4
     for (int t = sidx; t < T; t += S) {
+      const double2 gt = g[t];
       if constexpr (KIND == 2) {
-        const float2 xv = xl[zpad(top - t)];
-        ar = fma(gl[t].x, (double)xv.x, fma(-gl[t].y, (double)xv.y, ar));
-        ai = fma(gl[t].x, (double)xv.y, fma(gl[t].y, (double)xv.x, ai));
+        const float2 xv = xl[zpad<PAD>(top - t)];
+        ar = fma(gt.x, (double)xv.x, fma(-gt.y, (double)xv.y, ar));
+        ai = fma(gt.x, (double)xv.y, fma(gt.y, (double)xv.x, ai));
       } else {
-        const double xv = (double)xl[zpad(top - t)];
-        ar = fma(gl[t].x, xv, ar);
-        ai = fma(gl[t].y, xv, ai);
+        const double xv = (double)xl[zpad<PAD>(top - t)];
+        ar = fma(gt.x, xv, ar);
+        ai = fma(gt.y, xv, ai);
       }
     }
   }
@@ -700,11 +717,10 @@ hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s) {
 }
 
 hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
-  // LDS tile: T FP64 taps, the partial sums, and the samples of opb outputs,
-  // within 64 KB
+  // LDS tile: the partial sums and the samples of opb outputs, within 64 KB
   constexpr int64_t kTileBytes = 64 * 1024;
   const int64_t xb = a.in_kind == 0 ? 4 : 8;
-  const int64_t fixed = 16 * (int64_t)a.T + 16 * kZoomThreads;
+  const int64_t fixed = 16 * kZoomThreads;
   const int S = a.T < 128 ? 1 : (a.T < 256 ? 2 : 4);
   int64_t opb = 0;
   if (fixed + xb * (a.T + a.T / 64 + 1) <= kTileBytes && a.N * xb < ((int64_t)1 << 31)) {
@@ -723,12 +739,17 @@ hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
       hipLaunchKernelGGL(kernel, grid, block, shm, s, a.x, a.xs, a.N, a.D, a.LD, a.T, a.g, a.ph, a.u, bpt,
                          (int)opb, vec4);
     };
+    auto by_s = [&](auto k1, auto k2, auto k4) { S == 1 ? go(k1) : (S == 2 ? go(k2) : go(k4)); };
+    const bool pad = a.D % 8 == 0;
     if (a.in_kind == 1)
-      S == 1 ? go(k_zoom_front<1, 1>) : (S == 2 ? go(k_zoom_front<1, 2>) : go(k_zoom_front<1, 4>));
+      pad ? by_s(k_zoom_front<1, 1, true>, k_zoom_front<1, 2, true>, k_zoom_front<1, 4, true>)
+          : by_s(k_zoom_front<1, 1, false>, k_zoom_front<1, 2, false>, k_zoom_front<1, 4, false>);
     else if (a.in_kind == 2)
-      S == 1 ? go(k_zoom_front<2, 1>) : (S == 2 ? go(k_zoom_front<2, 2>) : go(k_zoom_front<2, 4>));
+      pad ? by_s(k_zoom_front<2, 1, true>, k_zoom_front<2, 2, true>, k_zoom_front<2, 4, true>)
+          : by_s(k_zoom_front<2, 1, false>, k_zoom_front<2, 2, false>, k_zoom_front<2, 4, false>);
     else
-      S == 1 ? go(k_zoom_front<0, 1>) : (S == 2 ? go(k_zoom_front<0, 2>) : go(k_zoom_front<0, 4>));
+      pad ? by_s(k_zoom_front<0, 1, true>, k_zoom_front<0, 2, true>, k_zoom_front<0, 4, true>)
+          : by_s(k_zoom_front<0, 1, false>, k_zoom_front<0, 2, false>, k_zoom_front<0, 4, false>);
     return hipGetLastError();
   }
   const int64_t bpt = (a.LD + 255) / 256;
