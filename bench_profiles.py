@@ -2,7 +2,7 @@
 
   python bench_profiles.py stats <kernel_stats.csv> <out.md> "<command>"
   python bench_profiles.py traffic <fetch_counter.csv> <write_counter.csv> <out.json> "<cmd>"
-  python bench_profiles.py kernel-traffic <fetch_counter.csv> <write_counter.csv> <kernel_stats.csv>
+  python bench_profiles.py kernel-traffic <fetch_counter.csv> <write_counter.csv> <kernel_trace.csv>
          <calibration.json> <out.md> "<cmd>" <name-substring> ...
 
 Byte counters are scaled by what the same counters read for the 1 GiB device
@@ -16,8 +16,13 @@ import json
 import os
 import sys
 
-KERNEL_KEYS = {"czt": "k_czt<8192, 0", "fft_zeropad": "k_fftpad", "zoom_front": "k_zoom_front",
-               "zoom_short_dft": "k_czt<2048, 2"}
+# bench dispatches: (kernel-name substring, grid size in work-items or None);
+# the grid tells the timed 8192 x 4096 launches from the same kernels' use in
+# the multi-dimensional transforms
+KERNEL_KEYS = {"czt": ("k_czt<8192, 0, false>", 4194304), "fft_zeropad": ("k_fftpad_real<2048, 16, 0>", None),
+               "zoom_front": ("k_zoom_front<0, 1, false>", 6291456),
+               "zoom_short_dft": ("k_czt<2048, 2, false>", 3145728),
+               "transpose_2d_scans": ("k_transpose_c64", 524288), "transpose_3d_cube": ("k_transpose_c64", 2097152)}
 
 
 def stats(path, out, cmd):
@@ -51,9 +56,9 @@ def traffic(fetch_csv, write_csv, out, cmd, source_hash):
            "calibration": {"copy_bytes": 1 << 30, "fetch_kib": copy_f[2], "write_kib": copy_w[2],
                            "fetch_scale": sf, "write_scale": sw},
            "kernels": {}}
-    for name, key in KERNEL_KEYS.items():
-        fv = [x[2] for x in f if key in x[0]]
-        wv = [x[2] for x in w if key in x[0]]
+    for name, (key, grid) in KERNEL_KEYS.items():
+        fv = [x[2] for x in f if key in x[0] and grid in (None, x[1])]
+        wv = [x[2] for x in w if key in x[0] and grid in (None, x[1])]
         if fv and wv:
             fb = sum(fv) / len(fv) * 1024 * sf
             wb = sum(wv) / len(wv) * 1024 * sw
@@ -68,21 +73,31 @@ def kernel_traffic(fetch_csv, write_csv, stats_csv, calib_json, out, cmd, keys):
     cal = json.load(open(calib_json))["calibration"]
     f = _per_dispatch(fetch_csv, "FETCH_SIZE")
     w = _per_dispatch(write_csv, "WRITE_SIZE")
-    dur = {r["Name"].split("(")[0]: float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    # average duration per (kernel, grid size) from the kernel trace
+    acc = {}
+    for r in csv.DictReader(open(stats_csv)):
+        key = (r["Kernel_Name"].split("(")[0],
+               int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+        a = acc.setdefault(key, [0.0, 0])
+        a[0] += float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        a[1] += 1
+    dur = {k: v[0] / v[1] for k, v in acc.items()}
     lines = ["# HBM traffic per dispatch", "", f"Command (counters, one run per counter):\n\n    {cmd}\n",
              f"Scaled by the 1 GiB copy calibration of `profiles/traffic.json` (FETCH x{cal['fetch_scale']:.3f}, "
-             f"WRITE x{cal['write_scale']:.3f}); durations from the kernel-trace run of the same command.", "",
-             "| kernel | dispatches | fetch (MB) | write (MB) | average (us) | GB/s |", "|---|---|---|---|---|---|"]
-    names = sorted({x[0].split("(")[0] for x in f if any(k in x[0] for k in keys)})
-    for name in names:
-        fv = [x[2] for x in f if x[0].split("(")[0] == name]
-        wv = [x[2] for x in w if x[0].split("(")[0] == name]
-        if not fv or not wv or name not in dur:
+             f"WRITE x{cal['write_scale']:.3f}); durations from the kernel-trace run of the same command, "
+             "per kernel and grid size (work-items).", "",
+             "| kernel | grid | dispatches | fetch (MB) | write (MB) | average (us) | GB/s |",
+             "|---|---|---|---|---|---|---|"]
+    groups = sorted({(x[0].split("(")[0], x[1]) for x in f if any(k in x[0] for k in keys)})
+    for name, grid in groups:
+        fv = [x[2] for x in f if x[0].split("(")[0] == name and x[1] == grid]
+        wv = [x[2] for x in w if x[0].split("(")[0] == name and x[1] == grid]
+        if not fv or not wv or (name, grid) not in dur:
             continue
         fb = sum(fv) / len(fv) * 1024 * cal["fetch_scale"]
         wb = sum(wv) / len(wv) * 1024 * cal["write_scale"]
-        us = dur[name] / 1e3
-        lines.append(f"| `{name}` | {len(fv)} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {us:.1f} | "
+        us = dur[(name, grid)] / 1e3
+        lines.append(f"| `{name}` | {grid} | {len(fv)} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {us:.1f} | "
                      f"{(fb + wb) / (us * 1e-6) / 1e9:.0f} |")
     open(out, "w").write("\n".join(lines) + "\n")
 

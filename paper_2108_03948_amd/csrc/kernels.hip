@@ -85,10 +85,12 @@ __global__ void __launch_bounds__(Fft<L>::NT, SEG ? 1 : 4)
         v[F::in_slot(e)] = cscale(c, ld_real<KIND>(rx, n));
     }
     F::forward(v, lds, t, twd);
+    // from L = 8192 up the spectrum's offsets are recomputed too (the V
+    // loads otherwise pin the first transform's index registers: spills)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const unsigned k = t + NT * e;
-      v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * k)));
+      v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * (L >= 8192 ? k + opaque_zero() : k))));
     }
     F::out_to_in(v);
     // from L = 8192 up, a fresh copy of the thread index: the second
@@ -473,8 +475,11 @@ __global__ void __launch_bounds__(kZoomThreads)
       float4 w[kBatch];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        const int64_t sn = n0a + 4 * (int64_t)(q0 + u * kZoomThreads);  // past nq: n >= N, reads 0
-        w[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(unsigned)(sn * 4), 0, 0));
+        // quads past the tile take an offset beyond the extent: they read 0
+        // with no memory request
+        const int q = q0 + u * kZoomThreads;
+        const unsigned off = q < nq ? (unsigned)((n0a + 4 * (int64_t)q) * 4) : 0xFFFFFFF0u;
+        w[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)off, 0, 0));
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
