@@ -169,27 +169,65 @@ __global__ void k_batch_reset(unsigned *counters, int n) {
 
 // zoom front end for every zoom job (one workgroup per job):
 // u[m] = e^{-j 2 pi nu_N m D} sum_t g[t] x[mD - t], FP64 taps, phasors and
-// sums (the T-term sum in FP32 would lose accuracy as sqrt(T))
+// sums (the T-term sum in FP32 would lose accuracy as sqrt(T)).  The job's
+// samples pass through an LDS tile in chunks of opb outputs (coalesced loads,
+// zeros outside [0, N), one pad slot every 64 samples against the stride-D
+// reads); the tap index is the same across the wave, so the taps come
+// through scalar loads.  Filters longer than half the tile read x and the
+// taps straight from global memory.
+constexpr int kBZTile = 8192;  // samples per chunk
+
 __global__ void __launch_bounds__(256)
     k_batch_zoom_front(const float *__restrict__ x, float2 *__restrict__ u, const float2 *__restrict__ arena,
                        const ZoomJob *__restrict__ jobs) {
+  __shared__ float xl[kBZTile + kBZTile / 64 + 1];
   const ZoomJob j = jobs[blockIdx.x];
   const double2 *g = (const double2 *)(arena + j.g_off);
   const double2 *ph = (const double2 *)(arena + j.ph_off);
   const float *xb = x + j.x_off;
-  for (int m = threadIdx.x; m < j.LD; m += 256) {
-    const int64_t base = (int64_t)m * j.D;
-    double ar = 0.0, ai = 0.0;
-    for (int tt = 0; tt < j.T; ++tt) {
-      const int64_t n = base - tt;
-      if (n >= 0 && n < j.N) {
-        const double xv = (double)xb[n];
-        ar = fma(g[tt].x, xv, ar);
-        ai = fma(g[tt].y, xv, ai);
+  const int D = j.D, T = j.T, N = j.N, LD = j.LD;
+  if (2 * T > kBZTile) {
+    for (int m = threadIdx.x; m < LD; m += 256) {
+      const int64_t base = (int64_t)m * D;
+      double ar = 0.0, ai = 0.0;
+      for (int tt = 0; tt < T; ++tt) {
+        const int64_t n = base - tt;
+        if (n >= 0 && n < N) {
+          const double xv = (double)xb[n];
+          ar = fma(g[tt].x, xv, ar);
+          ai = fma(g[tt].y, xv, ai);
+        }
       }
+      const double2 p = ph[m];
+      u[j.u_off + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));
     }
-    const double2 p = ph[m];
-    u[j.u_off + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));
+    return;
+  }
+  // outputs per chunk: their samples, (opb - 1) D + T, fit the tile (opb >= 1)
+  const int opb = (kBZTile - T) / D + 1 < 256 ? (kBZTile - T) / D + 1 : 256;
+  for (int m0 = 0; m0 < LD; m0 += opb) {
+    const int64_t n0 = (int64_t)m0 * D - (T - 1);
+    const int span = (opb - 1) * D + T;
+    __syncthreads();  // the previous chunk's reads are done
+    for (int i = threadIdx.x; i < span; i += 256) {
+      const int64_t n = n0 + i;
+      xl[i + (i >> 6)] = (n >= 0 && n < N) ? xb[n] : 0.f;
+    }
+    __syncthreads();
+    const int m = m0 + (int)threadIdx.x;
+    if ((int)threadIdx.x < opb && m < LD) {
+      const int top = (int)threadIdx.x * D + T - 1;  // tile index of x[m D]
+      double ar = 0.0, ai = 0.0;
+      for (int tt = 0; tt < T; ++tt) {
+        const double2 gt = g[tt];
+        const int i = top - tt;
+        const double xv = (double)xl[i + (i >> 6)];
+        ar = fma(gt.x, xv, ar);
+        ai = fma(gt.y, xv, ai);
+      }
+      const double2 p = ph[m];
+      u[j.u_off + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));
+    }
   }
 }
 
@@ -584,7 +622,7 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
     }
     int L, nseg, nblk;
     int64_t Ns, Mb;
-    if (!czt_shape(Nin, j.M, &L, &Ns, &nseg, &Mb, &nblk)) {
+    if (!czt_shape(Nin, j.M, &L, &Ns, &nseg, &Mb, &nblk, true)) {
       snprintf(msg, sizeof msg, "job %lld: N=%lld, M=%lld too long for the single-pass path", (long long)i,
                (long long)Nin, (long long)j.M);
       return bfail(TZ_EUNSUPPORTED, msg);
