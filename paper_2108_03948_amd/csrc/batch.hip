@@ -99,13 +99,15 @@ __device__ __forceinline__ void czt_item(const BatchItem &it, bool active, const
         v[F::in_slot(e)] = cscale(c, ld_f32(rx, 4 * n));
     }
     F::forward(v, lds, t, twd);
+    // from L = 8192 up the spectral product and the second transform recompute
+    // their thread-derived offsets (fewer live registers: no spills at 128)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const unsigned k = t + NT * e;
-      v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * k)));
+      v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * (L >= 8192 ? k + opaque_zero() : k))));
     }
     F::out_to_in(v);
-    F::forward(v, lds, t, twd);
+    F::forward(v, lds, L >= 8192 ? (int)(t + opaque_zero()) : (int)t, twd);
     const Rsrc rq = make_rsrc(arena + it.post_off + (int64_t)s * it.post_stride, (uint64_t)it.kmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -123,10 +125,12 @@ __device__ __forceinline__ void czt_item(const BatchItem &it, bool active, const
   }
 }
 
-// Persistent kernel for the units of one FFT-length class: every workgroup
-// takes units from the class's counter until it passes the last one.
-template <int L>
-__global__ void __launch_bounds__(batch_threads<L>())
+// Persistent kernel for the units of one FFT-length class and flavour (SEG:
+// segmented input, CIN: complex input): every workgroup takes units from the
+// bucket's counter until it passes the last one.  Without segments the kernel
+// asks for four waves per SIMD (128 VGPRs).
+template <int L, bool SEG, bool CIN>
+__global__ void __launch_bounds__(batch_threads<L>(), SEG ? 1 : 4)
     k_batch_class(const float *__restrict__ x, float2 *__restrict__ X, const float2 *__restrict__ u,
                   const float2 *__restrict__ arena, const BatchItem *__restrict__ items,
                   const BatchUnit *__restrict__ units, int n_units, unsigned *counter,
@@ -136,7 +140,9 @@ __global__ void __launch_bounds__(batch_threads<L>())
   __shared__ float2 twl[tw_lds_points<L>()];
   __shared__ int next;
   const unsigned tid = threadIdx.x;
-  const unsigned sg = tid / NT, t = tid % NT;
+  // a subgroup spans whole waves (NT >= 64): its index, and the work item it
+  // selects, are wave-uniform and live in scalar registers
+  const unsigned sg = __builtin_amdgcn_readfirstlane(tid / NT), t = tid % NT;
   const TwLds twd = load_twiddles<L>(twl, tw, tid, batch_threads<L>());
   for (;;) {
     if (tid == 0) next = (int)atomicAdd(counter, 1u);
@@ -148,18 +154,9 @@ __global__ void __launch_bounds__(batch_threads<L>())
     const bool active = (int)sg < un.count;
     const BatchItem it = items[un.first + (active ? (int)sg : 0)];
     float2 *sub = lds + sg * lds_points<L>();
-    // flavor is uniform over the unit, so every wave takes the same branch
-    if (L < kMaxL || !(un.flavor & 2)) {
-      if (un.flavor & 1)
-        czt_item<L, false, true>(it, active, x, X, u, arena, sub, twd, t);
-      else
-        czt_item<L, false, false>(it, active, x, X, u, arena, sub, twd, t);
-    } else {
-      if (un.flavor & 1)
-        czt_item<L, true, true>(it, active, x, X, u, arena, sub, twd, t);
-      else
-        czt_item<L, true, false>(it, active, x, X, u, arena, sub, twd, t);
-    }
+    // the thread index through an opaque zero: addresses derived from it are
+    // formed per unit instead of being hoisted out of the loop and held live
+    czt_item<L, SEG, CIN>(it, active, x, X, u, arena, sub, twd, t + opaque_zero());
   }
 }
 
@@ -390,7 +387,8 @@ struct tz_batch {
   int64_t n_jobs = 0;
   std::vector<BatchItem> items;
   std::vector<BatchUnit> units;  // grouped by class; order inside a class chosen by the autotuner
-  int cls_first[15] = {}, cls_count[15] = {};
+  int cls_count[15] = {};                   // units per FFT-length class
+  int bkt_first[60] = {}, bkt_count[60] = {};  // bucket = class * 4 + flavor
   std::vector<ZoomJob> zjobs;
   void *d_arena = nullptr, *d_items = nullptr, *d_units = nullptr, *d_zjobs = nullptr;
   void *d_u = nullptr, *d_counter = nullptr;
@@ -434,34 +432,53 @@ double unit_cost(const tz_batch &b, const BatchUnit &u) {
   return c * (double)(1LL << u.lclass) * (double)u.lclass;
 }
 
-// units of each class in the order `inner` asks for (classes stay contiguous)
+// units of each class and flavour in the order `inner` asks for (every
+// bucket stays contiguous, at the same place for either order)
 std::vector<BatchUnit> order_units(const tz_batch &b, const std::vector<BatchUnit> &units, int inner) {
   std::vector<BatchUnit> u = units;
   if (inner == 0)
     std::stable_sort(u.begin(), u.end(), [&](const BatchUnit &a, const BatchUnit &c) {
       if (a.lclass != c.lclass) return a.lclass > c.lclass;
+      if (a.flavor != c.flavor) return a.flavor < c.flavor;
       return unit_cost(b, a) > unit_cost(b, c);
     });
   else
-    std::stable_sort(u.begin(), u.end(), [](const BatchUnit &a, const BatchUnit &c) { return a.lclass > c.lclass; });
+    std::stable_sort(u.begin(), u.end(), [](const BatchUnit &a, const BatchUnit &c) {
+      if (a.lclass != c.lclass) return a.lclass > c.lclass;
+      return a.flavor < c.flavor;
+    });
   return u;
 }
 
 template <int L>
-tz_status add_class_node(tz_batch *b, int c, const float *xf, float2 *Xc, const hipGraphNode_t *deps, int ndeps,
-                         hipGraphNode_t *node) {
+tz_status add_class_node(tz_batch *b, int bucket, const float *xf, float2 *Xc, const hipGraphNode_t *deps,
+                         int ndeps, hipGraphNode_t *node) {
   const float2 *u = (const float2 *)b->d_u;
   const float2 *arena = (const float2 *)b->d_arena;
   const BatchItem *it = (const BatchItem *)b->d_items;
-  const BatchUnit *un = (const BatchUnit *)b->d_units + b->cls_first[c];
-  int nu = b->cls_count[c];
-  unsigned *ctr = (unsigned *)b->d_counter + c;
-  const float2 *tw = (const float2 *)b->d_tw[c];
+  const BatchUnit *un = (const BatchUnit *)b->d_units + b->bkt_first[bucket];
+  int nu = b->bkt_count[bucket];
+  unsigned *ctr = (unsigned *)b->d_counter + bucket;
+  const float2 *tw = (const float2 *)b->d_tw[bucket / 4];
   void *args[] = {(void *)&xf, (void *)&Xc, (void *)&u, (void *)&arena, (void *)&it, (void *)&un,
                   (void *)&nu, (void *)&ctr, (void *)&tw};
   hipKernelNodeParams p{};
-  p.func = (void *)k_batch_class<L>;
-  p.gridDim = dim3((unsigned)std::min(b->grid, nu));
+  const int fl = bucket % 4;
+  // segmented items only occur at the longest length
+  if constexpr (L == kMaxL) {
+    static void *const f[4] = {(void *)k_batch_class<L, false, false>, (void *)k_batch_class<L, false, true>,
+                               (void *)k_batch_class<L, true, false>, (void *)k_batch_class<L, true, true>};
+    p.func = f[fl];
+  } else {
+    if (fl & 2) return bfail(TZ_EUNSUPPORTED, "segmented work item below the longest FFT length");
+    p.func = (fl & 1) ? (void *)k_batch_class<L, false, true> : (void *)k_batch_class<L, false, false>;
+  }
+  // persistent grid: every workgroup the CUs can hold at once
+  int per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p.func, batch_threads<L>(), 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  p.gridDim = dim3((unsigned)std::min(b->grid * per_cu, nu));
   p.blockDim = dim3(batch_threads<L>());
   p.kernelParams = args;
   BHIP(hipGraphAddKernelNode(node, b->graph, deps, ndeps, &p), "graph class node");
@@ -469,6 +486,7 @@ tz_status add_class_node(tz_batch *b, int c, const float *xf, float2 *Xc, const 
 }
 
 // graph: reset counters -> zoom front end -> one persistent kernel per class
+// and flavour
 tz_status build_graph(tz_batch *b, const void *x, void *X) {
   if (b->exec) {
     (void)hipGraphExecDestroy(b->exec);
@@ -482,7 +500,7 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
   hipGraphNode_t reset, prev;
   {
     unsigned *ctr = (unsigned *)b->d_counter;
-    int n = 15;
+    int n = 60;
     void *args[] = {(void *)&ctr, (void *)&n};
     hipKernelNodeParams p{};
     p.func = (void *)k_batch_reset;
@@ -509,23 +527,25 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
     prev = front;
   }
   const hipGraphNode_t root = prev;
-  for (int c = 14; c >= 8; --c) {
-    if (!b->cls_count[c]) continue;
-    const hipGraphNode_t dep = (b->topology == 0) ? root : prev;
-    hipGraphNode_t node;
-    tz_status st = TZ_OK;
-    switch (c) {
-      case 8: st = add_class_node<256>(b, c, xf, Xc, &dep, 1, &node); break;
-      case 9: st = add_class_node<512>(b, c, xf, Xc, &dep, 1, &node); break;
-      case 10: st = add_class_node<1024>(b, c, xf, Xc, &dep, 1, &node); break;
-      case 11: st = add_class_node<2048>(b, c, xf, Xc, &dep, 1, &node); break;
-      case 12: st = add_class_node<4096>(b, c, xf, Xc, &dep, 1, &node); break;
-      case 13: st = add_class_node<8192>(b, c, xf, Xc, &dep, 1, &node); break;
-      default: st = add_class_node<16384>(b, c, xf, Xc, &dep, 1, &node); break;
+  for (int c = 14; c >= 8; --c)
+    for (int fl = 0; fl < 4; ++fl) {
+      const int bucket = c * 4 + fl;
+      if (!b->bkt_count[bucket]) continue;
+      const hipGraphNode_t dep = (b->topology == 0) ? root : prev;
+      hipGraphNode_t node;
+      tz_status st = TZ_OK;
+      switch (c) {
+        case 8: st = add_class_node<256>(b, bucket, xf, Xc, &dep, 1, &node); break;
+        case 9: st = add_class_node<512>(b, bucket, xf, Xc, &dep, 1, &node); break;
+        case 10: st = add_class_node<1024>(b, bucket, xf, Xc, &dep, 1, &node); break;
+        case 11: st = add_class_node<2048>(b, bucket, xf, Xc, &dep, 1, &node); break;
+        case 12: st = add_class_node<4096>(b, bucket, xf, Xc, &dep, 1, &node); break;
+        case 13: st = add_class_node<8192>(b, bucket, xf, Xc, &dep, 1, &node); break;
+        default: st = add_class_node<16384>(b, bucket, xf, Xc, &dep, 1, &node); break;
+      }
+      if (st) return st;
+      prev = node;
     }
-    if (st) return st;
-    prev = node;
-  }
   BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
   b->last_x = x;
   b->last_X = X;
@@ -674,8 +694,9 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
     }
   b->units = order_units(*b, units, 0);
   for (size_t i = 0; i < b->units.size(); ++i) {
-    const int c = b->units[i].lclass;
-    if (!b->cls_count[c]) b->cls_first[c] = (int)i;
+    const int c = b->units[i].lclass, bk = c * 4 + b->units[i].flavor;
+    if (!b->bkt_count[bk]) b->bkt_first[bk] = (int)i;
+    ++b->bkt_count[bk];
     ++b->cls_count[c];
   }
 
@@ -684,7 +705,7 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
   BHIP(hipMalloc(&b->d_items, sizeof(BatchItem) * b->items.size()), "batch items");
   BHIP(hipMalloc(&b->d_units, sizeof(BatchUnit) * b->units.size()), "batch units");
   BHIP(hipMalloc(&b->d_u, sizeof(float2) * std::max<int64_t>(uscratch, 64)), "batch zoom scratch");
-  BHIP(hipMalloc(&b->d_counter, sizeof(unsigned) * 16), "batch counters");
+  BHIP(hipMalloc(&b->d_counter, sizeof(unsigned) * 64), "batch counters");
   if (!b->zjobs.empty()) {
     BHIP(hipMalloc(&b->d_zjobs, sizeof(ZoomJob) * b->zjobs.size()), "batch zoom jobs");
     BHIP(hipMemcpy(b->d_zjobs, b->zjobs.data(), sizeof(ZoomJob) * b->zjobs.size(), hipMemcpyHostToDevice),
