@@ -302,7 +302,9 @@ __global__ void __launch_bounds__(64 * P)
     // (twiddles, LDS addresses) is formed per trace instead of being hoisted
     // out of the loop and kept live in registers across it
     const unsigned tid = threadIdx.x + opaque_zero();
-    const unsigned r = tid / 64, lane = tid % 64;
+    // the wave index is wave-uniform: it and what derives from it only need
+    // scalar registers
+    const unsigned r = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
     fetch(b, lane);
     // z[m] W_Nh^{r m} / 2 with m = lane + 64 e: W_Nh^{r lane} W_NU^{r e} / 2
     {

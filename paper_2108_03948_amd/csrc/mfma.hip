@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(L / 16, 4)
   constexpr int XB = KIND == 1 ? 8 : 4;
   __shared__ float2 lds[lds_points<L>()];
   __shared__ float2 twl[tw_lds_points<L>()];
-  const int t = threadIdx.x, wave = t / 64, lane = t % 64, h = lane / 32;
+  const int t = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64, h = lane / 32;
   const int64_t b = blockIdx.x;
   const TwLds twd = load_twiddles<L>(twl, tw, t, NT);
   MF mf;
@@ -261,7 +261,8 @@ __global__ void __launch_bounds__(L / 16, 4)
   __syncthreads();
   // fresh copies of the thread indices: the second transform recomputes its
   // LDS addresses instead of keeping those of the first one live
-  const int t2 = (int)(t + opaque_zero()), wave2 = t2 / 64, lane2 = t2 % 64, h2 = lane2 / 32;
+  const int t2 = (int)(t + opaque_zero()), wave2 = __builtin_amdgcn_readfirstlane(t2 / 64), lane2 = t2 % 64,
+            h2 = lane2 / 32;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const int j = 64 * wave2 + 32 * g + lane2 % 32;
