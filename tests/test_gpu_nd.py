@@ -172,6 +172,27 @@ def test_czt_nd_cube_sampled(tz, dev, orc):
     assert_arrays_close(X[:, bins[0]][:, :, bins[1]][:, :, :, bins[2]], ref, what="cube, sampled bins")
 
 
+def test_czt_nd_arrays_larger_than_a_chunk(tz, dev, orc):
+    """Arrays whose intermediates exceed the cache-sized chunk run one per
+    chunk (here 2 arrays of 3000 x 3000 -> 3000 x 2500), written into padded
+    output rows whose padding must stay untouched."""
+    import torch
+    B, N0, N1, M0, M1 = 2, 3000, 3000, 3000, 2500
+    rng = np.random.default_rng(46)
+    x = white(B, (N0,), N1, seed=2500)
+    axes = random_axes(rng, (M0, M1))
+    full = torch.full((B, M0 * M1 + 512), complex(5.0, 5.0), dtype=torch.complex64, device=dev)
+    out = full[:, : M0 * M1].view(B, M0, M1)
+    say(f"case: czt_nd 2-D {B} x {N0} x {N1} -> {M0} x {M1}, one array per chunk, padded output")
+    tz.czt_nd(to_dev(x, dev), axes, out=out)
+    f = full.cpu().numpy()
+    assert np.all(f[:, M0 * M1:] == np.complex64(complex(5.0, 5.0)))
+    b0 = np.sort(rng.choice(M0, 12, replace=False))
+    b1 = np.sort(rng.choice(M1, 12, replace=False))
+    X = f[:, : M0 * M1].reshape(B, M0, M1)
+    assert_arrays_close(X[:, b0][:, :, b1], orc.czt_nd(x, axes, bins=[b0, b1]), what="large arrays, sampled")
+
+
 # ---------------------------------------------------------------------------
 # zoom_fft_nd
 # ---------------------------------------------------------------------------
