@@ -5,7 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "fft_core.h"
 #include "internal.h"
@@ -581,6 +584,183 @@ __global__ void __launch_bounds__(256)
   u[b * LD + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));
 }
 
+// Persistent form for real f32 traces on 16-byte boundaries (the long-scan and
+// batched workloads).  Each workgroup walks tiles (trace b, outputs r opb ..
+// r opb + opb - 1) with a grid-stride loop and fetches the next tile's samples
+// into registers (QPT 16-byte loads per thread, all in flight at once) while
+// the current tile's sums run from LDS, so the HBM reads of one tile overlap
+// the FP64 arithmetic of the previous one.  The tile position advances by
+// additions (no integer division in the loop).
+//
+// The tile starts at n0a = n0 rounded down to a multiple of 4 (n0 = m0 D -
+// (T-1), delta = n0 - n0a), so quad q lands on tile words 4q .. 4q+3.  With
+// P = 2 (D a multiple of 8) the tile has two pad slots after every D samples:
+// sample i sits at word i + 2 floor(i / D).  Output o of the tile at tap t
+// reads tile sample i = o D + c, c = T - 1 + delta - t, i.e. word o (D + P) +
+// c + P floor(c / D).  The output part o (D + 2) has stride 2 mod 4 across the
+// banks, so the paired reads of two neighbouring taps (the compiler merges
+// them) hit distinct banks; the tap part is the same in every lane, so within
+// a block of D taps it is an immediate offset of the LDS read.
+//
+// Group s of the S tap groups (whole waves) takes the contiguous taps
+// [s tpg, (s+1) tpg); lane j of a group sums outputs j + r nout, r < R, so
+// every tap fetched through the scalar unit (the same for the whole wave)
+// feeds R outputs per lane before the next wait on the scalar and LDS loads.
+// The partial sums of the groups then go through the tile's own LDS.
+template <int S, int P, int QPT, int R>
+__global__ void __launch_bounds__(kZoomThreads)
+    k_zoom_front_pf(const float *__restrict__ x, int64_t xs, int64_t N, int D, int64_t LD, int T,
+                    const double2 *__restrict__ g, const double2 *__restrict__ ph, float2 *__restrict__ u,
+                    int bpt, int opb, int B, uint32_t dmagic) {
+  extern __shared__ double2 zsm[];
+  float *xl = (float *)zsm;  // the tile, then the partial sums part[S][opb]
+  double2 *part = zsm;
+  constexpr int nout = kZoomThreads / S;
+  const int tid = threadIdx.x;
+  const int span = (opb - 1) * D + T;
+  // tile (b, r) = tile index b bpt + r; the grid stride in the same form
+  struct Pos {
+    int b, r;
+  };
+  const int G = (int)gridDim.x;
+  const int sb = G / bpt, sr = G - (G / bpt) * bpt;
+  auto advance = [&](Pos q) {
+    q.r += sr;
+    q.b += sb;
+    if (q.r >= bpt) {
+      q.r -= bpt;
+      ++q.b;
+    }
+    return q;
+  };
+  // first sample n0 of the sums, quad-aligned start n0a, quads of the tile
+  auto geom = [&](Pos q, int64_t *n0a, int *delta, int *nq) {
+    const int64_t n0 = (int64_t)q.r * opb * D - (T - 1);
+    *n0a = n0 & ~(int64_t)3;
+    *delta = (int)(n0 - *n0a);
+    *nq = (*delta + span + 3) >> 2;
+  };
+  float4 w[QPT];
+  // 16-byte loads of the tile's quads; quads before sample 0 take offsets
+  // above 2^31 and quads past the tile an offset past the extent, so both read
+  // 0 (the host keeps N * 4 below 2^31); the one quad holding sample N - 1
+  // and the end of the trace (N % 4 != 0) is loaded sample by sample.  With
+  // live = false every load reads 0 without a memory request: the loads are
+  // still issued, so the count of loads in flight is the same on every path
+  // and a wait for an older load never waits for these
+  auto fetch = [&](Pos q, bool live) {
+    int64_t n0a;
+    int delta, nq;
+    geom(q, &n0a, &delta, &nq);
+    if (!live) nq = 0;
+    const Rsrc rx = make_rsrc(x + (int64_t)(live ? q.b : 0) * xs, (uint64_t)N * 4);
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) {
+      const int qi = tid + k * kZoomThreads;
+      const int64_t sn = n0a + 4 * (int64_t)qi;
+      const unsigned off = qi < nq ? (unsigned)(sn * 4) : 0xFFFFFFF0u;
+      w[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)off, 0, 0));
+      if (qi < nq && sn < N && sn + 3 >= N)
+        w[k] = make_float4(ld_f32(rx, (unsigned)(sn * 4)), ld_f32(rx, (unsigned)(sn * 4 + 4)),
+                           ld_f32(rx, (unsigned)(sn * 4 + 8)), ld_f32(rx, (unsigned)(sn * 4 + 12)));
+    }
+  };
+  const int sidx = __builtin_amdgcn_readfirstlane(tid / nout);
+  const int j = tid % nout;
+  const int tpg = (T + S - 1) / S;
+  const int t_lo = sidx * tpg < T ? sidx * tpg : T;
+  const int t_hi = t_lo + tpg < T ? t_lo + tpg : T;
+  const int lb = j * (D + P);
+  const int ostride = nout * (D + P);  // tile words between outputs j and j + nout
+  Pos cur{(int)blockIdx.x / bpt, (int)blockIdx.x - ((int)blockIdx.x / bpt) * bpt};
+  if (cur.b >= B) return;
+  fetch(cur, true);
+  for (;;) {
+    int64_t n0a;
+    int delta, nq;
+    geom(cur, &n0a, &delta, &nq);
+    const int64_t m0 = (int64_t)cur.r * opb;
+    // this thread's mixing phasors (outputs tid + 256 i of the tile), requested
+    // ahead of the next tile's samples: waiting for them never waits for those
+    double2 p[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int64_t m = m0 + tid + kZoomThreads * i;
+      p[i] = ph[m < LD ? m : LD - 1];
+    }
+    // quads into the tile (D is a multiple of 4 when P > 0, so a quad never
+    // straddles a pad)
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) {
+      const int qi = tid + k * kZoomThreads;
+      if (qi < nq) {
+        const unsigned i = 4u * (unsigned)qi;
+        float *d = xl + i + (P ? P * __umulhi(i, dmagic) : 0u);
+        d[0] = w[k].x;
+        d[1] = w[k].y;
+        d[2] = w[k].z;
+        d[3] = w[k].w;
+      }
+    }
+    // the registers are free again: the next tile's loads go out before the
+    // barrier and stay in flight through this tile's sums
+    const Pos next = advance(cur);
+    const bool more = next.b < B;
+    fetch(more ? next : cur, more);
+    __syncthreads();
+    // taps [t_lo, t_hi) of outputs j + r nout: tile samples c = T - 1 + delta - t
+    double ar[R], ai[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ar[r] = ai[r] = 0.0;
+    {
+      const int c_lo = T + delta - t_hi, c_hi = T + delta - t_lo;
+      const double2 *gp = g + (T - 1 + delta);  // tap of sample c: gp[-c]
+      int c = c_lo;
+      int cq = P ? c_lo / D : 0;
+      while (c < c_hi) {
+        const int e = P ? ((cq + 1) * D < c_hi ? (cq + 1) * D : c_hi) : c_hi;
+        const float *row = xl + lb + P * cq;
+#pragma unroll 8
+        for (; c < e; ++c) {
+          const double2 gt = gp[-c];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            // outputs past the tile read words past its samples (inside the
+            // allocation) and are never stored
+            const double xv = (double)row[c + r * ostride];
+            ar[r] = fma(gt.x, xv, ar[r]);
+            ai[r] = fma(gt.y, xv, ai[r]);
+          }
+        }
+        ++cq;
+      }
+    }
+    __syncthreads();  // every tile read is done: the partial sums take its place
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (j + r * nout < opb) part[sidx * opb + j + r * nout] = make_double2(ar[r], ai[r]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int o = tid + kZoomThreads * i;
+      const int64_t m = m0 + o;
+      if (o < opb && m < LD) {
+        double sr2 = 0.0, si2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          sr2 += part[q * opb + o].x;
+          si2 += part[q * opb + o].y;
+        }
+        u[(int64_t)cur.b * LD + m] =
+            make_float2((float)(p[i].x * sr2 - p[i].y * si2), (float)(p[i].x * si2 + p[i].y * sr2));
+      }
+    }
+    if (!more) break;
+    __syncthreads();  // the sums are read before the next tile overwrites them
+    cur = next;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -723,12 +903,110 @@ hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// resident workgroups per CU x CUs for a kernel with `shm` bytes of dynamic
+// LDS, at most `work` (queried once per device, kernel and LDS size)
+static unsigned persistent_grid_shm(const void *kernel, int threads, size_t shm, int64_t work) {
+  struct Entry {
+    int dev;
+    const void *fn;
+    size_t shm;
+    int slots;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int slots = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (const Entry &e : cache)
+      if (e.dev == dev && e.fn == kernel && e.shm == shm) slots = e.slots;
+  }
+  if (!slots) {
+    int ncu = 0, occ = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, shm);
+    slots = (ncu > 0 ? ncu : 1) * (occ > 0 ? occ : 1);
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({dev, kernel, shm, slots});
+  }
+  return (unsigned)(work < slots ? work : slots);
+}
+
+// persistent front end for aligned f32 traces; false when the filter is too
+// long for its tile (the caller then takes the one-tile-per-workgroup kernel)
+static bool zoom_front_pf(const ZoomFrontLaunch &a, int S, hipStream_t s) {
+  constexpr int64_t kTileBytes = 40 * 1024;  // four workgroups per CU
+  constexpr int kQmax = 9;                   // 16-byte loads per thread and tile
+  const int P = a.D % 8 == 0 ? 2 : 0;
+  // tile of opb outputs: quads (start rounded down by up to 3) and LDS words;
+  // the partial sums S x opb double2 share the allocation
+  // lanes whose outputs lie past opb (opb < r2 nout) read up to
+  // (r2 nout - opb) (D + P) words past the tile, inside the allocation
+  auto shape = [&](int64_t opb, int s2, int r2, int64_t *span4, int64_t *bytes) {
+    const int64_t span = (opb - 1) * a.D + a.T;
+    *span4 = (span + 3 + 3) / 4 * 4;
+    const int64_t idle = std::max<int64_t>(0, (int64_t)r2 * (kZoomThreads / s2) - opb);
+    const int64_t words = *span4 + P * (*span4 / a.D) + 1 + idle * (a.D + P);
+    *bytes = std::max<int64_t>(4 * words, 16 * s2 * opb);
+  };
+  auto fits = [&](int64_t opb, int s2, int r2) {
+    int64_t span4, bytes;
+    shape(opb, s2, r2, &span4, &bytes);
+    return bytes <= kTileBytes && span4 / 4 <= kQmax * kZoomThreads &&
+           (!P || (uint64_t)span4 * (uint64_t)a.D < ((uint64_t)1 << 32));
+  };
+  // two outputs per lane with the fewest tap groups whose tile fits, else one
+  int R = 0;
+  int64_t opb = 0;
+  for (int s2 = S; s2 <= 4 && !R; s2 *= 2)
+    if (fits(2 * (kZoomThreads / s2), s2, 2)) {
+      R = 2;
+      S = s2;
+      opb = 2 * (kZoomThreads / s2);
+    }
+  if (!R) {
+    R = 1;
+    for (opb = kZoomThreads / S; opb >= 16; opb -= opb > 64 ? 16 : 4)
+      if (fits(opb, S, 1)) break;
+  }
+  const int64_t bpt = (a.LD + opb - 1) / opb, ntiles = a.B * bpt;
+  if (opb < 16 || a.D > (1 << 30) || ntiles >= ((int64_t)1 << 31)) return false;
+  int64_t span4, bytes;
+  shape(opb, S, R, &span4, &bytes);
+  const int nqt = (int)((span4 / 4 + kZoomThreads - 1) / kZoomThreads);
+  const size_t shm = (size_t)bytes;
+  const uint32_t dmagic = P ? (uint32_t)((((uint64_t)1 << 32) + a.D - 1) / a.D) : 0u;
+  auto go = [&](auto kernel) {
+    const dim3 grid(persistent_grid_shm((const void *)kernel, kZoomThreads, shm, ntiles)), block(kZoomThreads);
+    hipLaunchKernelGGL(kernel, grid, block, shm, s, (const float *)a.x, a.xs, a.N, (int)a.D, a.LD, a.T, a.g, a.ph,
+                       a.u, (int)bpt, (int)opb, (int)a.B, dmagic);
+  };
+  auto by_q = [&](auto k2, auto k4, auto k9) { nqt <= 2 ? go(k2) : (nqt <= 4 ? go(k4) : go(k9)); };
+#define TZ_ZPF(S_, P_, R_) by_q(k_zoom_front_pf<S_, P_, 2, R_>, k_zoom_front_pf<S_, P_, 4, R_>, k_zoom_front_pf<S_, P_, 9, R_>)
+#define TZ_ZPF_S(P_, R_) (S == 1 ? TZ_ZPF(1, P_, R_) : (S == 2 ? TZ_ZPF(2, P_, R_) : TZ_ZPF(4, P_, R_)))
+  if (R == 2)
+    P ? TZ_ZPF_S(2, 2) : TZ_ZPF_S(0, 2);
+  else
+    P ? TZ_ZPF_S(2, 1) : TZ_ZPF_S(0, 1);
+#undef TZ_ZPF_S
+#undef TZ_ZPF
+  return true;
+}
+
 hipError_t launch_zoom_front(const ZoomFrontLaunch &a, hipStream_t s) {
   // LDS tile: the partial sums and the samples of opb outputs, within 64 KB
   constexpr int64_t kTileBytes = 64 * 1024;
   const int64_t xb = a.in_kind == 0 ? 4 : 8;
   const int64_t fixed = 16 * kZoomThreads;
   const int S = a.T < 128 ? 1 : (a.T < 256 ? 2 : 4);
+  // persistent kernel for filters of 96+ taps on aligned f32 traces (measured:
+  // 255 taps, D = 64: 389 -> 291 us; 127 taps, D = 16: 138 -> 113 us); shorter
+  // filters run faster one tile per workgroup (63 taps, D = 6: 79 vs 95 us),
+  // their sums being too short to cover the extra barriers and phasor loads
+  if (a.in_kind == 0 && a.T >= 96 && ((uintptr_t)a.x & 15) == 0 && ((a.xs * 4) & 15) == 0 &&
+      a.N * 4 < ((int64_t)1 << 31) && zoom_front_pf(a, S, s))
+    return hipGetLastError();
   int64_t opb = 0;
   if (fixed + xb * (a.T + a.T / 64 + 1) <= kTileBytes && a.N * xb < ((int64_t)1 << 31)) {
     const int64_t xmax = (kTileBytes - fixed) / xb * 64 / 65 - 1;  // samples, pads included

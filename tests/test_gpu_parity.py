@@ -177,6 +177,16 @@ def test_fft_zeropad_shapes(tz, dev, orc, N, nz, half):
     (3000, 500, 16, 255, (0.4e12, 0.9e12)),
     (999, 301, 3, 31, (1.0e12, 4.0e12)),
     (512, 256, 1, 1, (0.3e12, 1.2e12)),
+    # long filters split over four waves, pad every D samples with D = 64 and
+    # with D = 40 (a multiple of 8 that is no power of two), D % 8 == 4
+    (20000, 700, 64, 511, (0.05e12, 0.15e12)),
+    (6001, 300, 40, 300, (0.2e12, 0.4e12)),
+    (4093, 1000, 12, 127, (0.3e12, 1.0e12)),
+    (2999, 400, 5, 200, (0.5e12, 2.0e12)),
+    # filters too long for two outputs per lane: one per lane, and a tile
+    # narrower than its lanes
+    (30000, 200, 128, 1000, (0.05e12, 0.1e12)),
+    (30000, 200, 128, 2000, (0.05e12, 0.1e12)),
 ])
 def test_zoom_shapes(tz, dev, orc, N, M, D, T, band):
     x = synth.pairs(2, N=N)
@@ -187,7 +197,7 @@ def test_zoom_shapes(tz, dev, orc, N, M, D, T, band):
     assert_close(Z, orc.zoom_fft(x.astype(np.float64), fs, f1, f2, M, D, taps=T), what="zoom")
 
 
-@pytest.mark.parametrize("N,D,T", [(1001, 6, 63), (1003, 64, 255), (4097, 3, 130), (5, 2, 63)])
+@pytest.mark.parametrize("N,D,T", [(1001, 6, 63), (1003, 64, 255), (4097, 3, 130), (5, 2, 63), (1025, 8, 127)])
 def test_zoom_padded_rows(tz, dev, orc, N, D, T):
     """Rows on 16-byte boundaries (stride a multiple of 4 samples) with N % 4 != 0:
     the front end's wide loads, including the one that holds sample N."""
