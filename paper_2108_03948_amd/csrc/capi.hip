@@ -323,13 +323,14 @@ tz_status spiral_scaling(int64_t N, int64_t M, double ma, double mw, PhaseParams
 // four-step path: chunks of traces through the plan's per-stream workspace
 tz_status run_long(Device &d, BluePlan &pl, const void *x, int in_kind, void *X, const Common &c, int64_t M,
                    hipStream_t s) {
-  if (c.precision != TZ_FP32)
-    return fail(TZ_EUNSUPPORTED, "split precision needs L in {4096, 8192, 16384}; N=%lld, M=%lld uses the "
-                                 "four-step FP32 path (L=%d)",
-                (long long)pl.N, (long long)pl.M, pl.L);
   LongLaunch a;
   a.L1 = pl.L1;
   a.L2 = pl.L / pl.L1;
+  a.precision = c.precision;
+  if (c.precision != TZ_FP32 && !long_rows_mfma_supported(a.L1, a.L2))
+    return fail(TZ_EUNSUPPORTED, "split precision on the four-step path needs rows of L2 in {4096, 8192, "
+                                 "16384}; N=%lld, M=%lld has L=%d = %d x %d",
+                (long long)pl.N, (long long)pl.M, pl.L, a.L1, a.L2);
   tz_status st = get_twiddles(d, a.L1, s, &a.tw_col);
   if (st) return st;
   if ((st = get_twiddles(d, a.L2, s, &a.tw_row))) return st;

@@ -591,4 +591,15 @@ struct WaveFft {
   }
 };
 
+// Workgroup g of G (G a multiple of 8) -> work item q, numbered so that each
+// XCD (dispatch is round-robin over 8) takes one contiguous run of q:
+// neighbouring items share cache lines and table rows in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_item(int64_t g, int64_t G) { return (g & 7) * (G >> 3) + (g >> 3); }
+
+// W_L^m for m < L from the two-level table tb: lo[i] = W_L^i (i < 2048),
+// hi[i] = W_L^{2048 i}
+__device__ __forceinline__ float2 big_twiddle(const float2 *__restrict__ tb, unsigned m) {
+  return cmul(tb[m & 2047u], tb[2048u + (m >> 11)]);
+}
+
 }  // namespace tz

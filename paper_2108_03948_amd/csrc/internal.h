@@ -177,10 +177,15 @@ struct LongLaunch {
   int64_t os, M;
   int L1, L2;
   int64_t B, chunk;
+  int precision;  // TZ_FP32, or split precision for the row FFTs (L2 >= 4096)
 };
 // L1 for a four-step length L (a power of two in [2^17, 2^24]); false otherwise
 bool long_shape(int64_t L, int *L1);
 hipError_t launch_czt_long(const LongLaunch &a, hipStream_t s);
+// split-precision row kernel of the four-step path (mfma.hip): L2 in
+// {4096, 8192, 16384}, L1 in {320, 512, 1024}
+bool long_rows_mfma_supported(int L1, int L2);
+hipError_t launch_long_rows_mfma(const LongLaunch &a, int L1, int64_t nb, hipStream_t s);
 
 // Zero-padded FFT, direct (N_fft = F) or split (N_fft = P * F, F >= N).
 struct PadLaunch {

@@ -23,6 +23,7 @@
 
 #include "fft_core.h"
 #include "internal.h"
+#include "thzspec.h"
 
 namespace tz {
 
@@ -94,17 +95,6 @@ struct ColFft {
     run(v, lds, tv, c, tw, std::make_integer_sequence<int, P>{});
   }
 };
-
-// Workgroup g of G (G a multiple of 8) -> work item q, numbered so that each
-// XCD (dispatch is round-robin over 8) takes one contiguous run of q:
-// neighbouring items share cache lines and table rows in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_item(int64_t g, int64_t G) { return (g & 7) * (G >> 3) + (g >> 3); }
-
-// W_L^m for m < L from the two-level table tb: lo[i] = W_L^i (i < 2048),
-// hi[i] = W_L^{2048 i}
-__device__ __forceinline__ float2 big_twiddle(const float2 *__restrict__ tb, unsigned m) {
-  return cmul(tb[m & 2047u], tb[2048u + (m >> 11)]);
-}
 
 // ---------------------------------------------------------------------------
 // cols: Z[b][k1][n2] = sum_n1 x[n1 L2 + n2] pre[n1 L2 + n2] W_L1^{n1 k1}
@@ -295,7 +285,12 @@ static hipError_t run_chunks(const LongLaunch &a, hipStream_t s) {
     const int64_t nb = (a.B - b0 < a.chunk) ? (a.B - b0) : a.chunk;
     const void *x = (const char *)a.x + b0 * a.xs * XB;
     launch_cols_fwd<L1>(a, x, nb, s);
-    if (!launch_rows_l2<L1>(a, nb, s)) return hipErrorInvalidValue;
+    if (a.precision != TZ_FP32) {
+      const hipError_t e = launch_long_rows_mfma(a, L1, nb, s);
+      if (e != hipSuccess) return e;
+    } else if (!launch_rows_l2<L1>(a, nb, s)) {
+      return hipErrorInvalidValue;
+    }
     // ncg_out * nb workgroups; the XCD numbering needs a multiple of 8
     const int64_t G = nb * ncg_out;
     if (G % 8 == 0) {

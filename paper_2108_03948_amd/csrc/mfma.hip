@@ -52,8 +52,15 @@ struct Split<TZ_SPLIT_BF16> {
 // index of output c (c < 8) held by lane half h
 __device__ __forceinline__ int out_k(int h, int c) { return (c < 4) ? 4 * h + c : 8 + 4 * h + (c - 4); }
 
-template <int L, int PREC>
+// NTERM = 2: operands split x = x_hi + x_lo, product A_hi B_hi + A_hi B_lo +
+// A_lo B_hi (about 16 significant bits per BF16 operand, 22 per FP16 one).
+// NTERM = 3 (BF16): x = x_hi + x_mid + x_lo and the six products of order
+// <= 2 (hi.hi; hi.mid, mid.hi; hi.lo, mid.mid, lo.hi), about 24 bits: twice
+// the matrix-core work, for chains of transforms whose two-term error adds up
+// past 1e-5.
+template <int L, int PREC, int NTERM = 2>
 struct MfmaFft {
+  static_assert(NTERM == 2 || NTERM == 3, "two- or three-term split");
   using SP = Split<PREC>;
   using V = typename SP::V;
   using S = typename SP::S;
@@ -64,8 +71,8 @@ struct MfmaFft {
   static_assert(L == 4096 || L == 8192 || L == 16384, "three radix-16 passes plus radix 1, 2 or 4");
 
   // DFT-matrix operands of this lane: rows i = l%32, columns k = 8h + q;
-  // a1 multiplies Re x, a2 multiplies Im x.
-  V a1h, a1l, a2h, a2l;
+  // a1 multiplies Re x, a2 multiplies Im x (a?m used with NTERM = 3 only).
+  V a1h, a1m, a1l, a2h, a2m, a2l;
 
   __device__ void init(int lane) {
     const int i = lane % 32, h = lane / 32;
@@ -80,9 +87,18 @@ struct MfmaFft {
       const float v2 = (i < 16) ? -fi : fr; // coefficient of Im x[k]
       const S h1 = (S)v1, h2 = (S)v2;
       a1h[q] = h1;
-      a1l[q] = (S)(v1 - (float)h1);
       a2h[q] = h2;
-      a2l[q] = (S)(v2 - (float)h2);
+      if constexpr (NTERM == 3) {
+        const float r1 = v1 - (float)h1, r2 = v2 - (float)h2;
+        const S m1 = (S)r1, m2 = (S)r2;
+        a1m[q] = m1;
+        a2m[q] = m2;
+        a1l[q] = (S)(r1 - (float)m1);
+        a2l[q] = (S)(r2 - (float)m2);
+      } else {
+        a1l[q] = (S)(v1 - (float)h1);
+        a2l[q] = (S)(v2 - (float)h2);
+      }
     }
   }
 
@@ -104,23 +120,52 @@ struct MfmaFft {
       up = ldexpf(1.f, sh);
       down = ldexpf(1.f, -sh);
     }
-    V brh, brl, bih, bil;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const float xr = kScale ? x[q].x * up : x[q].x, xi = kScale ? x[q].y * up : x[q].y;
-      const S hr = (S)xr, hi = (S)xi;
-      brh[q] = hr;
-      brl[q] = (S)(xr - (float)hr);
-      bih[q] = hi;
-      bil[q] = (S)(xi - (float)hi);
-    }
     float16v c = {};
-    c = SP::mfma(a1h, brh, c);
-    c = SP::mfma(a1h, brl, c);
-    c = SP::mfma(a1l, brh, c);
-    c = SP::mfma(a2h, bih, c);
-    c = SP::mfma(a2h, bil, c);
-    c = SP::mfma(a2l, bih, c);
+    if constexpr (NTERM == 2) {
+      V brh, brl, bih, bil;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float xr = kScale ? x[q].x * up : x[q].x, xi = kScale ? x[q].y * up : x[q].y;
+        const S hr = (S)xr, hi = (S)xi;
+        brh[q] = hr;
+        brl[q] = (S)(xr - (float)hr);
+        bih[q] = hi;
+        bil[q] = (S)(xi - (float)hi);
+      }
+      c = SP::mfma(a1h, brh, c);
+      c = SP::mfma(a1h, brl, c);
+      c = SP::mfma(a1l, brh, c);
+      c = SP::mfma(a2h, bih, c);
+      c = SP::mfma(a2h, bil, c);
+      c = SP::mfma(a2l, bih, c);
+    } else {
+      V brh, brm, brl, bih, bim, bil;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float xr = kScale ? x[q].x * up : x[q].x, xi = kScale ? x[q].y * up : x[q].y;
+        const S hr = (S)xr, hi = (S)xi;
+        const float rr = xr - (float)hr, ri = xi - (float)hi;
+        const S mr = (S)rr, mi = (S)ri;
+        brh[q] = hr;
+        brm[q] = mr;
+        brl[q] = (S)(rr - (float)mr);
+        bih[q] = hi;
+        bim[q] = mi;
+        bil[q] = (S)(ri - (float)mi);
+      }
+      c = SP::mfma(a1h, brh, c);
+      c = SP::mfma(a1h, brm, c);
+      c = SP::mfma(a1m, brh, c);
+      c = SP::mfma(a1h, brl, c);
+      c = SP::mfma(a1m, brm, c);
+      c = SP::mfma(a1l, brh, c);
+      c = SP::mfma(a2h, bih, c);
+      c = SP::mfma(a2h, bim, c);
+      c = SP::mfma(a2m, bih, c);
+      c = SP::mfma(a2h, bil, c);
+      c = SP::mfma(a2m, bim, c);
+      c = SP::mfma(a2l, bih, c);
+    }
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
       if constexpr (kScale) {
@@ -277,6 +322,116 @@ __global__ void __launch_bounds__(L / 16, 4)
   for (int e = 0; e < E; ++e) {
     const unsigned k = (unsigned)(t2 + NT * e);
     st_c64(cmul(cconj(v[MF::out_slot(e)]), ld_c64(rq, 8 * k)), rX, 8 * k);
+  }
+}
+
+// Row pass of the four-step path (the spectral product of eq. (15) on the
+// rows of the L1 x L2 layout) with split-precision radix-16 passes: per row
+// k1 of trace b,
+//   Hc[k1][n2] = W_L^{k1 n2} FFT_L2( conj( V[k1 + L1 k2] FFT_L2( W_L^{k1 n2} Z[k1][.] ) ) ),
+// in place; the same algebra as the FP32 row kernel, with its two L2-point
+// FFTs as in k_czt_mfma.
+template <int L1, int L2, int PREC>
+__global__ void __launch_bounds__(L2 / 16, 4)
+    k_long_rows_mfma(float2 *__restrict__ Z, const float2 *__restrict__ Vt, const float2 *__restrict__ tw_row,
+                     const float2 *__restrict__ tbig, int64_t nb) {
+  // BF16 takes the three-term split here: the two-term one measured 1.0e-5
+  // on 256 x 2^20 long scans (L = 320 x 4096), at the 1e-5 bar
+  using MF = MfmaFft<L2, PREC, PREC == TZ_SPLIT_BF16 ? 3 : 2>;
+  constexpr int NT = MF::NT, E = MF::E, Q = MF::Q;
+  constexpr int64_t L = (int64_t)L1 * L2;
+  __shared__ float2 lds[lds_points<L2>()];
+  __shared__ float2 twl[tw_lds_points<L2>()];
+  const int t = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64, h = lane / 32;
+  // rows of equal k1 (one V row) for the traces of the chunk run back to back
+  const int64_t q = xcd_item(blockIdx.x, gridDim.x);
+  const unsigned k1 = (unsigned)(q / nb);
+  const int64_t b = q % nb;
+  const TwLds twd = load_twiddles<L2>(twl, tw_row, t, NT);
+  MF mf;
+  mf.init(lane);
+  __syncthreads();
+  const Rsrc rz = make_rsrc(Z + b * L + (int64_t)k1 * L2, (uint64_t)L2 * 8);
+  const Rsrc rv = make_rsrc(Vt + (int64_t)k1 * L2, (uint64_t)L2 * 8);
+  float2 xin[2][8];
+  float2 v[E];
+  // the row, times W_L^{k1 n2}, straight into the matrix-core layout
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int j = 64 * wave + 32 * g + lane % 32;
+#pragma unroll
+    for (int qq = 0; qq < 8; ++qq) {
+      const unsigned n2 = (unsigned)(j + (8 * h + qq) * Q);
+      xin[g][qq] = cmul(ld_c64(rz, 8 * n2), big_twiddle(tbig, k1 * n2));
+    }
+  }
+  mf.template pass<0>(xin, v, lds, wave, lane, twd);
+  mf.template pass<1>(xin, v, lds, wave, lane, twd);
+  mf.template pass<2>(xin, v, lds, wave, lane, twd);
+  mf.trailing(v, twd);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const unsigned k2 = (unsigned)(t + NT * e);
+    v[MF::out_slot(e)] = cconj(cmul(v[MF::out_slot(e)], ld_c64(rv, 8 * k2)));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds[lds_idx(t + NT * e)] = v[MF::out_slot(e)];
+  __syncthreads();
+  // fresh copies of the thread indices for the second transform
+  const int t2 = (int)(t + opaque_zero()), wave2 = __builtin_amdgcn_readfirstlane(t2 / 64), lane2 = t2 % 64,
+            h2 = lane2 / 32;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int j = 64 * wave2 + 32 * g + lane2 % 32;
+#pragma unroll
+    for (int qq = 0; qq < 8; ++qq) xin[g][qq] = lds[lds_idx(j + (8 * h2 + qq) * Q)];
+  }
+  mf.template pass<0>(xin, v, lds, wave2, lane2, twd);
+  mf.template pass<1>(xin, v, lds, wave2, lane2, twd);
+  mf.template pass<2>(xin, v, lds, wave2, lane2, twd);
+  mf.trailing(v, twd);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const unsigned n2 = (unsigned)(t2 + NT * e);
+    st_c64(cmul(v[MF::out_slot(e)], big_twiddle(tbig, k1 * n2)), rz, 8 * n2);
+  }
+}
+
+bool long_rows_mfma_supported(int L1, int L2) {
+  return (L1 == 320 || L1 == 512 || L1 == 1024) && (L2 == 4096 || L2 == 8192 || L2 == 16384);
+}
+
+template <int L1, int L2>
+static void long_rows_mfma_dispatch(const LongLaunch &a, int64_t nb, hipStream_t s) {
+  const dim3 grid((unsigned)(nb * L1)), block(L2 / 16);
+  if (a.precision == TZ_SPLIT_FP16)
+    hipLaunchKernelGGL((k_long_rows_mfma<L1, L2, TZ_SPLIT_FP16>), grid, block, 0, s, a.work, a.Vt, a.tw_row, a.tbig,
+                       nb);
+  else
+    hipLaunchKernelGGL((k_long_rows_mfma<L1, L2, TZ_SPLIT_BF16>), grid, block, 0, s, a.work, a.Vt, a.tw_row, a.tbig,
+                       nb);
+}
+
+template <int L1>
+static hipError_t long_rows_mfma_l2(const LongLaunch &a, int64_t nb, hipStream_t s) {
+  switch (a.L2) {
+    case 4096: long_rows_mfma_dispatch<L1, 4096>(a, nb, s); break;
+    case 8192: long_rows_mfma_dispatch<L1, 8192>(a, nb, s); break;
+    case 16384: long_rows_mfma_dispatch<L1, 16384>(a, nb, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_long_rows_mfma(const LongLaunch &a, int L1, int64_t nb, hipStream_t s) {
+  if (!long_rows_mfma_supported(L1, a.L2) ||
+      (a.precision != TZ_SPLIT_FP16 && a.precision != TZ_SPLIT_BF16))
+    return hipErrorInvalidValue;
+  switch (L1) {
+    case 320: return long_rows_mfma_l2<320>(a, nb, s);
+    case 512: return long_rows_mfma_l2<512>(a, nb, s);
+    default: return long_rows_mfma_l2<1024>(a, nb, s);
   }
 }
 

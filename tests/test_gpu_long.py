@@ -159,3 +159,54 @@ def test_long_scans_zoom(tz, orc, long_scans):
         worst = max(worst, e)
         assert e <= TOL, (b, e)
     say(f"  worst sampled rel L2 {worst:.3e}")
+
+
+# ---------------------------------------------------------------------------
+# split precision on the four-step path: the row FFTs' radix-16 passes on the
+# matrix cores (hi + lo operands, FP32 accumulation); the column FFTs, chirps
+# and twiddles stay FP32
+# ---------------------------------------------------------------------------
+TOL_SPLIT = 1e-5
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+@pytest.mark.parametrize("N,M", [(1000000, 200000), (1500000, 100000), (2400000, 100000)])
+def test_long_czt_split_precision(tz, orc, prec, N, M):
+    """Rows of 4096 (L = 320 x 4096 and 512 x 4096) and of 8192 (320 x 8192)."""
+    import torch
+    L, blocks = tz.czt_plan_shape(N, M)
+    say(f"case: long czt {prec} N={N} M={M} plan L={L} blocks={blocks}")
+    rng = np.random.default_rng(N + M + 7)
+    x = rng.standard_normal((2, N)).astype(np.float32)
+    W = np.exp(-2j * np.pi * 0.37 / (N + M))
+    A = np.exp(2j * np.pi * 0.0123)
+    X = tz.czt(torch.from_numpy(x).cuda(), M, W, A, precision=prec).cpu().numpy()
+    assert np.isfinite(X).all()
+    bins = sample_bins(M, rng, 64)
+    ref = orc.czt(x.astype(np.float64), M, W, A, bins)
+    for b in range(2):
+        e = rel(X[b, bins], ref[b])
+        say(f"  trace {b}: rel L2 {e:.3e}")
+        assert e <= TOL_SPLIT
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+def test_long_scans_czt_split(tz, orc, long_scans, prec):
+    """The long-scan CZT (256 x 2^20 -> 2^18 bins, L = 320 x 4096) at split
+    precision: error against the FP64 oracle and time against the FP32 path."""
+    x, xd = long_scans
+    say(f"case: long scans czt {prec} B={B_LONG} N={N_LONG} M={M_LONG}")
+    X, ms = timed(lambda: tz.czt_band_exact(xd, M_LONG, FS, F1, F2, precision=prec))
+    _, ms32 = timed(lambda: tz.czt_band_exact(xd, M_LONG, FS, F1, F2))
+    say(f"  {prec} {ms:.3f} ms per batch, FP32 {ms32:.3f} ms ({ms32 / ms:.2f}x)")
+    Xh = X.cpu().numpy()
+    assert np.isfinite(Xh).all()
+    rng = np.random.default_rng(13)
+    worst = 0.0
+    for b in (0, 77, 255):
+        bins = sample_bins(M_LONG, rng, 64)
+        ref = orc.czt_band_exact(x[b:b + 1].astype(np.float64), M_LONG, FS, F1, F2, bins)[0]
+        e = rel(Xh[b, bins], ref)
+        worst = max(worst, e)
+        assert e <= TOL_SPLIT, (b, e)
+    say(f"  worst sampled rel L2 {worst:.3e}")
