@@ -55,9 +55,12 @@ enum { TZ_F32 = 0, TZ_F64 = 1 };
 /* arithmetic of the FFT stages.  TZ_SPLIT_FP16 / TZ_SPLIT_BF16 run the
  * radix-16 passes of czt() / czt_band_exact() on the matrix cores as dense
  * 16-point DFT-matrix products with operands split into high and low 16-bit
- * parts and FP32 accumulation (for FFT lengths 4096, 8192 and 16384 with one
- * bin block and real input; other shapes and the other transforms return
- * TZ_EUNSUPPORTED). */
+ * parts and FP32 accumulation: single-pass plans of FFT length 4096, 8192 or
+ * 16384 with one bin block and real input, and four-step plans (N + M - 1 up
+ * to 2^24) whose row FFTs have length 4096, 8192 or 16384 (there BF16 splits
+ * each operand into three parts); the four-step column FFTs, chirps and
+ * twiddles stay FP32.  Other shapes and the other transforms return
+ * TZ_EUNSUPPORTED. */
 enum { TZ_FP32 = 0, TZ_SPLIT_FP16 = 1, TZ_SPLIT_BF16 = 2 };
 /* flags */
 enum {
