@@ -4,6 +4,7 @@
   python bench_profiles.py traffic <fetch_counter.csv> <write_counter.csv> <out.json> "<cmd>"
   python bench_profiles.py kernel-traffic <fetch_counter.csv> <write_counter.csv> <kernel_trace.csv>
          <calibration.json> <out.md> "<cmd>" <name-substring> ...
+  python bench_profiles.py utilization <counter.csv> <out.md> "<cmd>" <name-substring> ...
 
 Byte counters are scaled by what the same counters read for the 1 GiB device
 copy that ``bench.py --calib-copy`` runs first (dispatch with the largest grid
@@ -102,8 +103,35 @@ def kernel_traffic(fetch_csv, write_csv, stats_csv, calib_json, out, cmd, keys):
     open(out, "w").write("\n".join(lines) + "\n")
 
 
+def utilization(counter_csv, out, cmd, keys):
+    """VALUBusy and MfmaUtil (percent of the dispatch's GPU-active time the
+    vector ALUs / matrix cores were busy) per kernel and grid size."""
+    acc = {}
+    for r in csv.DictReader(open(counter_csv)):
+        name = r["Kernel_Name"].split("(")[0]
+        if not any(k in r["Kernel_Name"] for k in keys):
+            continue
+        d = acc.setdefault((name, int(r["Grid_Size"])), {})
+        d.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = ["# Vector ALU and matrix-core utilization per dispatch", "",
+             f"Command:\n\n    {cmd}\n",
+             "VALUBusy = 100 SQ_ACTIVE_INST_VALU / (CUs x GRBM_GUI_ACTIVE); MfmaUtil = 100 "
+             "SQ_VALU_MFMA_BUSY_CYCLES / (SIMDs x GRBM_GUI_ACTIVE), averaged over the dispatches of each "
+             "kernel and grid size (work-items).", "",
+             "| kernel | grid | dispatches | VALUBusy (%) | MfmaUtil (%) |", "|---|---|---|---|---|"]
+    for (name, grid), d in sorted(acc.items()):
+        vb, mu = d.get("VALUBusy", []), d.get("MfmaUtil", [])
+        if not vb:
+            continue
+        lines.append(f"| `{name}` | {grid} | {len(vb)} | {sum(vb) / len(vb):.1f} | "
+                     f"{(sum(mu) / len(mu)) if mu else float('nan'):.1f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
+    if sys.argv[1] == "utilization":
+        utilization(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:])
+    elif sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "kernel-traffic":
         kernel_traffic(*sys.argv[2:8], sys.argv[8:])
