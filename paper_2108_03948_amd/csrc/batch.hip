@@ -80,10 +80,12 @@ __device__ __forceinline__ void czt_item(const BatchItem &it, bool active, const
   const int kmax = active ? it.kmax : 0;  // an idle subgroup computes but stores nothing
   const Rsrc rV = make_rsrc(arena + it.V_off, (uint64_t)L * 8);
   const Rsrc rX = make_rsrc(X + it.X_off, (uint64_t)kmax * 8);
-  float2 acc[SEG ? E : 1];
   float2 v[E];
   const int nloop = SEG ? it.nseg : 1;
   for (int s = 0; s < nloop; ++s) {
+    // with segments every iteration derives its thread offsets afresh (none
+    // loop-invariant, none held in registers across iterations)
+    const unsigned t1 = (SEG || L >= 16384) ? t + opaque_zero() : t;
     const int64_t n0 = (int64_t)s * it.Ns;
     const int64_t nmax = (it.N - n0 < it.Ns) ? (it.N - n0) : it.Ns;
     const Rsrc rp = make_rsrc(arena + it.pre_off, (uint64_t)nmax * 8);
@@ -91,46 +93,41 @@ __device__ __forceinline__ void czt_item(const BatchItem &it, bool active, const
                         : make_rsrc(x + it.x_off + n0, (uint64_t)nmax * 4);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned n = t + NT * e;
+      const unsigned n = t1 + NT * e;
       const float2 c = ld_c64(rp, 8 * n);
       if constexpr (CIN)
         v[F::in_slot(e)] = cmul(ld_c64(rx, 8 * n), c);
       else
         v[F::in_slot(e)] = cscale(c, ld_f32(rx, 4 * n));
     }
-    F::forward(v, lds, t, twd);
+    F::forward(v, lds, t1, twd);
     // from L = 8192 up the spectral product and the second transform recompute
     // their thread-derived offsets (fewer live registers: no spills at 128)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned k = t + NT * e;
+      const unsigned k = t1 + NT * e;
       v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * (L >= 8192 ? k + opaque_zero() : k))));
     }
     F::out_to_in(v);
-    F::forward(v, lds, L >= 8192 ? (int)(t + opaque_zero()) : (int)t, twd);
+    const unsigned t2 = L >= 8192 ? t + opaque_zero() : t1;
+    F::forward(v, lds, (int)t2, twd);
     const Rsrc rq = make_rsrc(arena + it.post_off + (int64_t)s * it.post_stride, (uint64_t)it.kmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned k = t + NT * e;
+      const unsigned k = ((SEG || L >= 16384) ? t2 : t) + NT * e;
       const float2 r = cmul(cconj(v[F::out_slot(e)]), ld_c64(rq, 8 * k));
-      if constexpr (SEG)
-        acc[e] = (s == 0) ? r : cadd(acc[e], r);
-      else
-        st_c64(r, rX, 8 * k);  // bins past the block are dropped
+      // segments accumulate in X (see k_czt); bins past the block are dropped
+      st_c64((SEG && s > 0) ? cadd(ld_c64(rX, 8 * k), r) : r, rX, 8 * k);
     }
-  }
-  if constexpr (SEG) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) st_c64(acc[e], rX, 8 * (t + NT * e));
   }
 }
 
 // Persistent kernel for the units of one FFT-length class and flavour (SEG:
 // segmented input, CIN: complex input): every workgroup takes units from the
-// bucket's counter until it passes the last one.  Without segments the kernel
-// asks for four waves per SIMD (128 VGPRs).
+// bucket's counter until it passes the last one.  The kernel asks for four
+// waves per SIMD (128 VGPRs).
 template <int L, bool SEG, bool CIN>
-__global__ void __launch_bounds__(batch_threads<L>(), SEG ? 1 : 4)
+__global__ void __launch_bounds__(batch_threads<L>(), 4)
     k_batch_class(const float *__restrict__ x, float2 *__restrict__ X, const float2 *__restrict__ u,
                   const float2 *__restrict__ arena, const BatchItem *__restrict__ items,
                   const BatchUnit *__restrict__ units, int n_units, unsigned *counter,

@@ -35,10 +35,10 @@ __device__ __forceinline__ float load_real(const void *__restrict__ x, int64_t i
 // With one segment and one block this is exactly eq. (15).  The inverse FFT
 // is the forward FFT of the conjugate, conjugated (1/L sits in V).
 // ---------------------------------------------------------------------------
-// SEG = false asks for four waves per SIMD (128 VGPRs): L = 8192 then runs
-// two workgroups per CU instead of one
+// Four waves per SIMD (128 VGPRs): L = 8192 runs two workgroups per CU
+// instead of one
 template <int L, int KIND, bool SEG>
-__global__ void __launch_bounds__(Fft<L>::NT, SEG ? 1 : 4)
+__global__ void __launch_bounds__(Fft<L>::NT, 4)
     k_czt(const void *__restrict__ x, int64_t xs, int64_t N, int64_t Ns, int nseg,
           const float2 *__restrict__ c_pre, const float2 *__restrict__ c_post,
           const float2 *__restrict__ V, const float2 *__restrict__ tw, float2 *__restrict__ X,
@@ -69,10 +69,12 @@ __global__ void __launch_bounds__(Fft<L>::NT, SEG ? 1 : 4)
   const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
   const Rsrc rX = make_rsrc(X + b * os + k0, (uint64_t)kmax * 8);
 
-  float2 acc[SEG ? E : 1];
   float2 v[E];
   const int nloop = SEG ? nseg : 1;
   for (int s = 0; s < nloop; ++s) {
+    // with segments every iteration derives its thread offsets afresh, so
+    // none of them is loop-invariant and held in registers across iterations
+    const unsigned t1 = (SEG || L >= 16384) ? t + opaque_zero() : t;
     const int64_t n0 = (int64_t)s * Ns;
     const int64_t nmax = (N - n0 < Ns) ? (N - n0) : Ns;  // samples of this segment
     // reads past the segment return 0: the zero padding of y up to L
@@ -80,40 +82,40 @@ __global__ void __launch_bounds__(Fft<L>::NT, SEG ? 1 : 4)
     const Rsrc rp = make_rsrc(c_pre + (int64_t)blk * Ns, (uint64_t)nmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned n = t + NT * e;
+      const unsigned n = t1 + NT * e;
       const float2 c = ld_c64(rp, 8 * n);
       if constexpr (KIND == 2)
         v[F::in_slot(e)] = cmul(ld_c64(rx, 8 * n), c);
       else
         v[F::in_slot(e)] = cscale(c, ld_real<KIND>(rx, n));
     }
-    F::forward(v, lds, t, twd);
+    F::forward(v, lds, t1, twd);
     // from L = 8192 up the spectrum's offsets are recomputed too (the V
     // loads otherwise pin the first transform's index registers: spills)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned k = t + NT * e;
+      const unsigned k = t1 + NT * e;
       v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * (L >= 8192 ? k + opaque_zero() : k))));
     }
     F::out_to_in(v);
     // from L = 8192 up, a fresh copy of the thread index: the second
     // transform recomputes its LDS addresses instead of keeping those of the
     // first one live (fewer registers; shorter transforms run faster without)
-    F::forward(v, lds, L >= 8192 ? (int)(t + opaque_zero()) : (int)t, twd);
+    const unsigned t2 = L >= 8192 ? t + opaque_zero() : t1;
+    F::forward(v, lds, (int)t2, twd);
     const Rsrc rq = make_rsrc(c_post + ((int64_t)s * nblk + blk) * Mb, (uint64_t)kmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned k = t + NT * e;
+      const unsigned k = ((SEG || L >= 16384) ? t2 : t) + NT * e;
       const float2 r = cmul(cconj(v[F::out_slot(e)]), ld_c64(rq, 8 * k));
-      if constexpr (SEG)
-        acc[e] = (s == 0) ? r : cadd(acc[e], r);
-      else
-        st_c64(r, rX, 8 * k);  // bins past this block are dropped
+      // segments accumulate in X itself: segment s > 0 adds to what this
+      // thread stored for the same bins in segment s - 1 (a register
+      // accumulator spilled ~80 registers at L = 16384).  The two transforms
+      // between the store and the read-back pass workgroup barriers, whose
+      // release fences wait for the thread's stores.  Bins past this block
+      // are dropped (and read as 0)
+      st_c64((SEG && s > 0) ? cadd(ld_c64(rX, 8 * k), r) : r, rX, 8 * k);
     }
-  }
-  if constexpr (SEG) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) st_c64(acc[e], rX, 8 * (t + NT * e));
   }
 }
 
