@@ -83,9 +83,10 @@ __device__ __forceinline__ void czt_item(const BatchItem &it, bool active, const
   float2 v[E];
   const int nloop = SEG ? it.nseg : 1;
   for (int s = 0; s < nloop; ++s) {
-    // with segments every iteration derives its thread offsets afresh (none
-    // loop-invariant, none held in registers across iterations)
-    const unsigned t1 = (SEG || L >= 16384) ? t + opaque_zero() : t;
+    // every segment (and the single pass of an unsegmented item) derives its
+    // thread offsets afresh: none is held in registers across the loop or
+    // from the unit's start (no spills in any class, 103 registers at 8192)
+    const unsigned t1 = t + opaque_zero();
     const int64_t n0 = (int64_t)s * it.Ns;
     const int64_t nmax = (it.N - n0 < it.Ns) ? (it.N - n0) : it.Ns;
     const Rsrc rp = make_rsrc(arena + it.pre_off, (uint64_t)nmax * 8);
@@ -114,7 +115,7 @@ __device__ __forceinline__ void czt_item(const BatchItem &it, bool active, const
     const Rsrc rq = make_rsrc(arena + it.post_off + (int64_t)s * it.post_stride, (uint64_t)it.kmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned k = ((SEG || L >= 16384) ? t2 : t) + NT * e;
+      const unsigned k = t2 + NT * e;
       const float2 r = cmul(cconj(v[F::out_slot(e)]), ld_c64(rq, 8 * k));
       // segments accumulate in X (see k_czt); bins past the block are dropped
       st_c64((SEG && s > 0) ? cadd(ld_c64(rX, 8 * k), r) : r, rX, 8 * k);

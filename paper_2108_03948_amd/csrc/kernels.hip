@@ -73,8 +73,10 @@ __global__ void __launch_bounds__(Fft<L>::NT, 4)
   const int nloop = SEG ? nseg : 1;
   for (int s = 0; s < nloop; ++s) {
     // with segments every iteration derives its thread offsets afresh, so
-    // none of them is loop-invariant and held in registers across iterations
-    const unsigned t1 = (SEG || L >= 16384) ? t + opaque_zero() : t;
+    // none of them is loop-invariant and held in registers across iterations;
+    // the same removes the spills of the single-pass kernel at L = 16384
+    constexpr bool kFresh = SEG || L >= 16384;
+    const unsigned t1 = kFresh ? t + opaque_zero() : t;
     const int64_t n0 = (int64_t)s * Ns;
     const int64_t nmax = (N - n0 < Ns) ? (N - n0) : Ns;  // samples of this segment
     // reads past the segment return 0: the zero padding of y up to L
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(Fft<L>::NT, 4)
     const Rsrc rq = make_rsrc(c_post + ((int64_t)s * nblk + blk) * Mb, (uint64_t)kmax * 8);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned k = ((SEG || L >= 16384) ? t2 : t) + NT * e;
+      const unsigned k = (kFresh ? t2 : t) + NT * e;
       const float2 r = cmul(cconj(v[F::out_slot(e)]), ld_c64(rq, 8 * k));
       // segments accumulate in X itself: segment s > 0 adds to what this
       // thread stored for the same bins in segment s - 1 (a register
@@ -153,29 +155,46 @@ __global__ void __launch_bounds__(Fft<L>::NT)
   const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
   const Rsrc rp = make_rsrc(c_pre, (uint64_t)N * 8);
   const Rsrc rH = make_rsrc(H + p * os, (uint64_t)M * 8);  // bins past M are dropped
-  float2 gr[E], v[E];
+  // From L = 16384 up the reference's g_r waits in H[k] itself (each thread
+  // reads back its own stores after the sample's transforms, whose barriers'
+  // release fences wait for them) rather than in 2E registers, and each trace
+  // of the pair derives its thread offsets afresh: 125-140 registers spilled
+  // otherwise.  Shorter transforms keep g_r in registers.
+  constexpr bool kInH = L >= 16384;
+  float2 gr[kInH ? 1 : E], v[E];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
+    const unsigned t1 = kInH ? t + opaque_zero() : t;
     const Rsrc rx = make_rsrc((const char *)x + (2 * p + s) * xs * XB, (uint64_t)N * XB);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned n = t + NT * e;  // samples past N read as 0
+      const unsigned n = t1 + NT * e;  // samples past N read as 0
       v[F::in_slot(e)] = cscale(ld_c64(rp, 8 * n), ld_real<KIND>(rx, n));
     }
-    F::forward(v, lds, t, twd);
+    F::forward(v, lds, t1, twd);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const unsigned k = t + NT * e;
+      const unsigned k = t1 + NT * e;
       v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * (k + opaque_zero()))));
     }
     F::out_to_in(v);
-    F::forward(v, lds, t, twd);
+    const unsigned t2 = kInH ? t + opaque_zero() : t;
+    F::forward(v, lds, t2, twd);
     if (s == 0) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) gr[e] = v[F::out_slot(e)];
+      for (int e = 0; e < E; ++e) {
+        if constexpr (kInH)
+          st_c64(v[F::out_slot(e)], rH, 8 * (t2 + NT * e));
+        else
+          gr[e] = v[F::out_slot(e)];
+      }
     } else {
 #pragma unroll
-      for (int e = 0; e < E; ++e) st_c64(cconj(cdiv(v[F::out_slot(e)], gr[e])), rH, 8 * (t + NT * e));
+      for (int e = 0; e < E; ++e) {
+        const unsigned k = t2 + NT * e;
+        const float2 g = kInH ? ld_c64(rH, 8 * k) : gr[kInH ? 0 : e];
+        st_c64(cconj(cdiv(v[F::out_slot(e)], g)), rH, 8 * k);
+      }
     }
   }
 }
