@@ -165,23 +165,27 @@ __global__ void k_batch_reset(unsigned *counters, int n) {
 // zoom front end for every zoom job (one workgroup per job):
 // u[m] = e^{-j 2 pi nu_N m D} sum_t g[t] x[mD - t], FP64 taps, phasors and
 // sums (the T-term sum in FP32 would lose accuracy as sqrt(T)).  The job's
-// samples pass through an LDS tile in chunks of opb outputs (coalesced loads,
-// zeros outside [0, N), one pad slot every 64 samples against the stride-D
-// reads); the tap index is the same across the wave, so the taps come
-// through scalar loads.  Filters longer than half the tile read x and the
-// taps straight from global memory.
-constexpr int kBZTile = 8192;  // samples per chunk
+// samples pass through an LDS tile in chunks of opb outputs (buffer loads:
+// zeros outside [0, N)); the tap index is the same across the wave, so the
+// taps come through scalar loads.  When D is a multiple of 4 the tile has two
+// pad words after every D samples (sample i at word i + 2 floor(i/D)): output
+// j's base j (D + 2) then spreads the lanes over the banks, and the offset of
+// tap c, c + 2 floor(c/D), is the same in every lane, an immediate of the LDS
+// read within each block of D taps.  Other D keep a linear tile (the per-tap
+// offsets fold the same way).  Filters longer than half the tile, and traces
+// of 2^29 samples or more, read x and the taps straight from global memory.
+constexpr int kBZTile = 6144;  // samples per chunk
 
 __global__ void __launch_bounds__(256)
     k_batch_zoom_front(const float *__restrict__ x, float2 *__restrict__ u, const float2 *__restrict__ arena,
                        const ZoomJob *__restrict__ jobs) {
-  __shared__ float xl[kBZTile + kBZTile / 64 + 1];
+  __shared__ float xl[kBZTile + kBZTile / 2 + 1];
   const ZoomJob j = jobs[blockIdx.x];
   const double2 *g = (const double2 *)(arena + j.g_off);
   const double2 *ph = (const double2 *)(arena + j.ph_off);
   const float *xb = x + j.x_off;
   const int D = j.D, T = j.T, N = j.N, LD = j.LD;
-  if (2 * T > kBZTile) {
+  if (2 * T > kBZTile || N >= (1 << 29)) {
     for (int m = threadIdx.x; m < LD; m += 256) {
       const int64_t base = (int64_t)m * D;
       double ar = 0.0, ai = 0.0;
@@ -198,27 +202,38 @@ __global__ void __launch_bounds__(256)
     }
     return;
   }
+  const int P = D % 4 == 0 ? 2 : 0;
+  const uint32_t dmagic = P ? (uint32_t)((((uint64_t)1 << 32) + D - 1) / D) : 0u;  // floor(i/D) = umulhi(i, dmagic)
+  // reads past N return 0; n < 0 wraps to an offset above 2^31 (N * 4 < 2^31)
+  const Rsrc rx = make_rsrc(xb, (uint64_t)N * 4);
   // outputs per chunk: their samples, (opb - 1) D + T, fit the tile (opb >= 1)
   const int opb = (kBZTile - T) / D + 1 < 256 ? (kBZTile - T) / D + 1 : 256;
+  const int jt = (int)threadIdx.x;
+  const float *base = xl + jt * (D + P);
+  const double2 *gp = g + (T - 1);  // tap of tile sample c (c = T - 1 - t): gp[-c]
   for (int m0 = 0; m0 < LD; m0 += opb) {
     const int64_t n0 = (int64_t)m0 * D - (T - 1);
     const int span = (opb - 1) * D + T;
     __syncthreads();  // the previous chunk's reads are done
-    for (int i = threadIdx.x; i < span; i += 256) {
-      const int64_t n = n0 + i;
-      xl[i + (i >> 6)] = (n >= 0 && n < N) ? xb[n] : 0.f;
-    }
+#pragma unroll 4
+    for (int i = jt; i < span; i += 256)
+      xl[i + (P ? P * __umulhi((unsigned)i, dmagic) : 0u)] = ld_f32(rx, (unsigned)((n0 + i) * 4));
     __syncthreads();
-    const int m = m0 + (int)threadIdx.x;
-    if ((int)threadIdx.x < opb && m < LD) {
-      const int top = (int)threadIdx.x * D + T - 1;  // tile index of x[m D]
+    const int m = m0 + jt;
+    if (jt < opb && m < LD) {
       double ar = 0.0, ai = 0.0;
-      for (int tt = 0; tt < T; ++tt) {
-        const double2 gt = g[tt];
-        const int i = top - tt;
-        const double xv = (double)xl[i + (i >> 6)];
-        ar = fma(gt.x, xv, ar);
-        ai = fma(gt.y, xv, ai);
+      int c = 0, cq = 0;
+      while (c < T) {
+        const int e = P ? ((cq + 1) * D < T ? (cq + 1) * D : T) : T;
+        const float *row = base + P * cq;
+#pragma unroll 8
+        for (; c < e; ++c) {
+          const double2 gt = gp[-c];
+          const double xv = (double)row[c];
+          ar = fma(gt.x, xv, ar);
+          ai = fma(gt.y, xv, ai);
+        }
+        ++cq;
       }
       const double2 p = ph[m];
       u[j.u_off + m] = make_float2((float)(p.x * ar - p.y * ai), (float)(p.x * ai + p.y * ar));

@@ -874,56 +874,6 @@ hipError_t launch_fftpad(const PadLaunch &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// workgroups that fill the device once: CUs x resident workgroups per CU,
-// at most `work` (queried once per device and kernel)
-template <class K>
-static unsigned persistent_grid(K kernel, int threads, int64_t work) {
-  static int cache[64];
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  int &slots = cache[dev & 63];
-  if (!slots) {
-    int ncu = 0, occ = 0;
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0);
-    slots = (ncu > 0 ? ncu : 1) * (occ > 0 ? occ : 1);
-  }
-  return (unsigned)(work < slots ? work : slots);
-}
-
-template <int F, int P>
-static void pad_real_launch(const PadRealLaunch &a, hipStream_t s) {
-  const dim3 block(64 * P);
-  if (a.in_kind == 1) {
-    const dim3 grid(persistent_grid(k_fftpad_real<F, P, 1>, 64 * P, a.B));
-    hipLaunchKernelGGL((k_fftpad_real<F, P, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.root_h, a.root_f, a.tw,
-                       a.X, a.os, a.half, a.B);
-  } else {
-    const dim3 grid(persistent_grid(k_fftpad_real<F, P, 0>, 64 * P, a.B));
-    hipLaunchKernelGGL((k_fftpad_real<F, P, 0>), grid, block, 0, s, a.x, a.xs, a.N, a.root_h, a.root_f, a.tw,
-                       a.X, a.os, a.half, a.B);
-  }
-}
-
-// (F, P) pairs with a compiled whole-spectrum kernel
-bool fftpad_real_supported(int F, int P) {
-  switch (F * 100 + P) {
-    case 102408: case 102416: case 204808: case 204816: return true;
-    default: return false;
-  }
-}
-
-hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s) {
-  switch (a.F * 100 + a.P) {
-    case 102408: pad_real_launch<1024, 8>(a, s); break;   // N_fft 16384, N <= 2048
-    case 102416: pad_real_launch<1024, 16>(a, s); break;  // N_fft 32768, N <= 2048
-    case 204808: pad_real_launch<2048, 8>(a, s); break;   // N_fft 32768, N <= 4096
-    case 204816: pad_real_launch<2048, 16>(a, s); break;  // N_fft 65536, N <= 4096
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 // resident workgroups per CU x CUs for a kernel with `shm` bytes of dynamic
 // LDS, at most `work` (queried once per device, kernel and LDS size)
 static unsigned persistent_grid_shm(const void *kernel, int threads, size_t shm, int64_t work) {
@@ -952,6 +902,39 @@ static unsigned persistent_grid_shm(const void *kernel, int threads, size_t shm,
     cache.push_back({dev, kernel, shm, slots});
   }
   return (unsigned)(work < slots ? work : slots);
+}
+
+template <int F, int P>
+static void pad_real_launch(const PadRealLaunch &a, hipStream_t s) {
+  const dim3 block(64 * P);
+  if (a.in_kind == 1) {
+    const dim3 grid(persistent_grid_shm((const void *)k_fftpad_real<F, P, 1>, 64 * P, 0, a.B));
+    hipLaunchKernelGGL((k_fftpad_real<F, P, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.root_h, a.root_f, a.tw,
+                       a.X, a.os, a.half, a.B);
+  } else {
+    const dim3 grid(persistent_grid_shm((const void *)k_fftpad_real<F, P, 0>, 64 * P, 0, a.B));
+    hipLaunchKernelGGL((k_fftpad_real<F, P, 0>), grid, block, 0, s, a.x, a.xs, a.N, a.root_h, a.root_f, a.tw,
+                       a.X, a.os, a.half, a.B);
+  }
+}
+
+// (F, P) pairs with a compiled whole-spectrum kernel
+bool fftpad_real_supported(int F, int P) {
+  switch (F * 100 + P) {
+    case 102408: case 102416: case 204808: case 204816: return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s) {
+  switch (a.F * 100 + a.P) {
+    case 102408: pad_real_launch<1024, 8>(a, s); break;   // N_fft 16384, N <= 2048
+    case 102416: pad_real_launch<1024, 16>(a, s); break;  // N_fft 32768, N <= 2048
+    case 204808: pad_real_launch<2048, 8>(a, s); break;   // N_fft 32768, N <= 4096
+    case 204816: pad_real_launch<2048, 16>(a, s); break;  // N_fft 65536, N <= 4096
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // persistent front end for aligned f32 traces; false when the filter is too
