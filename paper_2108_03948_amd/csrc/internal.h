@@ -92,7 +92,8 @@ inline bool czt_shape(int64_t N, int64_t M, int *L, int64_t *Ns, int *nseg, int6
     *nblk = (int)((M + bMb - 1) / bMb);
   }
   if (fast) {
-    // segments accumulate in registers (a slower kernel): weigh them 1.3x
+    // segments add their partial sums into the output (a read and a write per
+    // bin and extra segment): weigh them 1.3x
     const double cost = ok ? (double)best * fft_pair_cost(kMaxL) * (*nseg > 1 ? 1.3 : 1.0) : 1e300;
     int l = kMaxL;
     int64_t mb = 0;

@@ -111,7 +111,7 @@ def test_czt_shapes_ragged(tz, dev, orc, N, M):
     assert_close(X, orc.czt(x.astype(np.float64), M, W, A), what=f"czt N={N} M={M}")
 
 
-@pytest.mark.parametrize("N,M", [(12000, 6000), (16384, 8192), (3000, 15000)])
+@pytest.mark.parametrize("N,M", [(12000, 6000), (16384, 8192), (3000, 15000), (16000, 2000), (16100, 8000)])
 def test_czt_segments_and_blocks(tz, dev, orc, N, M):
     x = synth.pairs(1, N=N).astype(np.float32)
     fs, f1, f2 = 20e12, 0.05e12, 2.0e12
