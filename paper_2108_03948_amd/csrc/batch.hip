@@ -117,7 +117,9 @@ __device__ __forceinline__ void czt_item(const BatchItem &it, bool active, const
     for (int e = 0; e < E; ++e) {
       const unsigned k = t2 + NT * e;
       const float2 r = cmul(cconj(v[F::out_slot(e)]), ld_c64(rq, 8 * k));
-      // segments accumulate in X (see k_czt); bins past the block are dropped
+      // segments accumulate in X: each thread adds to its own stores of the
+      // previous segment (same addresses, program order); bins past the block
+      // are dropped
       st_c64((SEG && s > 0) ? cadd(ld_c64(rX, 8 * k), r) : r, rX, 8 * k);
     }
   }

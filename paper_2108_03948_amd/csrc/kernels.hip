@@ -111,11 +111,11 @@ __global__ void __launch_bounds__(Fft<L>::NT, 4)
       const unsigned k = (kFresh ? t2 : t) + NT * e;
       const float2 r = cmul(cconj(v[F::out_slot(e)]), ld_c64(rq, 8 * k));
       // segments accumulate in X itself: segment s > 0 adds to what this
-      // thread stored for the same bins in segment s - 1 (a register
-      // accumulator spilled ~80 registers at L = 16384).  The two transforms
-      // between the store and the read-back pass workgroup barriers, whose
-      // release fences wait for the thread's stores.  Bins past this block
-      // are dropped (and read as 0)
+      // same thread stored for the same bins in segment s - 1 (a register
+      // accumulator spilled ~80 registers at L = 16384).  A thread's store
+      // and later load of one address stay in program order, as for any
+      // store-then-load through a pointer; no other thread touches these
+      // bins.  Bins past this block are dropped (and read as 0)
       st_c64((SEG && s > 0) ? cadd(ld_c64(rX, 8 * k), r) : r, rX, 8 * k);
     }
   }
@@ -156,9 +156,9 @@ __global__ void __launch_bounds__(Fft<L>::NT)
   const Rsrc rp = make_rsrc(c_pre, (uint64_t)N * 8);
   const Rsrc rH = make_rsrc(H + p * os, (uint64_t)M * 8);  // bins past M are dropped
   // From L = 16384 up the reference's g_r waits in H[k] itself (each thread
-  // reads back its own stores after the sample's transforms, whose barriers'
-  // release fences wait for them) rather than in 2E registers, and each trace
-  // of the pair derives its thread offsets afresh: 125-140 registers spilled
+  // reads back only its own stores of those bins, which stay in program
+  // order with its loads) rather than in 2E registers, and each trace of the
+  // pair derives its thread offsets afresh: 125-140 registers spilled
   // otherwise.  Shorter transforms keep g_r in registers.
   constexpr bool kInH = L >= 16384;
   float2 gr[kInH ? 1 : E], v[E];
