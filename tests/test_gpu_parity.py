@@ -187,6 +187,10 @@ def test_fft_zeropad_shapes(tz, dev, orc, N, nz, half):
     # narrower than its lanes
     (30000, 200, 128, 1000, (0.05e12, 0.1e12)),
     (30000, 200, 128, 2000, (0.05e12, 0.1e12)),
+    # degenerate: decimation longer than the trace (one output, M = 1) and a
+    # filter far longer than the trace
+    (10, 1, 16, 127, (0.3e12, 1.2e12)),
+    (3, 7, 1, 200, (0.3e12, 1.2e12)),
 ])
 def test_zoom_shapes(tz, dev, orc, N, M, D, T, band):
     x = synth.pairs(2, N=N)
