@@ -273,6 +273,60 @@ void tz_batch_destroy(tz_batch *batch);
 int64_t tz_batch_describe(const tz_batch *batch, char *buf, int64_t len);
 
 /* ---------------------------------------------------------------------- */
+/* Explicit plans.  tz_plan_create() resolves everything one transform of  */
+/* one shape needs (the chirp tables and filter spectrum of eqs. (13)-(15), */
+/* FFT twiddles, FIR taps and mixing phasors of eqs. (6)-(10)) and builds   */
+/* it on opts->stream, synchronising that stream.  tz_plan_execute() then   */
+/* only enqueues kernels: it allocates no device memory and does not        */
+/* synchronise, so it may be called inside HIP stream capture or a tight    */
+/* serving loop.  Scratch memory (the four-step path's intermediates, the  */
+/* Zoom FFT's decimated rows) is a caller-owned workspace of at least       */
+/* tz_plan_workspace() bytes.                                               */
+
+enum { TZ_PLAN_FFT_ZEROPAD = 0, TZ_PLAN_CZT = 1, TZ_PLAN_CZT_BAND_EXACT = 2, TZ_PLAN_ZOOM = 3 };
+
+typedef struct {
+    int32_t kind;                 /* TZ_PLAN_*                                  */
+    int64_t N;                    /* samples per trace (eq. (1))                */
+    int64_t M;                    /* bins: czt, czt_band_exact, zoom            */
+    int64_t n_zeros;              /* fft_zeropad: zeros appended (eq. (5))      */
+    tz_c64 W, A;                  /* czt: contour A W^-k (eqs. (16)-(17))       */
+    int64_t fs_hz, f1_hz, f2_hz;  /* czt_band_exact: integer-hertz band         */
+    double fs, f1, f2;            /* zoom: band (Hz); fs also sets the bin      */
+                                  /* frequencies of fft_zeropad and czt         */
+    int64_t D;                    /* zoom decimation (eq. (9))                  */
+} tz_plan_params;
+
+typedef struct tz_plan tz_plan;
+
+/* Build a plan for params with opts (batch, strides, in_dtype, precision,
+ * flags, fir_taps, fir_cutoff_hz as in the one-shot calls; NULL = defaults).
+ * The same argument checks and errors as fft_zeropad / czt /
+ * czt_band_exact / zoom_fft; TZ_EINVAL for an unknown kind.  The plan owns
+ * its tables (tz_release_plans() does not free them). */
+tz_status tz_plan_create(const tz_plan_params *params, const tz_opts *opts, tz_plan **plan);
+/* Bytes of workspace tz_plan_execute() needs (0 for most shapes). */
+tz_status tz_plan_workspace(const tz_plan *plan, size_t *bytes);
+/* Run the plan on device buffers x -> X (layouts as the one-shot call with
+ * the plan's opts) with workspace (device memory of at least
+ * tz_plan_workspace() bytes, or NULL when that is 0), asynchronously on
+ * stream (NULL = the null stream).  Allocates nothing.  TZ_EINVAL for NULL
+ * buffers, a missing workspace, or a current device other than the one the
+ * plan was built on.  Executions that share a workspace must be ordered on
+ * one stream; a plan itself is read-only and may run on several streams
+ * with separate workspaces. */
+tz_status tz_plan_execute(const tz_plan *plan, const void *x, void *X, void *workspace, void *stream);
+/* Free the plan (synchronises the device first). */
+void tz_plan_destroy(tz_plan *plan);
+/* Frequency in hertz of every output bin of params (host only, no device
+ * work): fft_zeropad k fs / N_fft (eq. (3)), k < N_fft or N_fft/2 + 1 with
+ * TZ_HALF in opts->flags; czt fs (nu_A + k nu_W) for A = e^{j 2 pi nu_A},
+ * W = e^{-j 2 pi nu_W} (eqs. (16)-(17)); czt_band_exact f1 + k (f2 - f1)/M
+ * (eq. (24)); zoom f_N + (k - floor(M/2)) fs / (D K) with f_N = (f1 + f2)/2
+ * and K = zoom_short_length().  f_out holds one double per bin. */
+tz_status tz_bin_freqs(const tz_plan_params *params, const tz_opts *opts, double *f_out);
+
+/* ---------------------------------------------------------------------- */
 const char *tz_last_error(void);   /* thread-local message of the last failure */
 const char *tz_version(void);
 void tz_release_plans(void);       /* free every cached plan (synchronises)    */

@@ -18,7 +18,7 @@ __all__ = [
     "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_transfer", "czt_nd", "zoom_fft_nd", "czt_band",
     "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "lib", "ThzError",
-    "Batch", "release_plans", "version",
+    "Batch", "Plan", "bin_freqs", "release_plans", "version",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -71,6 +71,16 @@ class tz_zoom_axis(ctypes.Structure):
     ]
 
 
+class tz_plan_params(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("N", ctypes.c_int64), ("M", ctypes.c_int64), ("n_zeros", ctypes.c_int64),
+        ("W", tz_c64), ("A", tz_c64), ("fs_hz", ctypes.c_int64), ("f1_hz", ctypes.c_int64),
+        ("f2_hz", ctypes.c_int64), ("fs", ctypes.c_double), ("f1", ctypes.c_double), ("f2", ctypes.c_double),
+        ("D", ctypes.c_int64),
+    ]
+
+
+TZ_PLAN_KINDS = {"fft_zeropad": 0, "czt": 1, "czt_band_exact": 2, "zoom": 3}
 TZ_MAX_DIMS = 3
 
 # every symbol declared in include/thzspec.h
@@ -80,7 +90,8 @@ EXPORTS = (
     "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "tz_batch_create",
     "tz_batch_launch", "tz_batch_destroy", "tz_batch_describe", "tz_last_error", "tz_version",
-    "tz_release_plans",
+    "tz_release_plans", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute", "tz_plan_destroy",
+    "tz_bin_freqs",
 )
 
 _lock = threading.Lock()
@@ -124,8 +135,16 @@ def lib() -> ctypes.CDLL:
         L.tz_last_error.restype = ctypes.c_char_p
         L.tz_version.restype = ctypes.c_char_p
         L.tz_release_plans.restype = None
+        pp = ctypes.POINTER(tz_plan_params)
+        L.tz_plan_create.argtypes = [pp, po, ctypes.POINTER(vp)]
+        L.tz_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.tz_plan_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.tz_plan_destroy.argtypes = [vp]
+        L.tz_plan_destroy.restype = None
+        L.tz_bin_freqs.argtypes = [pp, po, ctypes.POINTER(ctypes.c_double)]
         for f in ("fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "zoom_fft", "czt_band", "czt_plan_shape",
-                  "tz_batch_create", "tz_batch_launch"):
+                  "tz_batch_create", "tz_batch_launch", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute",
+                  "tz_bin_freqs"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         return L
@@ -407,6 +426,112 @@ class Batch:
     def close(self):
         if self._h:
             lib().tz_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# explicit plans
+# ---------------------------------------------------------------------------
+def _plan_params(kind, N, M, n_zeros, W, A, fs, f1, f2, D, fs_hz, f1_hz, f2_hz):
+    p = tz_plan_params()
+    p.kind = TZ_PLAN_KINDS[kind]
+    p.N, p.M, p.n_zeros, p.D = int(N), int(M), int(n_zeros), int(D)
+    p.W, p.A = tz_c64(complex(W).real, complex(W).imag), tz_c64(complex(A).real, complex(A).imag)
+    p.fs, p.f1, p.f2 = float(fs), float(f1), float(f2)
+    p.fs_hz, p.f1_hz, p.f2_hz = int(fs_hz), int(f1_hz), int(f2_hz)
+    return p
+
+
+def _plan_opts(batch, in_stride, out_stride, dtype, precision, half, taps, cutoff_hz, stream):
+    o = tz_opts()
+    lib().tz_opts_init(ctypes.byref(o))
+    o.batch = int(batch)
+    o.in_stride, o.out_stride = int(in_stride), int(out_stride)
+    o.in_dtype = TZ_F64 if str(dtype).endswith("float64") else TZ_F32
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.flags = TZ_HALF if half else 0
+    o.fir_taps, o.fir_cutoff_hz = int(taps), float(cutoff_hz)
+    if stream is not None:
+        o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    return o
+
+
+def bin_freqs(kind: str, *, N: int = 1, M: int = 1, n_zeros: int = 0, W: complex = 1.0, A: complex = 1.0,
+              fs: float = 0.0, f1: float = 0.0, f2: float = 0.0, D: int = 1, fs_hz: int = 0, f1_hz: int = 0,
+              f2_hz: int = 0, half: bool = False, taps: int = 0, cutoff_hz: float = 0.0):
+    """Frequency in Hz of every output bin of a transform (host only)."""
+    import numpy as np
+    p = _plan_params(kind, N, M, n_zeros, W, A, fs, f1, f2, D, fs_hz, f1_hz, f2_hz)
+    o = _plan_opts(1, 0, 0, "float32", "fp32", half, taps, cutoff_hz, None)
+    n = (N + n_zeros if not half else (N + n_zeros) // 2 + 1) if kind == "fft_zeropad" else M
+    f = np.empty(max(int(n), 1), dtype=np.float64)
+    _check(lib().tz_bin_freqs(ctypes.byref(p), ctypes.byref(o), f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return f[:n]
+
+
+class Plan:
+    """A transform of one shape built once (tz_plan_create): execute() only
+    enqueues kernels, with a caller-owned workspace of workspace_bytes.
+
+    kind: "fft_zeropad" (N, n_zeros, half), "czt" (N, M, W, A),
+    "czt_band_exact" (N, M, fs_hz, f1_hz, f2_hz) or "zoom" (N, M, fs, f1, f2,
+    D, taps, cutoff_hz); batch traces of dtype, rows in_stride / out_stride
+    elements apart (0 = packed)."""
+
+    def __init__(self, kind: str, *, N: int, batch: int = 1, M: int = 0, n_zeros: int = 0, W: complex = 1.0,
+                 A: complex = 1.0, fs: float = 0.0, f1: float = 0.0, f2: float = 0.0, D: int = 1, fs_hz: int = 0,
+                 f1_hz: int = 0, f2_hz: int = 0, dtype="float32", precision="fp32", half: bool = False,
+                 taps: int = 0, cutoff_hz: float = 0.0, in_stride: int = 0, out_stride: int = 0, stream=None):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.kind, self.N, self.batch = kind, int(N), int(batch)
+        self.dtype = torch.float64 if str(dtype).endswith("float64") else torch.float32
+        self.bins = (N + n_zeros if not half else (N + n_zeros) // 2 + 1) if kind == "fft_zeropad" else int(M)
+        self.in_stride = int(in_stride) or self.N
+        self.out_stride = int(out_stride) or self.bins
+        p = _plan_params(kind, N, M, n_zeros, W, A, fs, f1, f2, D, fs_hz, f1_hz, f2_hz)
+        o = _plan_opts(batch, in_stride, out_stride, dtype, precision, half, taps, cutoff_hz, stream)
+        h = ctypes.c_void_p()
+        _check(lib().tz_plan_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        _check(lib().tz_plan_workspace(self._h, ctypes.byref(n)))
+        self.workspace_bytes = n.value
+
+    def execute(self, x, out, workspace=None, stream=None):
+        """x: [batch, N] (rows in_stride apart), out: [batch, bins] complex64
+        (rows out_stride apart), workspace: a GPU tensor of at least
+        workspace_bytes bytes (None when that is 0).  Asynchronous."""
+        torch = _torch()
+        if not (x.is_cuda and out.is_cuda) or x.dtype != self.dtype or out.dtype != torch.complex64:
+            raise TypeError("x must be a GPU tensor of the plan's dtype and out a complex64 GPU tensor")
+        if x.shape[0] != self.batch or x.shape[-1] != self.N or out.shape != (self.batch, self.bins):
+            raise ValueError("x must be [batch, N] and out [batch, bins] of the plan")
+        if self.batch > 1 and (x.stride(0) != self.in_stride or out.stride(0) != self.out_stride):
+            raise ValueError("row strides must be the plan's in_stride / out_stride")
+        if x.stride(-1) != 1 or out.stride(-1) != 1:
+            raise ValueError("rows must be contiguous")
+        ws = 0
+        if self.workspace_bytes:
+            if workspace is None or not workspace.is_cuda or \
+                    workspace.numel() * workspace.element_size() < self.workspace_bytes:
+                raise ValueError(f"this plan needs a GPU workspace of {self.workspace_bytes} bytes")
+            ws = workspace.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        _check(lib().tz_plan_execute(self._h, x.data_ptr(), out.data_ptr(), ws, ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().tz_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -110,8 +110,10 @@ struct PadPlan {
 };
 
 struct Device {
-  std::map<int64_t, std::unique_ptr<DevMem>> twiddles;  // L -> e^{-j 2 pi m/L}
-  std::map<int64_t, std::unique_ptr<DevMem>> roots;     // Nfft -> e^{-j 2 pi m/Nfft}
+  // shared: an explicit plan (tz_plan_create) keeps the tables it uses alive
+  // past tz_release_plans()
+  std::map<int64_t, std::shared_ptr<DevMem>> twiddles;  // L -> e^{-j 2 pi m/L}
+  std::map<int64_t, std::shared_ptr<DevMem>> roots;     // Nfft -> e^{-j 2 pi m/Nfft}
   std::map<std::string, std::shared_ptr<BluePlan>> blue;
   std::map<std::string, std::shared_ptr<ZoomPlan>> zoom;
   std::map<std::string, std::shared_ptr<PadPlan>> pad;
@@ -138,29 +140,34 @@ std::string phase_key(const PhaseParams &p) {
   return buf;
 }
 
-tz_status get_twiddles(Device &d, int64_t L, hipStream_t s, const float2 **out) {
+// tables held by an explicit plan beside its Bluestein / zoom / pad plans
+using Keep = std::vector<std::shared_ptr<DevMem>>;
+
+tz_status get_twiddles(Device &d, int64_t L, hipStream_t s, const float2 **out, Keep *keep = nullptr) {
   auto &slot = d.twiddles[L];
   if (!slot) {
-    std::unique_ptr<DevMem> m(new DevMem());
+    auto m = std::make_shared<DevMem>();
     TZ_HIP(m->alloc(sizeof(float2) * L), "twiddle table");
     TZ_HIP(build_twiddles(m->as<float2>(), L, s), "twiddle build");
     TZ_HIP(hipStreamSynchronize(s), "twiddle build");
-    slot = std::move(m);
+    slot = m;
   }
   *out = slot->as<float2>();
+  if (keep) keep->push_back(slot);
   return TZ_OK;
 }
 
-tz_status get_roots(Device &d, int64_t Nfft, hipStream_t s, const float2 **out) {
+tz_status get_roots(Device &d, int64_t Nfft, hipStream_t s, const float2 **out, Keep *keep = nullptr) {
   auto &slot = d.roots[Nfft];
   if (!slot) {
-    std::unique_ptr<DevMem> m(new DevMem());
+    auto m = std::make_shared<DevMem>();
     TZ_HIP(m->alloc(sizeof(float2) * Nfft), "root table");
     TZ_HIP(build_root_table(m->as<float2>(), Nfft, Nfft, s), "root build");
     TZ_HIP(hipStreamSynchronize(s), "root build");
-    slot = std::move(m);
+    slot = m;
   }
   *out = slot->as<float2>();
+  if (keep) keep->push_back(slot);
   return TZ_OK;
 }
 
@@ -320,50 +327,70 @@ tz_status spiral_scaling(int64_t N, int64_t M, double ma, double mw, PhaseParams
   return TZ_OK;
 }
 
-// four-step path: chunks of traces through the plan's per-stream workspace
-tz_status run_long(Device &d, BluePlan &pl, const void *x, int in_kind, void *X, const Common &c, int64_t M,
-                   hipStream_t s) {
-  LongLaunch a;
-  a.L1 = pl.L1;
-  a.L2 = pl.L / pl.L1;
-  a.precision = c.precision;
-  if (c.precision != TZ_FP32 && !long_rows_mfma_supported(a.L1, a.L2))
-    return fail(TZ_EUNSUPPORTED, "split precision on the four-step path needs rows of L2 in {4096, 8192, "
-                                 "16384}; N=%lld, M=%lld has L=%d = %d x %d",
-                (long long)pl.N, (long long)pl.M, pl.L, a.L1, a.L2);
-  tz_status st = get_twiddles(d, a.L1, s, &a.tw_col);
-  if (st) return st;
-  if ((st = get_twiddles(d, a.L2, s, &a.tw_row))) return st;
-  a.chunk = kLongChunkBytes / ((int64_t)pl.L * 8);
-  if (a.chunk < 1) a.chunk = 1;
-  if (a.chunk > c.B) a.chunk = c.B;
-  void *w = nullptr;
-  if ((st = pl.work.get(s, sizeof(float2) * (size_t)pl.L * (size_t)a.chunk, &w))) return st;
-  a.work = (float2 *)w;
-  a.x = x;
-  a.in_kind = in_kind;
-  a.xs = c.xs;
-  a.N = pl.N;
-  a.c_pre = pl.c_pre.as<float2>();
-  a.c_post = pl.c_post.as<float2>();
-  a.Vt = pl.V.as<float2>();
-  a.tbig = pl.tbig.as<float2>();
-  a.X = (float2 *)X;
-  a.os = c.os;
-  a.M = M;
-  a.B = c.B;
-  TZ_HIP(launch_czt_long(a, s), "czt (four-step) launch");
-  return TZ_OK;
+// Everything a Bluestein launch needs beyond x and X, resolved through the
+// device's table caches (which may allocate and synchronise); exec_blue then
+// only launches kernels.  The four-step path runs chunks of traces through a
+// workspace of ws bytes.
+struct BlueExec {
+  std::shared_ptr<BluePlan> pl;
+  const float2 *tw = nullptr, *tw_col = nullptr, *tw_row = nullptr;
+  int64_t chunk = 0;
+  size_t ws = 0;
+};
+
+tz_status prepare_blue(Device &d, const std::shared_ptr<BluePlan> &pl, int in_kind, const Common &c,
+                       hipStream_t s, BlueExec *e, Keep *keep = nullptr) {
+  e->pl = pl;
+  if (pl->L1) {
+    const int L2 = pl->L / pl->L1;
+    if (c.precision != TZ_FP32 && !long_rows_mfma_supported(pl->L1, L2))
+      return fail(TZ_EUNSUPPORTED, "split precision on the four-step path needs rows of L2 in {4096, 8192, "
+                                   "16384}; N=%lld, M=%lld has L=%d = %d x %d",
+                  (long long)pl->N, (long long)pl->M, pl->L, pl->L1, L2);
+    tz_status st = get_twiddles(d, pl->L1, s, &e->tw_col, keep);
+    if (st) return st;
+    if ((st = get_twiddles(d, L2, s, &e->tw_row, keep))) return st;
+    e->chunk = kLongChunkBytes / ((int64_t)pl->L * 8);
+    if (e->chunk < 1) e->chunk = 1;
+    if (e->chunk > c.B) e->chunk = c.B;
+    e->ws = sizeof(float2) * (size_t)pl->L * (size_t)e->chunk;
+    return TZ_OK;
+  }
+  if (c.precision != TZ_FP32 && !czt_mfma_supported(pl->L, pl->nseg, pl->nblk, in_kind))
+    return fail(TZ_EUNSUPPORTED, "split precision needs L in {4096, 8192, 16384} with one bin block "
+                                 "(N + M - 1 <= 16384) and real input; this plan has L=%d",
+                pl->L);
+  return get_twiddles(d, pl->L, s, &e->tw, keep);
 }
 
-// M_out < pl.M evaluates only the first M_out bins (0 = all)
-tz_status run_blue(Device &d, BluePlan &pl, const void *x, int in_kind, void *X, const Common &c,
-                   hipStream_t s, int64_t M_out = 0) {
-  const int64_t M = M_out > 0 ? M_out : pl.M;
-  if (pl.L1) return run_long(d, pl, x, in_kind, X, c, M, s);
-  const float2 *tw = nullptr;
-  tz_status st = get_twiddles(d, pl.L, s, &tw);
-  if (st) return st;
+// launches only; M (<= the plan's M) bins per trace, ws of e.ws bytes
+tz_status exec_blue(const BlueExec &e, const void *x, int in_kind, void *X, const Common &c, int64_t M, void *ws,
+                    hipStream_t s) {
+  const BluePlan &pl = *e.pl;
+  if (pl.L1) {
+    LongLaunch a;
+    a.L1 = pl.L1;
+    a.L2 = pl.L / pl.L1;
+    a.precision = c.precision;
+    a.tw_col = e.tw_col;
+    a.tw_row = e.tw_row;
+    a.chunk = e.chunk;
+    a.work = (float2 *)ws;
+    a.x = x;
+    a.in_kind = in_kind;
+    a.xs = c.xs;
+    a.N = pl.N;
+    a.c_pre = pl.c_pre.as<float2>();
+    a.c_post = pl.c_post.as<float2>();
+    a.Vt = pl.V.as<float2>();
+    a.tbig = pl.tbig.as<float2>();
+    a.X = (float2 *)X;
+    a.os = c.os;
+    a.M = M;
+    a.B = c.B;
+    TZ_HIP(launch_czt_long(a, s), "czt (four-step) launch");
+    return TZ_OK;
+  }
   CztLaunch a;
   a.x = x;
   a.in_kind = in_kind;
@@ -374,7 +401,7 @@ tz_status run_blue(Device &d, BluePlan &pl, const void *x, int in_kind, void *X,
   a.c_pre = pl.c_pre.as<float2>();
   a.c_post = pl.c_post.as<float2>();
   a.V = pl.V.as<float2>();
-  a.tw = tw;
+  a.tw = e.tw;
   a.X = (float2 *)X;
   a.os = c.os;
   a.M = M;
@@ -384,15 +411,23 @@ tz_status run_blue(Device &d, BluePlan &pl, const void *x, int in_kind, void *X,
   a.B = c.B;
   a.precision = c.precision;
   if (c.precision != TZ_FP32) {
-    if (!czt_mfma_supported(pl.L, pl.nseg, pl.nblk, in_kind))
-      return fail(TZ_EUNSUPPORTED, "split precision needs L in {4096, 8192, 16384} with one bin block "
-                                   "(N + M - 1 <= 16384) and real input; this plan has L=%d",
-                  pl.L);
     TZ_HIP(launch_czt_mfma(a, s), "czt (split precision) launch");
-    return TZ_OK;
+  } else {
+    TZ_HIP(launch_czt(a, s), "czt launch");
   }
-  TZ_HIP(launch_czt(a, s), "czt launch");
   return TZ_OK;
+}
+
+// one-shot form: the four-step workspace is the plan's per-stream buffer;
+// M_out < pl.M evaluates only the first M_out bins (0 = all)
+tz_status run_blue(Device &d, std::shared_ptr<BluePlan> pl, const void *x, int in_kind, void *X, const Common &c,
+                   hipStream_t s, int64_t M_out = 0) {
+  BlueExec e;
+  tz_status st = prepare_blue(d, pl, in_kind, c, s, &e);
+  if (st) return st;
+  void *ws = nullptr;
+  if (e.ws && (st = pl->work.get(s, e.ws, &ws))) return st;
+  return exec_blue(e, x, in_kind, X, c, M_out > 0 ? M_out : pl->M, ws, s);
 }
 
 // zoom arguments shared by zoom_fft and zoom_fft_nd; K = round(M fs / (D (f2 - f1)))
@@ -440,12 +475,28 @@ tz_status get_zoom(Device &d, int64_t N, double fs, double f1, double f2, int64_
   return TZ_OK;
 }
 
-// front end (mix, FIR, decimate) into the plan's per-stream u, then the
-// short DFT into X; x holds c.B rows c.xs elements apart
-tz_status run_zoom(Device &d, ZoomPlan &z, const void *x, int in_kind, void *X, const Common &c) {
-  void *u = nullptr;
-  tz_status st = z.u.get(c.stream, sizeof(float2) * (size_t)z.LD * (size_t)c.B, &u);
-  if (st) return st;
+// the zoom's front end writes the decimated rows u (u_bytes), the short DFT
+// reads them; both resolved like BlueExec
+struct ZoomExec {
+  std::shared_ptr<ZoomPlan> z;
+  BlueExec b;
+  size_t u_bytes = 0;
+};
+
+tz_status prepare_zoom(Device &d, const std::shared_ptr<ZoomPlan> &z, const Common &c, hipStream_t s,
+                       ZoomExec *e, Keep *keep = nullptr) {
+  e->z = z;
+  e->u_bytes = (sizeof(float2) * (size_t)z->LD * (size_t)c.B + 255) & ~(size_t)255;
+  Common c2 = c;
+  c2.xs = z->LD;
+  return prepare_blue(d, z->blue, 2, c2, s, &e->b, keep);
+}
+
+// front end (mix, FIR, decimate) into u, then the short DFT into X; x holds
+// c.B rows c.xs elements apart
+tz_status exec_zoom(const ZoomExec &e, const void *x, int in_kind, void *X, const Common &c, void *u, void *ws,
+                    hipStream_t s) {
+  const ZoomPlan &z = *e.z;
   ZoomFrontLaunch f;
   f.x = x;
   f.in_kind = in_kind;
@@ -458,10 +509,22 @@ tz_status run_zoom(Device &d, ZoomPlan &z, const void *x, int in_kind, void *X, 
   f.ph = z.ph.as<double2>();
   f.u = (float2 *)u;
   f.B = c.B;
-  TZ_HIP(launch_zoom_front(f, c.stream), "zoom front-end launch");
+  TZ_HIP(launch_zoom_front(f, s), "zoom front-end launch");
   Common c2 = c;
   c2.xs = z.LD;
-  return run_blue(d, *z.blue, u, 2, X, c2, c.stream);
+  return exec_blue(e.b, u, 2, X, c2, z.blue->M, ws, s);
+}
+
+// one-shot form: u and the four-step workspace are the plans' per-stream buffers
+tz_status run_zoom(Device &d, const std::shared_ptr<ZoomPlan> &zp, const void *x, int in_kind, void *X,
+                   const Common &c) {
+  ZoomExec e;
+  tz_status st = prepare_zoom(d, zp, c, c.stream, &e);
+  if (st) return st;
+  void *u = nullptr, *ws = nullptr;
+  if ((st = zp->u.get(c.stream, e.u_bytes, &u))) return st;
+  if (e.b.ws && (st = zp->blue->work.get(c.stream, e.b.ws, &ws))) return st;
+  return exec_zoom(e, x, in_kind, X, c, u, ws, c.stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -599,6 +662,114 @@ PhaseParams zoom_phase(int64_t K, int64_t M) {
   return p;
 }
 
+// ---------------------------------------------------------------------------
+// zero-padded FFT: plan lookup, resolution of its tables, launches
+// ---------------------------------------------------------------------------
+tz_status get_pad(Device &d, int64_t N, int64_t nfft, hipStream_t s, std::shared_ptr<PadPlan> *out) {
+  char kb[64];
+  snprintf(kb, sizeof kb, "%lld/%lld", (long long)N, (long long)nfft);
+  auto &pp = d.pad[kb];
+  if (!pp) {
+    auto pl = std::make_shared<PadPlan>();
+    pl->N = N;
+    pl->Nfft = nfft;
+    pl->F = 0;
+    if (nfft % 2 == 0) {
+      const int64_t nh = nfft / 2;
+      for (int64_t F = 1024; F <= 2048; F <<= 1)
+        if (2 * F >= N && nh % F == 0 && fftpad_real_supported((int)F, (int)(nh / F))) {
+          pl->realF = (int)F;
+          pl->realP = (int)(nh / F);
+          break;
+        }
+    }
+    for (int64_t F = kMinL; F <= kMaxL; F <<= 1)
+      if (F >= N && nfft % F == 0) {
+        pl->F = (int)F;
+        pl->P = (int)(nfft / F);
+        break;
+      }
+    if (!pl->F) {  // no power-of-two factor >= N: evaluate the same bins as a CZT
+      PhaseParams p{};
+      p.rational = 1;
+      p.q = nfft;
+      p.pa = 0;
+      p.pw = 1;
+      p.a = 0.0;
+      p.w = 1.0 / (double)nfft;
+      tz_status st = get_blue(d, N, nfft, p, s, &pl->blue, true);
+      if (st) return st;
+    }
+    pp = pl;
+  }
+  *out = pp;
+  return TZ_OK;
+}
+
+struct PadExec {
+  std::shared_ptr<PadPlan> pp;
+  BlueExec b;  // N_fft without a fast factorisation
+  const float2 *tw = nullptr, *root = nullptr, *rh = nullptr, *rf = nullptr;
+  int64_t nout = 0;
+  int half = 0;
+};
+
+tz_status prepare_pad(Device &d, const std::shared_ptr<PadPlan> &pp, int in_kind, bool half, const Common &c,
+                      hipStream_t s, PadExec *e, Keep *keep = nullptr) {
+  e->pp = pp;
+  e->half = half ? 1 : 0;
+  e->nout = half ? pp->Nfft / 2 + 1 : pp->Nfft;
+  if (pp->blue) return prepare_blue(d, pp->blue, in_kind, c, s, &e->b, keep);
+  tz_status st;
+  if (pp->realF) {
+    if ((st = get_twiddles(d, pp->realF, s, &e->tw, keep))) return st;
+    if ((st = get_roots(d, pp->Nfft / 2, s, &e->rh, keep))) return st;
+    return get_roots(d, pp->Nfft, s, &e->rf, keep);
+  }
+  if ((st = get_twiddles(d, pp->F, s, &e->tw, keep))) return st;
+  if (pp->P > 1 && (st = get_roots(d, pp->Nfft, s, &e->root, keep))) return st;
+  return TZ_OK;
+}
+
+tz_status exec_pad(const PadExec &e, const void *x, int in_kind, void *X, const Common &c, void *ws, hipStream_t s) {
+  const PadPlan &pp = *e.pp;
+  // a Bluestein plan evaluates all Nfft bins; with TZ_HALF only the first nout
+  if (pp.blue) return exec_blue(e.b, x, in_kind, X, c, e.nout, ws, s);
+  if (pp.realF) {
+    PadRealLaunch a;
+    a.x = x;
+    a.in_kind = in_kind;
+    a.xs = c.xs;
+    a.N = pp.N;
+    a.F = pp.realF;
+    a.P = pp.realP;
+    a.tw = e.tw;
+    a.root_h = e.rh;
+    a.root_f = e.rf;
+    a.X = (float2 *)X;
+    a.os = c.os;
+    a.half = e.half;
+    a.B = c.B;
+    TZ_HIP(launch_fftpad_real(a, s), "fft_zeropad launch");
+    return TZ_OK;
+  }
+  PadLaunch a;
+  a.x = x;
+  a.in_kind = in_kind;
+  a.xs = c.xs;
+  a.N = pp.N;
+  a.F = pp.F;
+  a.P = pp.P;
+  a.tw = e.tw;
+  a.root = e.root;
+  a.X = (float2 *)X;
+  a.os = c.os;
+  a.nout = e.nout;
+  a.B = c.B;
+  TZ_HIP(launch_fftpad(a, s), "fft_zeropad launch");
+  return TZ_OK;
+}
+
 }  // namespace tz
 
 using namespace tz;
@@ -636,7 +807,7 @@ tz_status czt(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *X, 
   std::shared_ptr<BluePlan> pl;
   const bool fast = c.precision == TZ_FP32 && p.ma == 0.0 && p.mw == 0.0;
   if ((st = get_blue(d, N, M, p, c.stream, &pl, fast))) return st;
-  return run_blue(d, *pl, x, c.in_kind, X, c, c.stream);
+  return run_blue(d, pl, x, c.in_kind, X, c, c.stream);
 }
 
 tz_status czt_transfer(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *H, const tz_opts *o) {
@@ -691,7 +862,7 @@ tz_status czt_band_exact(const void *x, int64_t N, int64_t M, int64_t fs_hz, int
   Device &d = device_state(current_device());
   std::shared_ptr<BluePlan> pl;
   if ((st = get_blue(d, N, M, p, c.stream, &pl, c.precision == TZ_FP32))) return st;
-  return run_blue(d, *pl, x, c.in_kind, X, c, c.stream);
+  return run_blue(d, pl, x, c.in_kind, X, c, c.stream);
 }
 
 tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const tz_opts *o) {
@@ -706,86 +877,13 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
   if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "fft_zeropad runs in FP32 only");
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
-  char kb[64];
-  snprintf(kb, sizeof kb, "%lld/%lld", (long long)N, (long long)nfft);
-  auto &pp = d.pad[kb];
-  if (!pp) {
-    auto pl = std::make_shared<PadPlan>();
-    pl->N = N;
-    pl->Nfft = nfft;
-    pl->F = 0;
-    if (nfft % 2 == 0) {
-      const int64_t nh = nfft / 2;
-      for (int64_t F = 1024; F <= 2048; F <<= 1)
-        if (2 * F >= N && nh % F == 0 && fftpad_real_supported((int)F, (int)(nh / F))) {
-          pl->realF = (int)F;
-          pl->realP = (int)(nh / F);
-          break;
-        }
-    }
-    for (int64_t F = kMinL; F <= kMaxL; F <<= 1)
-      if (F >= N && nfft % F == 0) {
-        pl->F = (int)F;
-        pl->P = (int)(nfft / F);
-        break;
-      }
-    if (!pl->F) {  // no power-of-two factor >= N: evaluate the same bins as a CZT
-      PhaseParams p{};
-      p.rational = 1;
-      p.q = nfft;
-      p.pa = 0;
-      p.pw = 1;
-      p.a = 0.0;
-      p.w = 1.0 / (double)nfft;
-      if ((st = get_blue(d, N, nfft, p, c.stream, &pl->blue, true))) return st;
-    }
-    pp = pl;
-  }
-  if (pp->blue) {
-    // the cached Bluestein plan evaluates all Nfft bins; with TZ_HALF only
-    // the first nout are wanted
-    return run_blue(d, *pp->blue, x, c.in_kind, X, c, c.stream, nout);
-  }
-  if (pp->realF) {
-    const float2 *tw = nullptr, *rh = nullptr, *rf = nullptr;
-    if ((st = get_twiddles(d, pp->realF, c.stream, &tw))) return st;
-    if ((st = get_roots(d, nfft / 2, c.stream, &rh))) return st;
-    if ((st = get_roots(d, nfft, c.stream, &rf))) return st;
-    PadRealLaunch a;
-    a.x = x;
-    a.in_kind = c.in_kind;
-    a.xs = c.xs;
-    a.N = N;
-    a.F = pp->realF;
-    a.P = pp->realP;
-    a.tw = tw;
-    a.root_h = rh;
-    a.root_f = rf;
-    a.X = (float2 *)X;
-    a.os = c.os;
-    a.half = half ? 1 : 0;
-    a.B = c.B;
-    TZ_HIP(launch_fftpad_real(a, c.stream), "fft_zeropad launch");
-    return TZ_OK;
-  }
-  const float2 *tw = nullptr, *root = nullptr;
-  if ((st = get_twiddles(d, pp->F, c.stream, &tw))) return st;
-  if (pp->P > 1 && (st = get_roots(d, nfft, c.stream, &root))) return st;
-  PadLaunch a;
-  a.x = x;
-  a.in_kind = c.in_kind;
-  a.xs = c.xs;
-  a.N = N;
-  a.F = pp->F;
-  a.P = pp->P;
-  a.tw = tw;
-  a.root = root;
-  a.X = (float2 *)X;
-  a.os = c.os;
-  a.nout = nout;
-  a.B = c.B;
-  TZ_HIP(launch_fftpad(a, c.stream), "fft_zeropad launch");
-  return TZ_OK;
+  std::shared_ptr<PadPlan> pp;
+  if ((st = get_pad(d, N, nfft, c.stream, &pp))) return st;
+  PadExec e;
+  if ((st = prepare_pad(d, pp, c.in_kind, half, c, c.stream, &e))) return st;
+  void *ws = nullptr;
+  if (e.b.ws && (st = pp->blue->work.get(c.stream, e.b.ws, &ws))) return st;
+  return exec_pad(e, x, c.in_kind, X, c, ws, c.stream);
 }
 
 tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, int64_t M, int64_t D, void *X,
@@ -802,7 +900,7 @@ tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, in
   Device &d = device_state(current_device());
   std::shared_ptr<ZoomPlan> zp;
   if ((st = get_zoom(d, N, fs, f1, f2, M, D, T, fc, K, c.stream, &zp))) return st;
-  return run_zoom(d, *zp, x, c.in_kind, X, c);
+  return run_zoom(d, zp, x, c.in_kind, X, c);
 }
 
 tz_status czt_nd(const void *x, int ndim, const tz_czt_axis *axes, void *X, const tz_opts *o) {
@@ -850,7 +948,7 @@ tz_status czt_nd(const void *x, int ndim, const tz_czt_axis *axes, void *X, cons
                   ca.B = rows;
                   ca.xs = is;
                   ca.os = os;
-                  return run_blue(d, *pl[a], in, kind, out, ca, c.stream);
+                  return run_blue(d, pl[a], in, kind, out, ca, c.stream);
                 });
 }
 
@@ -893,7 +991,7 @@ tz_status zoom_fft_nd(const void *x, int ndim, const tz_zoom_axis *axes, void *X
                   ca.B = rows;
                   ca.xs = is;
                   ca.os = os;
-                  return run_zoom(d, *zp[a], in, kind, out, ca);
+                  return run_zoom(d, zp[a], in, kind, out, ca);
                 });
 }
 
@@ -947,6 +1045,190 @@ tz_status czt_plan_shape(int64_t N, int64_t M, int64_t *L, int64_t *blocks) {
   *L = k == 0 ? llong : l;
   *blocks = k == 0 ? 1 : (int64_t)nblk * nseg;
   return TZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// explicit plans
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct tz_plan {
+  int kind = 0, dev = 0;
+  Common c{};
+  int64_t bins = 0;
+  BlueExec b;
+  ZoomExec z;
+  PadExec p;
+  Keep keep;            // twiddle / root tables, held past tz_release_plans()
+  size_t ws = 0;        // workspace bytes
+  size_t u_bytes = 0;   // zoom: the workspace starts with the decimated rows
+};
+
+namespace {
+
+// argument checks of the one-shot calls without buffers (the plan gets them
+// at execution)
+const char kNoBuffer = 0;
+
+tz_status plan_czt_phase(const tz_plan_params &pp, const Common &c, PhaseParams *p) {
+  if (pp.M < 1) return fail(TZ_EINVAL, "M must be >= 1 (got %lld)", (long long)pp.M);
+  if (!finite_nonzero(pp.W) || !finite_nonzero(pp.A)) return fail(TZ_EINVAL, "W and A must be finite and non-zero");
+  *p = PhaseParams{};
+  p->rational = 0;
+  p->a = frac01(atan2(pp.A.im, pp.A.re) / (2.0 * M_PI));
+  p->w = frac01(-atan2(pp.W.im, pp.W.re) / (2.0 * M_PI));
+  if (!unit(pp.W) || !unit(pp.A)) {
+    tz_status st = spiral_scaling(pp.N, pp.M, log(hypot(pp.A.re, pp.A.im)), log(hypot(pp.W.re, pp.W.im)), p);
+    if (st) return st;
+    if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "spiral contours run in FP32 only");
+  }
+  return TZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tz_status tz_plan_create(const tz_plan_params *pp, const tz_opts *o, tz_plan **out) {
+  if (!pp || !out) return fail(TZ_EINVAL, "params and plan must not be NULL");
+  *out = nullptr;
+  std::unique_ptr<tz_plan> P(new tz_plan());
+  P->kind = pp->kind;
+  Common &c = P->c;
+  const void *nb = &kNoBuffer;
+  tz_status st = TZ_OK;
+  switch (pp->kind) {
+    case TZ_PLAN_FFT_ZEROPAD: {
+      if (pp->n_zeros < 0) return fail(TZ_EINVAL, "n_zeros must be >= 0 (got %lld)", (long long)pp->n_zeros);
+      const int64_t nfft = pp->N + pp->n_zeros;
+      if (nfft > INT32_MAX) return fail(TZ_EINVAL, "N + n_zeros exceeds 2^31 - 1");
+      const bool half = o && (o->flags & TZ_HALF);
+      P->bins = half ? nfft / 2 + 1 : nfft;
+      if ((st = check_common(nb, pp->N, (void *)nb, o, P->bins, &c))) return st;
+      if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "fft_zeropad runs in FP32 only");
+      std::lock_guard<std::mutex> lk(g_mu);
+      Device &d = device_state(current_device());
+      std::shared_ptr<PadPlan> pad;
+      if ((st = get_pad(d, pp->N, nfft, c.stream, &pad))) return st;
+      if ((st = prepare_pad(d, pad, c.in_kind, half, c, c.stream, &P->p, &P->keep))) return st;
+      P->ws = P->p.b.ws;
+      break;
+    }
+    case TZ_PLAN_CZT:
+    case TZ_PLAN_CZT_BAND_EXACT: {
+      PhaseParams ph{};
+      P->bins = pp->M;
+      if ((st = check_common(nb, pp->N, (void *)nb, o, pp->M < 1 ? 1 : pp->M, &c))) return st;
+      bool fast = c.precision == TZ_FP32;
+      if (pp->kind == TZ_PLAN_CZT) {
+        if ((st = plan_czt_phase(*pp, c, &ph))) return st;
+        fast = fast && ph.ma == 0.0 && ph.mw == 0.0;
+      } else {
+        if (pp->M < 1) return fail(TZ_EINVAL, "M must be >= 1 (got %lld)", (long long)pp->M);
+        if (pp->fs_hz < 1 || pp->f1_hz < 0 || pp->f2_hz <= pp->f1_hz)
+          return fail(TZ_EINVAL, "need fs >= 1, f1 >= 0, f2 > f1");
+        ph = band_phase(pp->fs_hz, pp->f1_hz, pp->f2_hz, pp->M);
+      }
+      std::lock_guard<std::mutex> lk(g_mu);
+      Device &d = device_state(current_device());
+      std::shared_ptr<BluePlan> pl;
+      if ((st = get_blue(d, pp->N, pp->M, ph, c.stream, &pl, fast))) return st;
+      if ((st = prepare_blue(d, pl, c.in_kind, c, c.stream, &P->b, &P->keep))) return st;
+      P->ws = P->b.ws;
+      break;
+    }
+    case TZ_PLAN_ZOOM: {
+      const int T = (o && o->fir_taps) ? o->fir_taps : 63;
+      const double fc = (o && o->fir_cutoff_hz != 0.0) ? o->fir_cutoff_hz : pp->fs / (2.0 * (double)pp->D);
+      int64_t K = 0;
+      if ((st = check_zoom(pp->fs, pp->f1, pp->f2, pp->M, pp->D, T, fc, &K))) return st;
+      P->bins = pp->M;
+      if ((st = check_common(nb, pp->N, (void *)nb, o, pp->M, &c))) return st;
+      if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "zoom_fft runs in FP32 only");
+      std::lock_guard<std::mutex> lk(g_mu);
+      Device &d = device_state(current_device());
+      std::shared_ptr<ZoomPlan> zp;
+      if ((st = get_zoom(d, pp->N, pp->fs, pp->f1, pp->f2, pp->M, pp->D, T, fc, K, c.stream, &zp))) return st;
+      if ((st = prepare_zoom(d, zp, c, c.stream, &P->z, &P->keep))) return st;
+      P->u_bytes = P->z.u_bytes;
+      P->ws = P->z.u_bytes + P->z.b.ws;
+      break;
+    }
+    default:
+      return fail(TZ_EINVAL, "unknown plan kind %d", pp->kind);
+  }
+  P->dev = current_device();
+  *out = P.release();
+  return TZ_OK;
+}
+
+tz_status tz_plan_workspace(const tz_plan *P, size_t *bytes) {
+  if (!P || !bytes) return fail(TZ_EINVAL, "plan and bytes must not be NULL");
+  *bytes = P->ws;
+  return TZ_OK;
+}
+
+tz_status tz_plan_execute(const tz_plan *P, const void *x, void *X, void *workspace, void *stream) {
+  if (!P) return fail(TZ_EINVAL, "plan must not be NULL");
+  if (!x || !X) return fail(TZ_EINVAL, "x and X must be device pointers, got NULL");
+  if (P->ws && !workspace) return fail(TZ_EINVAL, "this plan needs a workspace of %zu bytes", P->ws);
+  const int dev = current_device();
+  if (dev != P->dev) return fail(TZ_EINVAL, "plan built on device %d, current device is %d", P->dev, dev);
+  const hipStream_t s = (hipStream_t)stream;
+  const Common &c = P->c;
+  switch (P->kind) {
+    case TZ_PLAN_FFT_ZEROPAD: return exec_pad(P->p, x, c.in_kind, X, c, workspace, s);
+    case TZ_PLAN_ZOOM:
+      return exec_zoom(P->z, x, c.in_kind, X, c, workspace, (char *)workspace + P->u_bytes, s);
+    default: return exec_blue(P->b, x, c.in_kind, X, c, P->bins, workspace, s);
+  }
+}
+
+void tz_plan_destroy(tz_plan *P) {
+  if (!P) return;
+  (void)hipDeviceSynchronize();  // work that reads its tables may be in flight
+  std::lock_guard<std::mutex> lk(g_mu);
+  delete P;
+}
+
+tz_status tz_bin_freqs(const tz_plan_params *pp, const tz_opts *o, double *f) {
+  if (!pp || !f) return fail(TZ_EINVAL, "params and f_out must not be NULL");
+  switch (pp->kind) {
+    case TZ_PLAN_FFT_ZEROPAD: {
+      if (pp->N < 1 || pp->n_zeros < 0 || !(pp->fs > 0.0) || !isfinite(pp->fs))
+        return fail(TZ_EINVAL, "need N >= 1, n_zeros >= 0 and finite fs > 0");
+      const int64_t nfft = pp->N + pp->n_zeros;
+      const int64_t nout = (o && (o->flags & TZ_HALF)) ? nfft / 2 + 1 : nfft;
+      for (int64_t k = 0; k < nout; ++k) f[k] = (double)k * pp->fs / (double)nfft;
+      return TZ_OK;
+    }
+    case TZ_PLAN_CZT: {
+      if (pp->M < 1 || !finite_nonzero(pp->W) || !finite_nonzero(pp->A) || !(pp->fs > 0.0) || !isfinite(pp->fs))
+        return fail(TZ_EINVAL, "need M >= 1, finite non-zero W and A, finite fs > 0");
+      const double na = atan2(pp->A.im, pp->A.re) / (2.0 * M_PI), nw = -atan2(pp->W.im, pp->W.re) / (2.0 * M_PI);
+      for (int64_t k = 0; k < pp->M; ++k) f[k] = pp->fs * (na + (double)k * nw);
+      return TZ_OK;
+    }
+    case TZ_PLAN_CZT_BAND_EXACT: {
+      if (pp->M < 1 || pp->fs_hz < 1 || pp->f1_hz < 0 || pp->f2_hz <= pp->f1_hz)
+        return fail(TZ_EINVAL, "need M >= 1, fs >= 1, f1 >= 0, f2 > f1");
+      const double df = (double)(pp->f2_hz - pp->f1_hz) / (double)pp->M;
+      for (int64_t k = 0; k < pp->M; ++k) f[k] = (double)pp->f1_hz + (double)k * df;
+      return TZ_OK;
+    }
+    case TZ_PLAN_ZOOM: {
+      const int T = (o && o->fir_taps) ? o->fir_taps : 63;
+      const double fc = (o && o->fir_cutoff_hz != 0.0) ? o->fir_cutoff_hz : pp->fs / (2.0 * (double)pp->D);
+      int64_t K = 0;
+      tz_status st = check_zoom(pp->fs, pp->f1, pp->f2, pp->M, pp->D, T, fc, &K);
+      if (st) return st;
+      const double fN = 0.5 * (pp->f1 + pp->f2), step = pp->fs / ((double)pp->D * (double)K);
+      for (int64_t k = 0; k < pp->M; ++k) f[k] = fN + (double)(k - pp->M / 2) * step;
+      return TZ_OK;
+    }
+    default:
+      return fail(TZ_EINVAL, "unknown plan kind %d", pp->kind);
+  }
 }
 
 void tz_release_plans(void) {

@@ -249,3 +249,58 @@ def test_resolution_sweep_shapes(tz):
     for df in pts[1:]:
         s = bs.shapes(tz, df)
         assert abs(bs.FS / s["n_fft"] - df) <= bs.FS / s["n_fft"] ** 2
+
+
+def test_bin_freqs_closed_forms(tz):
+    """Frequencies of the output bins (host helper, no device work)."""
+    # eq. (24): czt_band_exact bins at f1 + k (f2 - f1)/M, f2 excluded
+    f = tz.bin_freqs("czt_band_exact", M=4096, fs_hz=20 * 10**12, f1_hz=2 * 10**11, f2_hz=25 * 10**11)
+    assert len(f) == 4096 and f[0] == 2e11 and f[-1] < 2.5e12
+    assert np.allclose(np.diff(f), 2.3e12 / 4096, rtol=1e-12, atol=0)
+    # the W, A of eqs. (22)-(23) trace the same grid on the plain CZT
+    W, A = tz.czt_band(20e12, 0.2e12, 2.5e12, 4096)
+    g = tz.bin_freqs("czt", M=4096, W=W, A=A, fs=20e12)
+    assert np.max(np.abs(g - f)) < 1e-3 * (2.3e12 / 4096)
+    # Section 3.1: 128 samples at 8 kHz over 100-1000 Hz are 7.03 Hz apart
+    t = json.load(open(GOLDEN))["two_tone_czt_plotting_resolution"]
+    h = tz.bin_freqs("czt_band_exact", M=t["samples"], fs_hz=t["fs_hz"], f1_hz=t["f1_hz"], f2_hz=t["f2_hz"])
+    assert round(h[1] - h[0], t["printed_digits"]) == t["printed_hz"]
+    # eq. (3): FFT bin k at k fs / N_fft; the half spectrum ends at fs / 2
+    z = tz.bin_freqs("fft_zeropad", N=1000, n_zeros=1048, fs=20e12)
+    assert len(z) == 2048 and z[0] == 0.0 and z[1] == 20e12 / 2048
+    zh = tz.bin_freqs("fft_zeropad", N=1000, n_zeros=1048, fs=20e12, half=True)
+    assert len(zh) == 1025 and zh[-1] == 10e12
+    # zoom grid: bin floor(M/2) at f_N = (f1 + f2)/2, spacing fs / (D K)
+    K = tz.zoom_short_length(20e12, 0.2e12, 2.5e12, 4096, 6)
+    q = tz.bin_freqs("zoom", M=4096, fs=20e12, f1=0.2e12, f2=2.5e12, D=6)
+    assert q[2048] == pytest.approx(1.35e12, rel=1e-15)
+    assert np.allclose(np.diff(q), 20e12 / (6 * K), rtol=1e-12, atol=0)
+
+
+def test_plan_invalid_arguments_rejected_before_device_work(tz):
+    L = tz.lib()
+    h = ctypes.c_void_p()
+
+    def create(kind, **kw):
+        p = tz._plan_params(kind, kw.get("N", 100), kw.get("M", 50), kw.get("n_zeros", 0), kw.get("W", 1.0),
+                            kw.get("A", 1.0), kw.get("fs", 20e12), kw.get("f1", 1e12), kw.get("f2", 2e12),
+                            kw.get("D", 4), kw.get("fs_hz", 20 * 10**12), kw.get("f1_hz", 10**12),
+                            kw.get("f2_hz", 2 * 10**12))
+        return _raw(tz, L.tz_plan_create, ctypes.byref(p), None, ctypes.byref(h))
+
+    for (kind, kw, msg) in [("fft_zeropad", dict(N=0), "N must be"), ("fft_zeropad", dict(n_zeros=-1), "n_zeros"),
+                            ("czt", dict(M=0), "M must be"), ("czt", dict(W=0.0), "non-zero"),
+                            ("czt_band_exact", dict(f2_hz=10**12), "f2 > f1"),
+                            ("zoom", dict(f2=0.5e12), "f2 > f1"), ("zoom", dict(D=0), "D must be")]:
+        st, err = create(kind, **kw)
+        assert st == tz.TZ_EINVAL and msg in err, (kind, kw, err)
+        assert not h.value
+    p = tz._plan_params("czt", 100, 50, 0, 1.0, 1.0, 0, 0, 0, 1, 0, 0, 0)
+    p.kind = 9
+    st, err = _raw(tz, L.tz_plan_create, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == tz.TZ_EINVAL and "unknown plan kind" in err
+    n = ctypes.c_size_t()
+    assert L.tz_plan_workspace(None, ctypes.byref(n)) == tz.TZ_EINVAL
+    assert L.tz_plan_execute(None, 1, 1, None, None) == tz.TZ_EINVAL
+    st, err = _raw(tz, L.tz_bin_freqs, None, None, None)
+    assert st == tz.TZ_EINVAL
