@@ -268,9 +268,25 @@ __global__ void __launch_bounds__(Fft<FL>::NT)
 // Persistent: each workgroup fills its twiddle tables once and then takes
 // traces b = blockIdx.x, + gridDim.x, ...; stores are never waited for at
 // barriers, so the writes of one trace drain while the next is loaded and
-// transformed.  (Fetching the next trace during the last half of the writes
-// was measured slower: holding its samples forces register spills.)
+// transformed.  (Fetching the next trace during the writes was measured
+// slower: its samples push FFT outputs into scratch, and loads and stores
+// share one in-order counter, so each reload waits for every store issued
+// before it.)
 // ---------------------------------------------------------------------------
+// Lane l receives v from lane l - 1 and lane 0 receives `first`: one DPP
+// whole-wave shift per component (no LDS round trip).
+__device__ __forceinline__ float2 lane_up1(float2 v, float2 first) {
+  constexpr int kWaveShr1 = 0x138;  // DPP control: wave_shr:1
+  return make_float2(
+      __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first.x), __float_as_int(v.x), kWaveShr1, 0xf, 0xf, false)),
+      __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first.y), __float_as_int(v.y), kWaveShr1, 0xf, 0xf, false)));
+}
+// v of lane 63, uniform over the wave
+__device__ __forceinline__ float2 lane63(float2 v) {
+  return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), 63)),
+                     __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), 63)));
+}
+
 template <int F, int P>
 struct PadWaveShape {
   using FF = WaveFft<F>;
@@ -405,14 +421,10 @@ __global__ void __launch_bounds__(64 * P)
         const float2 hi = ph_[it];
         const float2 x0 = comb(pa[136 * it], pm0[136 * (IT - 1 - it)], cmul(lo0, hi));
         const float2 x1 = comb(pa[136 * it + 1], pm1[136 * (IT - 1 - it)], cmul(lo1, hi));
-        float2 xm = make_float2(__shfl_up(x1.x, 1), __shfl_up(x1.y, 1));  // X[k-1] from lane - 1
-        if (it == 0) {
-          const float2 first = bin((k0 + NF - 1) & (NF - 1));
-          if (lane == 0) xm = first;
-        } else if (lane == 0) {
-          xm = carry;
-        }
-        carry = make_float2(__shfl(x1.x, 63), __shfl(x1.y, 63));
+        // X[k-1] from lane - 1; lane 0 takes the bin before the run (first
+        // step) or lane 63 of the previous step
+        const float2 xm = lane_up1(x1, it == 0 ? bin((k0 + NF - 1) & (NF - 1)) : carry);
+        carry = lane63(x1);
         // the pair (Nh, Nh+1) is the last of phase 0; in the half spectrum
         // only X[Nh] is written, and its mirror would repeat the direct store;
         // the pair (0, 1) (first of phase 0) has no mirror
