@@ -9,6 +9,8 @@ Section 3.2; a synthetic pulse here) the plotting resolution df runs from
   czt          band 0 - 2.5 THz, M = round((f2 - f1) N_fft / f_s) bins (eq. (25))
   zoom_fft     same band and M, f_N = 1.25 THz, D = floor(f_s / (1.25 (f2 - f1))),
                63-tap low-pass; short DFT length K = round(M f_s / (D (f2 - f1)))
+  ifft         the N_fft-point inverse DFT of the fft_zeropad spectrum back to
+               N_fft time samples (the FFT/IFFT comparison of Section 4, Fig. 12)
 
 Each method is timed (HIP events on the launch stream, plans built before the
 timed region) for one trace, as the paper does, and for a batch of 8192
@@ -58,7 +60,8 @@ def theory(tz, s):
     L_czt, _ = tz.czt_plan_shape(N, s["M"])
     LD = -(-N // s["D"])
     L_zoom, _ = tz.czt_plan_shape(LD, s["M"])
-    return {"fft": c(s["n_fft"]), "czt": 2 * c(L_czt), "zoom": 2 * c(L_zoom)}
+    L_ifft, _ = tz.czt_plan_shape(s["n_fft"], s["n_fft"])
+    return {"fft": c(s["n_fft"]), "czt": 2 * c(L_czt), "zoom": 2 * c(L_zoom), "ifft": 2 * c(L_ifft)}
 
 
 def main():
@@ -100,22 +103,26 @@ def main():
             Xf = torch.empty((x.shape[0], s["n_fft"]), dtype=torch.complex64, device=dev)
             Xc = torch.empty((x.shape[0], s["M"]), dtype=torch.complex64, device=dev)
             Xz = torch.empty_like(Xc)
+            Xi = torch.empty_like(Xf)
+            tz.fft_zeropad(x, s["n_zeros"], out=Xf, stream=stream)
             out[tag] = {
                 "fft": timed(lambda: tz.fft_zeropad(x, s["n_zeros"], out=Xf, stream=stream), reps),
                 "czt": timed(lambda: tz.czt(x, s["M"], W, A, out=Xc, stream=stream), reps),
                 "zoom": timed(lambda: tz.zoom_fft(x, FS, F1, F2, s["M"], s["D"], taps=TAPS, out=Xz,
                                                   stream=stream), reps),
+                "ifft": timed(lambda: tz.ifft(Xf, out=Xi, stream=stream), reps),
             }
-            del Xf, Xc, Xz
+            del Xf, Xc, Xz, Xi
         row = dict(s, us=out, theory=theory(tz, s))
         rows.append(row)
         print(json.dumps(row), flush=True)
 
     base = rows[0]
+    methods = ("fft", "czt", "zoom", "ifft")
     for r in rows:
-        r["rel"] = {tag: {m: r["us"][tag][m] / base["us"][tag][m] for m in ("fft", "czt", "zoom")}
+        r["rel"] = {tag: {m: r["us"][tag][m] / base["us"][tag][m] for m in methods}
                     for tag in ("single", "batch")}
-        r["rel_theory"] = {m: r["theory"][m] / base["theory"][m] for m in ("fft", "czt", "zoom")}
+        r["rel_theory"] = {m: r["theory"][m] / base["theory"][m] for m in methods}
     if args.out:
         cmd = "python bench_sweep.py " + " ".join(sys.argv[1:])
         lines = ["# Resolution sweep: time per call vs plotting resolution", "",
@@ -123,16 +130,17 @@ def main():
                  f"N = {N} samples at f_s = {FS / 1e12:g} THz, band {F1 / 1e12:g}-{F2 / 1e12:g} THz, "
                  f"zoom {TAPS} taps; single trace ({args.reps} calls per point) and "
                  f"{args.batch} traces; times in microseconds, rel = time / time at 20 GHz.", "",
-                 "| df (GHz) | N_fft | M | D | K | fft 1 | czt 1 | zoom 1 | fft B | czt B | zoom B | "
-                 "rel fft B | rel czt B | rel zoom B | theory fft | theory czt | theory zoom |",
-                 "|" + "---|" * 17]
+                 "| df (GHz) | N_fft | M | D | K | fft 1 | czt 1 | zoom 1 | ifft 1 | fft B | czt B | zoom B | "
+                 "ifft B | rel fft B | rel czt B | rel zoom B | rel ifft B | theory fft | theory czt | "
+                 "theory zoom | theory ifft |",
+                 "|" + "---|" * 21]
         for r in rows:
             u1, ub, rb, th = r["us"]["single"], r["us"]["batch"], r["rel"]["batch"], r["rel_theory"]
             lines.append(f"| {r['df_hz'] / 1e9:.1f} | {r['n_fft']} | {r['M']} | {r['D']} | {r['K']} | "
-                         f"{u1['fft']:.1f} | {u1['czt']:.1f} | {u1['zoom']:.1f} | "
-                         f"{ub['fft']:.1f} | {ub['czt']:.1f} | {ub['zoom']:.1f} | "
-                         f"{rb['fft']:.2f} | {rb['czt']:.2f} | {rb['zoom']:.2f} | "
-                         f"{th['fft']:.2f} | {th['czt']:.2f} | {th['zoom']:.2f} |")
+                         f"{u1['fft']:.1f} | {u1['czt']:.1f} | {u1['zoom']:.1f} | {u1['ifft']:.1f} | "
+                         f"{ub['fft']:.1f} | {ub['czt']:.1f} | {ub['zoom']:.1f} | {ub['ifft']:.1f} | "
+                         f"{rb['fft']:.2f} | {rb['czt']:.2f} | {rb['zoom']:.2f} | {rb['ifft']:.2f} | "
+                         f"{th['fft']:.2f} | {th['czt']:.2f} | {th['zoom']:.2f} | {th['ifft']:.2f} |")
         with open(args.out, "w") as f:
             f.write("\n".join(lines) + "\n")
 

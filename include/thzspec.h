@@ -160,6 +160,23 @@ tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2,
 tz_status czt_transfer(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *H,
                        const tz_opts *opts);
 
+/*
+ * Inverse DFT of complex spectra: the IFFT of the Bluestein convolution
+ * (eq. (12)) as a transform of its own, which Section 4 times against the
+ * FFT over the same resolutions:
+ *   x[n] = (1/N) sum_{k<N} X[k] exp(+j 2 pi k n / N),  n = 0 .. N-1.
+ * X: B = opts->batch rows of N complex64 (interleaved float re, im), row b
+ * at complex element b * in_stride (0 means N); x: B rows of N complex64,
+ * out_stride complex elements apart (0 means N).  Both are device memory
+ * owned by the caller; X is only read.  Computed as the CZT of eq. (11)
+ * with A = 1, W = e^{+j 2 pi / N} and exact integer chirp phases, the 1/N
+ * folded into the plan's chirp spectrum; any N with 2N - 1 <= 2^24.
+ * in_dtype must be TZ_F32 (the components of complex64).
+ * Errors: TZ_EINVAL for NULL pointers, N < 1, strides below N, in_dtype
+ * TZ_F64; TZ_EUNSUPPORTED for split precision or 2N - 1 > 2^24.
+ */
+tz_status ifft(const void *X, int64_t N, void *x, const tz_opts *opts);
+
 /* ---------------------------------------------------------------------- */
 /* Multi-dimensional transforms (the 2-D and 3-D case Section 5 names as
  * the setting where CZT and Zoom FFT pay off).  x holds B = opts->batch

@@ -55,9 +55,10 @@ def _load():
             lib.orc_zoom_taps.argtypes = [_i64, _dbl, _pd]
             lib.orc_zoom_frontend.argtypes = [_pd, ctypes.c_int, _i64, _i64, _i64, _dbl, _dbl, _dbl, _i64, _pd, _i64, _pd]
             lib.orc_zoom_short_dft.argtypes = [_pd, _i64, _i64, _i64, _i64, _pi, _i64, _pd]
+            lib.orc_ifft.argtypes = [_pd, _i64, _i64, _i64, _pi, _i64, _pd]
             lib.orc_zoom_K.argtypes = [_dbl, _dbl, _dbl, _i64, _i64]
             lib.orc_zoom_K.restype = _i64
-            for f in ("orc_fft_zeropad", "orc_czt", "orc_czt_band_exact", "orc_zoom_taps",
+            for f in ("orc_fft_zeropad", "orc_czt", "orc_czt_band_exact", "orc_ifft", "orc_zoom_taps",
                       "orc_zoom_frontend", "orc_zoom_short_dft"):
                 getattr(lib, f).restype = None
             _lib = lib
@@ -118,6 +119,20 @@ def czt(x, M: int, W: complex, A: complex, bins=None) -> np.ndarray:
     lib.orc_czt(xa.view(np.float64).ctypes.data_as(_pd) if is_c else _p(xa), int(is_c), N, B, N,
                 W.real, W.imag, A.real, A.imag, b.ctypes.data_as(_pi), b.size,
                 out.view(np.float64).ctypes.data_as(_pd))
+    return out
+
+
+def ifft(X, samples=None) -> np.ndarray:
+    """Inverse DFT closing the convolution of eq. (12) (and timed on its own
+    in Section 4): x[n] = (1/N) sum_{k<N} X[k] exp(+j 2 pi k n / N).
+    X complex [B, N]; only the listed samples n are formed."""
+    lib = _load()
+    Xa = np.ascontiguousarray(_traces(X), dtype=np.complex128)
+    B, N = Xa.shape
+    s = _bins(samples, N)
+    out = _out(B, s.size)
+    lib.orc_ifft(Xa.view(np.float64).ctypes.data_as(_pd), N, B, N, s.ctypes.data_as(_pi), s.size,
+                 out.view(np.float64).ctypes.data_as(_pd))
     return out
 
 

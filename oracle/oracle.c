@@ -96,6 +96,32 @@ void orc_czt(const double *x, int x_complex, int64_t xs, int64_t B, int64_t N,
         }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Inverse DFT: the IFFT that closes the FFT convolution of eq. (12), which
+ * Section 4 also times on its own against the FFT:
+ *   x[n] = (1/N) sum_{k<N} X[k] e^{+j 2 pi k n / N},   n = 0 .. N-1.
+ * X is complex interleaved, B rows of N (row b at complex element b*xs);
+ * only the samples listed in `samples` are formed.  e^{+j 2 pi r/N} is
+ * e^{-j 2 pi (N - r)/N}: the residue of -(k n) mod N is exact in int64.     */
+void orc_ifft(const double *X, int64_t xs, int64_t B, int64_t N,
+              const int64_t *samples, int64_t ns, double *out)
+{
+#pragma omp parallel for collapse(2) schedule(dynamic, 16)
+    for (int64_t b = 0; b < B; ++b)
+        for (int64_t i = 0; i < ns; ++i) {
+            const int64_t n = samples[i];
+            double complex acc = 0.0;
+            for (int64_t k = 0; k < N; ++k) {
+                const int64_t r = (int64_t)(((__int128)k * n) % N);
+                const double complex Xk = X[2 * (b * xs + k)] + I * X[2 * (b * xs + k) + 1];
+                acc += Xk * unit_phase((N - r) % N, N);
+            }
+            acc /= (double)N;
+            out[2 * (b * ns + i)] = creal(acc);
+            out[2 * (b * ns + i) + 1] = cimag(acc);
+        }
+}
+
 /* CZT over a band given in integer hertz (eqs. (22)-(24)):
  * A = e^{j 2 pi f1/fs}, W = e^{-j 2 pi (f2-f1)/(M fs)}, so bin k sits at
  * f1 + k (f2 - f1)/M and   X[k] = sum_n x[n] e^{-j 2 pi (f1 + k(f2-f1)/M) n / fs}.

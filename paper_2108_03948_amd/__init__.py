@@ -15,8 +15,8 @@ import os
 import threading
 
 __all__ = [
-    "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_transfer", "czt_nd", "zoom_fft_nd", "czt_band",
-    "fft_zero_count",
+    "fft_zeropad", "czt", "czt_band_exact", "zoom_fft", "czt_transfer", "ifft", "czt_nd", "zoom_fft_nd",
+    "czt_band", "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "lib", "ThzError",
     "Batch", "Plan", "bin_freqs", "release_plans", "version",
 ]
@@ -85,7 +85,7 @@ TZ_MAX_DIMS = 3
 
 # every symbol declared in include/thzspec.h
 EXPORTS = (
-    "tz_opts_init", "fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "zoom_fft", "czt_nd",
+    "tz_opts_init", "fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "ifft", "zoom_fft", "czt_nd",
     "zoom_fft_nd", "czt_band",
     "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "tz_batch_create",
@@ -114,6 +114,7 @@ def lib() -> ctypes.CDLL:
         L.fft_zeropad.argtypes = [vp, i64, i64, vp, po]
         L.czt.argtypes = [vp, i64, i64, tz_c64, tz_c64, vp, po]
         L.czt_transfer.argtypes = [vp, i64, i64, tz_c64, tz_c64, vp, po]
+        L.ifft.argtypes = [vp, i64, vp, po]
         L.czt_band_exact.argtypes = [vp, i64, i64, i64, i64, i64, vp, po]
         L.zoom_fft.argtypes = [vp, i64, dbl, dbl, dbl, i64, i64, vp, po]
         L.czt_nd.argtypes = [vp, ctypes.c_int, ctypes.POINTER(tz_czt_axis), vp, po]
@@ -142,7 +143,8 @@ def lib() -> ctypes.CDLL:
         L.tz_plan_destroy.argtypes = [vp]
         L.tz_plan_destroy.restype = None
         L.tz_bin_freqs.argtypes = [pp, po, ctypes.POINTER(ctypes.c_double)]
-        for f in ("fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "zoom_fft", "czt_band", "czt_plan_shape",
+        for f in ("fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "ifft", "zoom_fft", "czt_band",
+                  "czt_plan_shape",
                   "tz_batch_create", "tz_batch_launch", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute",
                   "tz_bin_freqs"):
             getattr(L, f).restype = ctypes.c_int
@@ -237,6 +239,33 @@ def czt(x, M: int, W: complex, A: complex, *, out=None, precision="fp32", stream
     with _torch().cuda.device(x.device):
         _check(lib().czt(x.data_ptr(), x.shape[1], int(M), tz_c64(W.real, W.imag), tz_c64(A.real, A.imag),
                          out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def ifft(X, *, out=None, stream=None):
+    """x[n] = (1/N) sum_k X[k] exp(+j 2 pi k n / N) for each row of the
+    complex64 spectra X ([N] or [B, N]); returns [B, N] complex64."""
+    torch = _torch()
+    if not isinstance(X, torch.Tensor) or not X.is_cuda:
+        raise TypeError("X must be a torch tensor on the GPU")
+    if X.dim() == 1:
+        X = X.unsqueeze(0)
+    if X.dim() != 2 or X.dtype != torch.complex64:
+        raise TypeError("X must be a complex64 tensor [N] or [B, N]")
+    if X.stride(1) != 1:
+        X = X.contiguous()
+    B, N = X.shape
+    out = _out(X, N, out)
+    o = tz_opts()
+    lib().tz_opts_init(ctypes.byref(o))
+    o.batch = B
+    o.in_stride = X.stride(0) if B > 1 else N
+    o.out_stride = out.stride(0)
+    if stream is None:
+        stream = torch.cuda.current_stream(X.device)
+    o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    with torch.cuda.device(X.device):
+        _check(lib().ifft(X.data_ptr(), N, out.data_ptr(), ctypes.byref(o)))
     return out
 
 

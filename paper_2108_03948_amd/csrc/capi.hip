@@ -137,7 +137,12 @@ std::string phase_key(const PhaseParams &p) {
     snprintf(buf, sizeof buf, "s%a/%a/%a/%a", p.a, p.w, p.ma, p.mw);
   else
     snprintf(buf, sizeof buf, "f%a/%a", p.a, p.w);
-  return buf;
+  std::string key = buf;
+  if (p.out_scale != 1.0) {
+    snprintf(buf, sizeof buf, "x%a", p.out_scale);
+    key += buf;
+  }
+  return key;
 }
 
 // tables held by an explicit plan beside its Bluestein / zoom / pad plans
@@ -651,6 +656,20 @@ PhaseParams band_phase(int64_t fs_hz, int64_t f1_hz, int64_t f2_hz, int64_t M) {
   return p;
 }
 
+// inverse DFT of N points: W = e^{+j 2 pi / N} = e^{-j 2 pi (N-1)/N}, A = 1,
+// outputs scaled by 1/N
+PhaseParams idft_phase(int64_t N) {
+  PhaseParams p{};
+  p.rational = 1;
+  p.q = N;
+  p.pw = (N - 1) % N;
+  p.pa = 0;
+  p.w = (double)p.pw / (double)N;
+  p.a = 0.0;
+  p.out_scale = 1.0 / (double)N;
+  return p;
+}
+
 PhaseParams zoom_phase(int64_t K, int64_t M) {
   PhaseParams p{};
   p.rational = 1;
@@ -884,6 +903,19 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
   void *ws = nullptr;
   if (e.b.ws && (st = pp->blue->work.get(c.stream, e.b.ws, &ws))) return st;
   return exec_pad(e, x, c.in_kind, X, c, ws, c.stream);
+}
+
+tz_status ifft(const void *X, int64_t N, void *x, const tz_opts *o) {
+  Common c;
+  tz_status st = check_common(X, N, x, o, N, &c);
+  if (st) return st;
+  if (c.in_kind != 0) return fail(TZ_EINVAL, "ifft takes complex64 spectra (in_dtype TZ_F32)");
+  if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "ifft runs in FP32 only");
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  std::shared_ptr<BluePlan> pl;
+  if ((st = get_blue(d, N, N, idft_phase(N), c.stream, &pl, true))) return st;
+  return run_blue(d, pl, X, 2, x, c, c.stream);
 }
 
 tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, int64_t M, int64_t D, void *X,

@@ -14,6 +14,9 @@ struct PhaseParams {
   // off the unit circle (|A| = e^ma, |W| = e^mw): tables carry magnitudes,
   // pre scaled by e^-alpha, conjugate chirp by e^-beta, post by e^(alpha+beta)
   double ma, mw, alpha, beta;
+  // outputs scaled by this factor, folded into the conjugate-chirp spectrum
+  // (the inverse DFT's 1/N)
+  double out_scale = 1.0;
 };
 
 // largest single-workgroup FFT length

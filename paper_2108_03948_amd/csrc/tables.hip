@@ -221,8 +221,8 @@ hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, in
     ns *= rs[i];
     double2 *t = a; a = b; b = t;
   }
-  // V = FFT(v) / L (the 1/L of the inverse FFT folded in)
-  hipLaunchKernelGGL(k_to_float_scaled, dim3(nblocks(L, 256)), dim3(256), 0, s, a, V, L, 1.0 / (double)L,
+  // V = FFT(v) / L (the 1/L of the inverse FFT folded in), times the output scale
+  hipLaunchKernelGGL(k_to_float_scaled, dim3(nblocks(L, 256)), dim3(256), 0, s, a, V, L, p.out_scale / (double)L,
                      (int64_t)L1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipFreeAsync(a, s);

@@ -136,6 +136,8 @@ def test_invalid_arguments_rejected_before_device_work(tz):
         (L.zoom_fft, (fake, 100, 20e12, 1e12, 2e12, 64, 0, fake, ctypes.byref(o)), "D must be"),
         (L.czt_band_exact, (fake, 10, 10, 0, 1, 2, fake, ctypes.byref(o)), "fs >= 1"),
         (L.czt_transfer, (fake, 10, 0, w, one, fake, ctypes.byref(o)), "M must be"),
+        (L.ifft, (None, 10, fake, ctypes.byref(o)), "NULL"),
+        (L.ifft, (fake, 0, fake, ctypes.byref(o)), "N must be"),
     ]
     for fn, args, msg in cases:
         st, err = _raw(tz, fn, *args)
@@ -161,6 +163,15 @@ def test_invalid_arguments_rejected_before_device_work(tz):
     o3.batch, o3.in_stride = 4, 5
     st, err = _raw(tz, L.czt, fake, 10, 10, w, one, fake, ctypes.byref(o3))
     assert st == tz.TZ_EINVAL and "in_stride" in err
+    # the inverse DFT takes complex64 spectra and runs in FP32
+    o4 = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(o4))
+    o4.in_dtype = tz.TZ_F64
+    st, err = _raw(tz, L.ifft, fake, 10, fake, ctypes.byref(o4))
+    assert st == tz.TZ_EINVAL and "complex64" in err
+    o4.in_dtype, o4.precision = tz.TZ_F32, tz.TZ_SPLIT_FP16
+    st, err = _raw(tz, L.ifft, fake, 10, fake, ctypes.byref(o4))
+    assert st == tz.TZ_EUNSUPPORTED and "FP32" in err
 
 
 def test_nd_invalid_arguments_rejected_before_device_work(tz):

@@ -1,0 +1,74 @@
+"""GPU parity of the inverse DFT (ifft) against the FP64 oracle.
+
+The inverse transform closes the FFT convolution of eq. (12) and is timed on
+its own against the FFT in Section 4.  It runs as a CZT with A = 1,
+W = e^{+j 2 pi / N} and the 1/N folded into the chirp spectrum, so the cases
+cover every Bluestein shape it can take: single pass (2N - 1 <= 16384), bin
+blocks / input segments just past it, and the four-step path (2N - 1 up to a
+few times 2^17).  Rows are strided on both sides; large N are checked on
+sampled outputs.  A round trip through the zero-padded FFT must return the
+trace.  Tolerance: relative L2 1e-6 per row (FP32 path).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tz():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_03948_amd as tz
+    tz.lib()
+    return tz
+
+
+def spectra(B, N, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((B, N)) + 1j * rng.standard_normal((B, N))).astype(np.complex64)
+
+
+@pytest.mark.parametrize("N", [1, 2, 7, 500, 1024, 4096, 8192, 8193, 12345, 65536, 100003])
+def test_ifft_matches_oracle(tz, orc, N):
+    import torch
+    B = 3
+    X = spectra(B, N, 500 + N % 1000)
+    dev = torch.device("cuda:0")
+    # strided rows on both sides: input rows N + 3 apart, output rows N + 5 apart
+    Xbig = torch.zeros((B, N + 3), dtype=torch.complex64, device=dev)
+    Xbig[:, :N] = torch.from_numpy(X).to(dev)
+    obig = torch.full((B, N + 5), complex(9.0, 9.0), dtype=torch.complex64, device=dev)
+    say(f"case: ifft N={N} B={B} (L, blocks) = {tz.czt_plan_shape(N, N)}")
+    tz.ifft(Xbig[:, :N], out=obig[:, :N])
+    torch.cuda.synchronize()
+    got = obig.cpu().numpy()
+    assert np.all(got[:, N:] == np.complex64(complex(9.0, 9.0))), "wrote past the row"
+    samples = np.arange(N) if N <= 4096 else np.unique(np.r_[0, 1, N - 1, np.random.default_rng(N).integers(0, N, 61)])
+    ref = orc.ifft(X.astype(np.complex128), samples=samples)
+    g = got[:, samples]
+    r = np.linalg.norm(g - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+    say(f"  max rel L2 {r.max():.3e} over {samples.size} samples per row")
+    assert np.isfinite(g).all() and r.max() <= TOL
+
+
+@pytest.mark.parametrize("N", [1000, 4096, 30000])
+def test_ifft_inverts_fft_zeropad(tz, N):
+    """ifft(fft_zeropad(x, 0)) returns the real traces (imaginary part ~ 0)."""
+    import torch
+    x = np.random.default_rng(N).standard_normal((4, N)).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    back = tz.ifft(tz.fft_zeropad(xd, 0)).cpu().numpy()
+    r = np.linalg.norm(back - x, axis=1) / np.linalg.norm(x, axis=1)
+    say(f"case: ifft(fft_zeropad(x)) N={N}: max rel L2 {r.max():.3e}")
+    assert r.max() <= TOL

@@ -84,6 +84,43 @@ def test_fft_zeropad_mpmath(orc):
 
 
 # --------------------------------------------------------------------------
+# inverse DFT (the IFFT of eq. (12), timed against the FFT in Section 4)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [1, 2, 7, 64, 500, 1031])
+def test_ifft_matches_numpy(orc, N):
+    rng = np.random.default_rng(400 + N)
+    X = rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))
+    assert rel(orc.ifft(X), np.fft.ifft(X, axis=1)) < 1e-13
+
+
+def test_ifft_closed_forms(orc):
+    """A single line X[k] = delta[k - k0] gives x[n] = e^{+j 2 pi k0 n / N} / N
+    (sign of the exponent and the 1/N); a flat spectrum gives an impulse at
+    n = 0."""
+    N, k0 = 97, 13
+    X = np.zeros(N, dtype=complex)
+    X[k0] = 1.0
+    n = np.arange(N)
+    assert np.max(np.abs(orc.ifft(X)[0] - np.exp(2j * np.pi * k0 * n / N) / N)) < 1e-15
+    x = orc.ifft(np.ones(N, dtype=complex))[0]
+    assert abs(x[0] - 1.0) < 1e-14 and np.max(np.abs(x[1:])) < 1e-14
+
+
+def test_ifft_inverts_the_zero_padded_fft_and_keeps_energy(orc):
+    """ifft(fft(x)) = x for the zero-padded FFT of eqs. (2)-(5) taken with
+    no padding, and Parseval: sum |x|^2 = (1/N) sum |X|^2."""
+    rng = np.random.default_rng(402)
+    x = rng.standard_normal((2, 300))
+    X = orc.fft_zeropad(x, 0)
+    assert rel(orc.ifft(X), x.astype(complex)) < 1e-13
+    xs = orc.ifft(X, samples=[0, 17, 299])
+    assert rel(xs, x[:, [0, 17, 299]].astype(complex)) < 1e-13
+    Y = rng.standard_normal((2, 211)) + 1j * rng.standard_normal((2, 211))
+    y = orc.ifft(Y)
+    assert abs(np.sum(np.abs(y) ** 2) - np.sum(np.abs(Y) ** 2) / 211) < 1e-12 * np.sum(np.abs(y) ** 2)
+
+
+# --------------------------------------------------------------------------
 # CZT (Section 2.3, eqs. (11)-(25))
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("N", [1, 5, 64, 200])
