@@ -15,7 +15,8 @@
  *   data_ptr()).  The caller owns them; they must not overlap.  The library
  *   never copies traces or spectra to or from the host.
  * - Transforms are forward and unscaled (a plain sum over n, no 1/N), as in
- *   eqs. (2) and (11).
+ *   eqs. (2) and (11); the one exception is ifft(), the inverse DFT of
+ *   complex spectra with its 1/N.
  * - Work is enqueued on opts->stream (a hipStream_t; NULL = the null stream)
  *   and returns before it finishes.  The first call with a new shape builds
  *   a plan (device tables, see below) and may allocate and synchronise that
@@ -300,11 +301,14 @@ int64_t tz_batch_describe(const tz_batch *batch, char *buf, int64_t len);
 /* Zoom FFT's decimated rows) is a caller-owned workspace of at least       */
 /* tz_plan_workspace() bytes.                                               */
 
-enum { TZ_PLAN_FFT_ZEROPAD = 0, TZ_PLAN_CZT = 1, TZ_PLAN_CZT_BAND_EXACT = 2, TZ_PLAN_ZOOM = 3 };
+enum {
+    TZ_PLAN_FFT_ZEROPAD = 0, TZ_PLAN_CZT = 1, TZ_PLAN_CZT_BAND_EXACT = 2, TZ_PLAN_ZOOM = 3,
+    TZ_PLAN_IFFT = 4  /* ifft(): N complex64 in, N complex64 out */
+};
 
 typedef struct {
     int32_t kind;                 /* TZ_PLAN_*                                  */
-    int64_t N;                    /* samples per trace (eq. (1))                */
+    int64_t N;                    /* samples per trace (eq. (1)); ifft: points  */
     int64_t M;                    /* bins: czt, czt_band_exact, zoom            */
     int64_t n_zeros;              /* fft_zeropad: zeros appended (eq. (5))      */
     tz_c64 W, A;                  /* czt: contour A W^-k (eqs. (16)-(17))       */
@@ -319,7 +323,7 @@ typedef struct tz_plan tz_plan;
 /* Build a plan for params with opts (batch, strides, in_dtype, precision,
  * flags, fir_taps, fir_cutoff_hz as in the one-shot calls; NULL = defaults).
  * The same argument checks and errors as fft_zeropad / czt /
- * czt_band_exact / zoom_fft; TZ_EINVAL for an unknown kind.  The plan owns
+ * czt_band_exact / zoom_fft / ifft; TZ_EINVAL for an unknown kind.  The plan owns
  * its tables (tz_release_plans() does not free them). */
 tz_status tz_plan_create(const tz_plan_params *params, const tz_opts *opts, tz_plan **plan);
 /* Bytes of workspace tz_plan_execute() needs (0 for most shapes). */
@@ -340,7 +344,8 @@ void tz_plan_destroy(tz_plan *plan);
  * TZ_HALF in opts->flags; czt fs (nu_A + k nu_W) for A = e^{j 2 pi nu_A},
  * W = e^{-j 2 pi nu_W} (eqs. (16)-(17)); czt_band_exact f1 + k (f2 - f1)/M
  * (eq. (24)); zoom f_N + (k - floor(M/2)) fs / (D K) with f_N = (f1 + f2)/2
- * and K = zoom_short_length().  f_out holds one double per bin. */
+ * and K = zoom_short_length().  f_out holds one double per bin.  TZ_EINVAL
+ * for TZ_PLAN_IFFT, whose outputs are time samples. */
 tz_status tz_bin_freqs(const tz_plan_params *params, const tz_opts *opts, double *f_out);
 
 /* ---------------------------------------------------------------------- */

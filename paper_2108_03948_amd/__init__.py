@@ -80,7 +80,7 @@ class tz_plan_params(ctypes.Structure):
     ]
 
 
-TZ_PLAN_KINDS = {"fft_zeropad": 0, "czt": 1, "czt_band_exact": 2, "zoom": 3}
+TZ_PLAN_KINDS = {"fft_zeropad": 0, "czt": 1, "czt_band_exact": 2, "zoom": 3, "ifft": 4}
 TZ_MAX_DIMS = 3
 
 # every symbol declared in include/thzspec.h
@@ -510,8 +510,9 @@ class Plan:
 
     kind: "fft_zeropad" (N, n_zeros, half), "czt" (N, M, W, A),
     "czt_band_exact" (N, M, fs_hz, f1_hz, f2_hz) or "zoom" (N, M, fs, f1, f2,
-    D, taps, cutoff_hz); batch traces of dtype, rows in_stride / out_stride
-    elements apart (0 = packed)."""
+    D, taps, cutoff_hz) or "ifft" (N: complex64 spectra in, N samples out);
+    batch traces of dtype, rows in_stride / out_stride elements apart
+    (0 = packed)."""
 
     def __init__(self, kind: str, *, N: int, batch: int = 1, M: int = 0, n_zeros: int = 0, W: complex = 1.0,
                  A: complex = 1.0, fs: float = 0.0, f1: float = 0.0, f2: float = 0.0, D: int = 1, fs_hz: int = 0,
@@ -522,11 +523,18 @@ class Plan:
             stream = torch.cuda.current_stream()
         self.kind, self.N, self.batch = kind, int(N), int(batch)
         self.dtype = torch.float64 if str(dtype).endswith("float64") else torch.float32
-        self.bins = (N + n_zeros if not half else (N + n_zeros) // 2 + 1) if kind == "fft_zeropad" else int(M)
+        if kind == "ifft":
+            self.dtype = torch.complex64
+            self.bins = int(N)
+        elif kind == "fft_zeropad":
+            self.bins = N + n_zeros if not half else (N + n_zeros) // 2 + 1
+        else:
+            self.bins = int(M)
         self.in_stride = int(in_stride) or self.N
         self.out_stride = int(out_stride) or self.bins
         p = _plan_params(kind, N, M, n_zeros, W, A, fs, f1, f2, D, fs_hz, f1_hz, f2_hz)
-        o = _plan_opts(batch, in_stride, out_stride, dtype, precision, half, taps, cutoff_hz, stream)
+        o = _plan_opts(batch, in_stride, out_stride, "float32" if kind == "ifft" else dtype, precision, half, taps,
+                       cutoff_hz, stream)
         h = ctypes.c_void_p()
         _check(lib().tz_plan_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)))
         self._h = h

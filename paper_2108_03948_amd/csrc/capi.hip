@@ -905,17 +905,30 @@ tz_status fft_zeropad(const void *x, int64_t N, int64_t n_zeros, void *X, const 
   return exec_pad(e, x, c.in_kind, X, c, ws, c.stream);
 }
 
+}  // extern "C"
+
+namespace {
+// the inverse DFT reads complex64 rows and runs in FP32
+tz_status check_ifft(Common *c) {
+  if (c->in_kind != 0) return fail(TZ_EINVAL, "ifft takes complex64 spectra (in_dtype TZ_F32)");
+  if (c->precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "ifft runs in FP32 only");
+  c->in_kind = 2;
+  return TZ_OK;
+}
+}  // namespace
+
+extern "C" {
+
 tz_status ifft(const void *X, int64_t N, void *x, const tz_opts *o) {
   Common c;
   tz_status st = check_common(X, N, x, o, N, &c);
   if (st) return st;
-  if (c.in_kind != 0) return fail(TZ_EINVAL, "ifft takes complex64 spectra (in_dtype TZ_F32)");
-  if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "ifft runs in FP32 only");
+  if ((st = check_ifft(&c))) return st;
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
   std::shared_ptr<BluePlan> pl;
   if ((st = get_blue(d, N, N, idft_phase(N), c.stream, &pl, true))) return st;
-  return run_blue(d, pl, X, 2, x, c, c.stream);
+  return run_blue(d, pl, X, c.in_kind, x, c, c.stream);
 }
 
 tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, int64_t M, int64_t D, void *X,
@@ -1186,6 +1199,18 @@ tz_status tz_plan_create(const tz_plan_params *pp, const tz_opts *o, tz_plan **o
       P->ws = P->z.u_bytes + P->z.b.ws;
       break;
     }
+    case TZ_PLAN_IFFT: {
+      P->bins = pp->N;
+      if ((st = check_common(nb, pp->N, (void *)nb, o, pp->N, &c))) return st;
+      if ((st = check_ifft(&c))) return st;
+      std::lock_guard<std::mutex> lk(g_mu);
+      Device &d = device_state(current_device());
+      std::shared_ptr<BluePlan> pl;
+      if ((st = get_blue(d, pp->N, pp->N, idft_phase(pp->N), c.stream, &pl, true))) return st;
+      if ((st = prepare_blue(d, pl, c.in_kind, c, c.stream, &P->b, &P->keep))) return st;
+      P->ws = P->b.ws;
+      break;
+    }
     default:
       return fail(TZ_EINVAL, "unknown plan kind %d", pp->kind);
   }
@@ -1258,6 +1283,8 @@ tz_status tz_bin_freqs(const tz_plan_params *pp, const tz_opts *o, double *f) {
       for (int64_t k = 0; k < pp->M; ++k) f[k] = fN + (double)(k - pp->M / 2) * step;
       return TZ_OK;
     }
+    case TZ_PLAN_IFFT:
+      return fail(TZ_EINVAL, "ifft writes time samples (t = n / fs), not frequency bins");
     default:
       return fail(TZ_EINVAL, "unknown plan kind %d", pp->kind);
   }

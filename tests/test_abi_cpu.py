@@ -315,3 +315,11 @@ def test_plan_invalid_arguments_rejected_before_device_work(tz):
     assert L.tz_plan_execute(None, 1, 1, None, None) == tz.TZ_EINVAL
     st, err = _raw(tz, L.tz_bin_freqs, None, None, None)
     assert st == tz.TZ_EINVAL
+    # the inverse-DFT plan takes complex64 spectra; its outputs are time samples
+    p = tz._plan_params("ifft", 100, 0, 0, 1.0, 1.0, 20e12, 0, 0, 1, 0, 0, 0)
+    o = tz._plan_opts(1, 0, 0, "float64", "fp32", False, 0, 0.0, None)
+    st, err = _raw(tz, L.tz_plan_create, ctypes.byref(p), ctypes.byref(o), ctypes.byref(h))
+    assert st == tz.TZ_EINVAL and "complex64" in err and not h.value
+    f = (ctypes.c_double * 100)()
+    st, err = _raw(tz, L.tz_bin_freqs, ctypes.byref(p), None, f)
+    assert st == tz.TZ_EINVAL and "time samples" in err

@@ -107,6 +107,21 @@ def test_plan_equals_one_shot_on_every_path(tz, dev):
         plan.close()
 
 
+@pytest.mark.parametrize("N", [3000, 70000])
+def test_ifft_plan_equals_one_shot(tz, dev, N):
+    """The inverse-DFT plan (single pass with bin blocks, and the four-step
+    path with its workspace) equals the one-shot ifft() bit for bit."""
+    import torch
+    rng = np.random.default_rng(N)
+    X = torch.from_numpy((rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))).astype(np.complex64)).to(dev)
+    plan = tz.Plan("ifft", N=N, batch=3)
+    say(f"case: ifft plan N={N}: workspace {plan.workspace_bytes} B")
+    got = run_plan(plan, X).cpu().numpy()
+    ref = tz.ifft(X).cpu().numpy()
+    assert np.array_equal(got, ref)
+    plan.close()
+
+
 def test_plan_against_oracle(tz, dev, orc):
     W, A = tz.czt_band(20e12, 0.2e12, 2.5e12, 1500)
     x, xd = traces(3, 2000, 7, dev)
