@@ -65,6 +65,27 @@ def test_long_czt_float_phases(tz, orc, N, M, dtype):
         assert e <= TOL
 
 
+def test_long_czt_at_the_longest_fft(tz, orc):
+    """N + M - 1 = 2^24, the longest Bluestein FFT the library runs (four-step
+    rows of 16384 under 1024 columns); one point more is refused on the host
+    (test_czt_plan_shape)."""
+    import torch
+    M = 64
+    N = (1 << 24) - M + 1
+    assert tz.czt_plan_shape(N, M) == (1 << 24, 1)
+    rng = np.random.default_rng(24)
+    x = rng.standard_normal((1, N)).astype(np.float32)
+    W = np.exp(-2j * np.pi * 0.29 / (1 << 24))
+    A = np.exp(2j * np.pi * 0.0417)
+    say(f"case: long czt at the longest FFT: N={N} M={M} L=2^24")
+    X = tz.czt(torch.from_numpy(x).cuda(), M, W, A).cpu().numpy()
+    bins = sample_bins(M, rng, 13)
+    ref = orc.czt(x.astype(np.float64), M, W, A, bins)
+    e = rel(X[0, bins], ref[0])
+    say(f"  rel L2 {e:.3e} over {bins.size} bins")
+    assert np.isfinite(X).all() and e <= TOL
+
+
 def test_long_czt_batch_of_eight_narrow_columns(tz, orc):
     """M below the row length L2 with a grid of whole column groups (8 traces)."""
     import torch
