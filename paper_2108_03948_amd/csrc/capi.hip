@@ -915,6 +915,41 @@ tz_status check_ifft(Common *c) {
   c->in_kind = 2;
   return TZ_OK;
 }
+
+// the inverse DFT: one FFT per row for power-of-two N up to 16384, else the
+// Bluestein form (A = 1, W = e^{+j 2 pi / N}, 1/N in the chirp spectrum)
+struct IfftExec {
+  int64_t N = 0;
+  bool direct = false;
+  const float2 *tw = nullptr;
+  BlueExec b;
+};
+
+tz_status prepare_ifft(Device &d, int64_t N, const Common &c, hipStream_t s, IfftExec *e, Keep *keep = nullptr) {
+  e->N = N;
+  if (ifft_direct_supported(N) && c.B <= INT32_MAX) {
+    e->direct = true;
+    return get_twiddles(d, N, s, &e->tw, keep);
+  }
+  std::shared_ptr<BluePlan> pl;
+  tz_status st = get_blue(d, N, N, idft_phase(N), s, &pl, true);
+  if (st) return st;
+  return prepare_blue(d, pl, c.in_kind, c, s, &e->b, keep);
+}
+
+tz_status exec_ifft(const IfftExec &e, const void *X, void *x, const Common &c, void *ws, hipStream_t s) {
+  if (!e.direct) return exec_blue(e.b, X, c.in_kind, x, c, e.N, ws, s);
+  IfftLaunch a;
+  a.X = (const float2 *)X;
+  a.xs = c.xs;
+  a.tw = e.tw;
+  a.x = (float2 *)x;
+  a.os = c.os;
+  a.B = c.B;
+  a.L = (int)e.N;
+  TZ_HIP(launch_ifft_pow2(a, s), "ifft launch");
+  return TZ_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -926,9 +961,11 @@ tz_status ifft(const void *X, int64_t N, void *x, const tz_opts *o) {
   if ((st = check_ifft(&c))) return st;
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
-  std::shared_ptr<BluePlan> pl;
-  if ((st = get_blue(d, N, N, idft_phase(N), c.stream, &pl, true))) return st;
-  return run_blue(d, pl, X, c.in_kind, x, c, c.stream);
+  IfftExec e;
+  if ((st = prepare_ifft(d, N, c, c.stream, &e))) return st;
+  void *ws = nullptr;
+  if (!e.direct && e.b.ws && (st = e.b.pl->work.get(c.stream, e.b.ws, &ws))) return st;
+  return exec_ifft(e, X, x, c, ws, c.stream);
 }
 
 tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, int64_t M, int64_t D, void *X,
@@ -1104,6 +1141,7 @@ struct tz_plan {
   BlueExec b;
   ZoomExec z;
   PadExec p;
+  IfftExec i;
   Keep keep;            // twiddle / root tables, held past tz_release_plans()
   size_t ws = 0;        // workspace bytes
   size_t u_bytes = 0;   // zoom: the workspace starts with the decimated rows
@@ -1205,10 +1243,8 @@ tz_status tz_plan_create(const tz_plan_params *pp, const tz_opts *o, tz_plan **o
       if ((st = check_ifft(&c))) return st;
       std::lock_guard<std::mutex> lk(g_mu);
       Device &d = device_state(current_device());
-      std::shared_ptr<BluePlan> pl;
-      if ((st = get_blue(d, pp->N, pp->N, idft_phase(pp->N), c.stream, &pl, true))) return st;
-      if ((st = prepare_blue(d, pl, c.in_kind, c, c.stream, &P->b, &P->keep))) return st;
-      P->ws = P->b.ws;
+      if ((st = prepare_ifft(d, pp->N, c, c.stream, &P->i, &P->keep))) return st;
+      P->ws = P->i.direct ? 0 : P->i.b.ws;
       break;
     }
     default:
@@ -1235,6 +1271,7 @@ tz_status tz_plan_execute(const tz_plan *P, const void *x, void *X, void *worksp
   const Common &c = P->c;
   switch (P->kind) {
     case TZ_PLAN_FFT_ZEROPAD: return exec_pad(P->p, x, c.in_kind, X, c, workspace, s);
+    case TZ_PLAN_IFFT: return exec_ifft(P->i, x, X, c, workspace, s);
     case TZ_PLAN_ZOOM:
       return exec_zoom(P->z, x, c.in_kind, X, c, workspace, (char *)workspace + P->u_bytes, s);
     default: return exec_blue(P->b, x, c.in_kind, X, c, P->bins, workspace, s);

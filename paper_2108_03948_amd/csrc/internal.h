@@ -186,6 +186,19 @@ struct LongLaunch {
 // L1 for a four-step length L (a power of two in [2^17, 2^24]); false otherwise
 bool long_shape(int64_t L, int *L1);
 hipError_t launch_czt_long(const LongLaunch &a, hipStream_t s);
+
+// ---- direct inverse DFT of power-of-two length (ifft.hip) ----
+struct IfftLaunch {
+  const float2 *X;   // B rows of L complex, xs apart
+  int64_t xs;
+  const float2 *tw;  // W_L^m, m < L
+  float2 *x;         // B rows of L complex, os apart
+  int64_t os, B;
+  int L;
+};
+// L = 256 .. 16384, a power of two
+bool ifft_direct_supported(int64_t N);
+hipError_t launch_ifft_pow2(const IfftLaunch &a, hipStream_t s);
 // split-precision row kernel of the four-step path (mfma.hip): L2 in
 // {4096, 8192, 16384}, L1 in {320, 512, 1024}
 bool long_rows_mfma_supported(int L1, int L2);

@@ -1,9 +1,11 @@
 """GPU parity of the inverse DFT (ifft) against the FP64 oracle.
 
 The inverse transform closes the FFT convolution of eq. (12) and is timed on
-its own against the FFT in Section 4.  It runs as a CZT with A = 1,
-W = e^{+j 2 pi / N} and the 1/N folded into the chirp spectrum, so the cases
-cover every Bluestein shape it can take: single pass (2N - 1 <= 16384), bin
+its own against the FFT in Section 4.  Power-of-two N from 256 to 16384 run
+as one FFT per row (conjugate, forward FFT, conjugate, scale); every other N
+runs as a CZT with A = 1, W = e^{+j 2 pi / N} and the 1/N folded into the
+chirp spectrum.  The cases cover both ends of the direct range, sizes just
+outside it, and every Bluestein shape: single pass (2N - 1 <= 16384), bin
 blocks / input segments just past it, and the four-step path (2N - 1 up to a
 few times 2^17).  Rows are strided on both sides; large N are checked on
 sampled outputs.  A round trip through the zero-padded FFT must return the
@@ -39,7 +41,7 @@ def spectra(B, N, seed):
     return (rng.standard_normal((B, N)) + 1j * rng.standard_normal((B, N))).astype(np.complex64)
 
 
-@pytest.mark.parametrize("N", [1, 2, 7, 500, 1024, 4096, 8192, 8193, 12345, 65536, 100003])
+@pytest.mark.parametrize("N", [1, 2, 7, 128, 256, 500, 1024, 4096, 8192, 8193, 12345, 16384, 65536, 100003])
 def test_ifft_matches_oracle(tz, orc, N):
     import torch
     B = 3
@@ -49,7 +51,8 @@ def test_ifft_matches_oracle(tz, orc, N):
     Xbig = torch.zeros((B, N + 3), dtype=torch.complex64, device=dev)
     Xbig[:, :N] = torch.from_numpy(X).to(dev)
     obig = torch.full((B, N + 5), complex(9.0, 9.0), dtype=torch.complex64, device=dev)
-    say(f"case: ifft N={N} B={B} (L, blocks) = {tz.czt_plan_shape(N, N)}")
+    direct = 256 <= N <= 16384 and N & (N - 1) == 0
+    say(f"case: ifft N={N} B={B} " + ("direct FFT" if direct else f"Bluestein (L, blocks) = {tz.czt_plan_shape(N, N)}"))
     tz.ifft(Xbig[:, :N], out=obig[:, :N])
     torch.cuda.synchronize()
     got = obig.cpu().numpy()

@@ -107,10 +107,11 @@ def test_plan_equals_one_shot_on_every_path(tz, dev):
         plan.close()
 
 
-@pytest.mark.parametrize("N", [3000, 70000])
+@pytest.mark.parametrize("N", [4096, 3000, 70000])
 def test_ifft_plan_equals_one_shot(tz, dev, N):
-    """The inverse-DFT plan (single pass with bin blocks, and the four-step
-    path with its workspace) equals the one-shot ifft() bit for bit."""
+    """The inverse-DFT plan (direct power-of-two FFT, Bluestein single pass
+    with bin blocks, and the four-step path with its workspace) equals the
+    one-shot ifft() bit for bit."""
     import torch
     rng = np.random.default_rng(N)
     X = torch.from_numpy((rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))).astype(np.complex64)).to(dev)
