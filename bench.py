@@ -333,6 +333,30 @@ def main():
                 "weighted_rel_l2_sampled": werr}
     log(f"bench: czt_transfer {ms_tr:.3f} ms for {B // 2} pairs, weighted rel L2 {werr:.2e}")
 
+    # inverse DFT of the 8192 CZT spectra (4096 complex points each: the
+    # direct one-FFT-per-row form), back to 4096 time samples per row
+    Xi = torch.empty_like(Xc)
+    for _ in range(2):
+        tz.ifft(Xc, out=Xi, stream=stream)
+    reps = max(5, args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        tz.ifft(Xc, out=Xi, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_if = e0.elapsed_time(e1) / reps
+    # every sample of two rows: a pulse concentrates its energy in a few
+    # samples, so a sparse sample of a row would weigh the rounding floor of
+    # the near-zero ones
+    ri = oracle.ifft(Xc[:2].cpu().numpy().astype(np.complex128))
+    ierr = float(np.linalg.norm(Xi[:2].cpu().numpy() - ri) / np.linalg.norm(ri))
+    ifft_b = 2 * B * M * 8
+    inverse = {"ms": ms_if, "rows": B, "points": M, "alg_GBps": ifft_b / (ms_if * 1e-3) / 1e9,
+               "hbm_frac": ifft_b / (ms_if * 1e-3) / 1e9 / HBM_PEAK_GBS, "rel_l2_sampled": ierr}
+    log(f"bench: ifft {ms_if:.3f} ms for {B} x {M}, {inverse['alg_GBps']:.0f} GB/s, rel L2 {ierr:.2e}")
+
     nd = bench_nd(tz, synth, oracle, dev, stream, max(3, args.steps // 4))
 
     out = {
@@ -360,6 +384,7 @@ def main():
         "kernels": kernels,
         "mfma_vs_fp32": mfma,
         "transfer": transfer,
+        "ifft": inverse,
         "nd": nd,
         "czt_rel_l2_sampled": err,
     }
