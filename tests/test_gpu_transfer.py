@@ -8,7 +8,8 @@ weighted error ||X_r (H_gpu - H)|| / ||X_s|| (the error of X_r H, an FP32 CZT
 error of both traces), <= 1e-6 like the CZT itself.  Bins within 20 dB of the
 reference peak (where a bin's own FP32 error is a few times the vector's) are
 also checked one by one (<= 1e-5 relative), and the integer-delay case
-against its closed form g e^{-j 2 pi nu d}.
+against its closed form g e^{-j 2 pi nu d}, also taken back to time with the
+inverse DFT (an impulse at the delay).
 """
 import sys
 
@@ -85,6 +86,30 @@ def test_transfer_integer_delay_closed_form(tz):
     e = np.max(np.abs(Hg - ref)) / g
     say(f"  max |H - g e^(-j 2 pi nu d)| / g = {e:.3e}")
     # white reference: no weak bins, every bin is within reach of FP32
+    assert e <= 1e-4
+
+
+def test_transfer_back_to_time_is_the_delay_impulse(tz):
+    """The response taken back to time: on the full-circle contour W =
+    e^{-j 2 pi / M} (A = e^{j 2 pi a}) a pure delay d with gain g has
+    H[k] = g e^{-j 2 pi (a + k / M) d}, whose inverse DFT over the M bins is
+    the impulse g e^{-j 2 pi a d} delta[n - d].  czt_transfer followed by ifft
+    must put it at sample d and leave the others at the rounding floor."""
+    import torch
+    rng = np.random.default_rng(33)
+    N, d, g, M, a = 900, 37, 0.6, 1024, 0.0123
+    xr = np.zeros(N, np.float32)
+    xr[: N - d] = rng.standard_normal(N - d)
+    xs = np.zeros(N, np.float32)
+    xs[d:] = np.float32(g) * xr[: N - d]
+    A, W = np.exp(2j * np.pi * a), np.exp(-2j * np.pi / M)
+    say("case: czt_transfer then ifft: delay impulse")
+    H = tz.czt_transfer(torch.from_numpy(np.stack([xr, xs])).cuda(), M, W, A)
+    h = tz.ifft(H).cpu().numpy()[0]
+    ref = np.zeros(M, complex)
+    ref[d] = g * np.exp(-2j * np.pi * a * d)
+    e = np.max(np.abs(h - ref)) / g
+    say(f"  max |h - g e^(-j 2 pi a d) delta[n - d]| / g = {e:.3e}, |h[d]| = {abs(h[d]):.6f}")
     assert e <= 1e-4
 
 
