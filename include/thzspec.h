@@ -169,9 +169,11 @@ tz_status czt_transfer(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, 
  * X: B = opts->batch rows of N complex64 (interleaved float re, im), row b
  * at complex element b * in_stride (0 means N); x: B rows of N complex64,
  * out_stride complex elements apart (0 means N).  Both are device memory
- * owned by the caller; X is only read.  Computed as the CZT of eq. (11)
- * with A = 1, W = e^{+j 2 pi / N} and exact integer chirp phases, the 1/N
- * folded into the plan's chirp spectrum; any N with 2N - 1 <= 2^24.
+ * owned by the caller; X is only read.  Power-of-two N from 256 to 16384
+ * run as one FFT per row (conjugate, forward FFT, conjugate, exact 1/N);
+ * any other N with 2N - 1 <= 2^24 as the CZT of eq. (11) with A = 1,
+ * W = e^{+j 2 pi / N} and exact integer chirp phases, the 1/N folded into
+ * the plan's chirp spectrum.
  * in_dtype must be TZ_F32 (the components of complex64).
  * Errors: TZ_EINVAL for NULL pointers, N < 1, strides below N, in_dtype
  * TZ_F64; TZ_EUNSUPPORTED for split precision or 2N - 1 > 2^24.
