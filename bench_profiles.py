@@ -23,7 +23,8 @@ import sys
 KERNEL_KEYS = {"czt": ("k_czt<8192, 0, false>", 4194304), "fft_zeropad": ("k_fftpad_real<2048, 16, 0>", None),
                "zoom_front": ("k_zoom_front<0, 1, false>", 6291456),
                "zoom_short_dft": ("k_czt<2048, 2, false>", 3145728),
-               "transpose_2d_scans": ("k_transpose_c64", 524288), "transpose_3d_cube": ("k_transpose_c64", 2097152)}
+               "transpose_2d_scans": ("k_transpose_c64", 524288), "transpose_3d_cube": ("k_transpose_c64", 2097152),
+               "ifft": ("k_ifft_pow2<4096>", None)}
 
 
 def stats(path, out, cmd):
