@@ -29,7 +29,7 @@ METRIC = "CZT outputs/s over batched THz traces; %HBM peak; MFMA vs FP32 at 1e-5
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ["paper_2108_03948_amd/csrc/kernels.hip", "paper_2108_03948_amd/csrc/fft_core.h"]
+CSRC = os.path.join(ROOT, "paper_2108_03948_amd", "csrc")
 
 N_PAIRS, N, FS = 4096, 4096, 20e12
 F1, F2, M = 0.2e12, 2.5e12, 4096
@@ -42,10 +42,12 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of every library source (kernels, launch sizing, tables): byte
+    counters taken with other sources are stale."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 

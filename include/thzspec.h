@@ -48,7 +48,8 @@ typedef enum {
     TZ_EINVAL = 1,        /* an argument is out of range (nothing launched) */
     TZ_ENOMEM = 2,        /* a plan table could not be allocated            */
     TZ_EDEVICE = 3,       /* a HIP call failed                              */
-    TZ_EUNSUPPORTED = 4   /* valid arguments outside what the GPU path does */
+    TZ_EUNSUPPORTED = 4,  /* valid arguments outside what the GPU path does */
+    TZ_ETIMEOUT = 5       /* a bounded wait ended before the work was done  */
 } tz_status;
 
 /* input element type */
@@ -286,6 +287,21 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
 tz_status tz_batch_launch(tz_batch *batch, const void *x_flat, void *X_flat, void *stream);
 /* Free the batch (synchronises the device first). */
 void tz_batch_destroy(tz_batch *batch);
+/* Elements of x_flat (floats) and X_flat (complex floats) the jobs reach:
+ * max(in_offset + N) and max(out_offset + M) over the jobs.  tz_batch_launch
+ * reads and writes exactly these ranges; buffers must hold at least that
+ * many elements (the launch itself takes bare pointers and cannot check).
+ * TZ_EINVAL for a NULL argument. */
+tz_status tz_batch_extents(const tz_batch *batch, int64_t *x_elems, int64_t *X_elems);
+/* Host-side bounded wait for the batch's last launch (a watchdog for the
+ * persistent kernels): polls its completion for at most timeout_ms
+ * milliseconds.  TZ_OK once it has finished (or if the batch was never
+ * launched), TZ_ETIMEOUT if it is still running when the time is up (the
+ * work itself continues and a later wait may succeed), TZ_EDEVICE if the
+ * device reported an error, TZ_EINVAL for a NULL batch or a negative or NaN
+ * timeout.  The kernels of a batch always terminate: every persistent
+ * workgroup leaves when the shared work counter passes the last unit. */
+tz_status tz_batch_wait(tz_batch *batch, double timeout_ms);
 /* Write a one-line description of the batch into buf (NUL-terminated, at
  * most len bytes): jobs, work units per FFT length, and the schedule the
  * autotuner picked at the first launch with the time of every candidate.

@@ -24,13 +24,13 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libthzspec.so")
 
-TZ_OK, TZ_EINVAL, TZ_ENOMEM, TZ_EDEVICE, TZ_EUNSUPPORTED = range(5)
+TZ_OK, TZ_EINVAL, TZ_ENOMEM, TZ_EDEVICE, TZ_EUNSUPPORTED, TZ_ETIMEOUT = range(6)
 TZ_F32, TZ_F64 = 0, 1
 TZ_FP32, TZ_SPLIT_FP16, TZ_SPLIT_BF16 = 0, 1, 2
 TZ_HALF = 1
 TZ_JOB_CZT, TZ_JOB_ZOOM = 0, 1
 PRECISIONS = {"fp32": TZ_FP32, "split_fp16": TZ_SPLIT_FP16, "split_bf16": TZ_SPLIT_BF16}
-_STATUS = {1: "TZ_EINVAL", 2: "TZ_ENOMEM", 3: "TZ_EDEVICE", 4: "TZ_EUNSUPPORTED"}
+_STATUS = {1: "TZ_EINVAL", 2: "TZ_ENOMEM", 3: "TZ_EDEVICE", 4: "TZ_EUNSUPPORTED", 5: "TZ_ETIMEOUT"}
 
 
 class ThzError(RuntimeError):
@@ -89,7 +89,8 @@ EXPORTS = (
     "zoom_fft_nd", "czt_band",
     "fft_zero_count",
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "tz_batch_create",
-    "tz_batch_launch", "tz_batch_destroy", "tz_batch_describe", "tz_last_error", "tz_version",
+    "tz_batch_launch", "tz_batch_destroy", "tz_batch_describe", "tz_batch_extents", "tz_batch_wait",
+    "tz_last_error", "tz_version",
     "tz_release_plans", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute", "tz_plan_destroy",
     "tz_bin_freqs",
 )
@@ -133,6 +134,8 @@ def lib() -> ctypes.CDLL:
         L.tz_batch_destroy.restype = None
         L.tz_batch_describe.argtypes = [vp, ctypes.c_char_p, i64]
         L.tz_batch_describe.restype = i64
+        L.tz_batch_extents.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.tz_batch_wait.argtypes = [vp, dbl]
         L.tz_last_error.restype = ctypes.c_char_p
         L.tz_version.restype = ctypes.c_char_p
         L.tz_release_plans.restype = None
@@ -145,7 +148,7 @@ def lib() -> ctypes.CDLL:
         L.tz_bin_freqs.argtypes = [pp, po, ctypes.POINTER(ctypes.c_double)]
         for f in ("fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "ifft", "zoom_fft", "czt_band",
                   "czt_plan_shape",
-                  "tz_batch_create", "tz_batch_launch", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute",
+                  "tz_batch_create", "tz_batch_launch", "tz_batch_extents", "tz_batch_wait", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute",
                   "tz_bin_freqs"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -434,18 +437,38 @@ class Batch:
         _check(lib().tz_batch_create(arr, len(jobs), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self.n_jobs = len(jobs)
+        xe, Xe = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tz_batch_extents(self._h, ctypes.byref(xe), ctypes.byref(Xe)))
+        self.x_elems, self.X_elems = xe.value, Xe.value
 
     def launch(self, x_flat, X_flat, stream=None):
+        """Run every job: x_flat float32 and X_flat complex64, contiguous GPU
+        tensors of at least x_elems / X_elems elements."""
         torch = _torch()
         if x_flat.dtype != torch.float32 or X_flat.dtype != torch.complex64:
             raise TypeError("x_flat must be float32 and X_flat complex64")
         if not (x_flat.is_cuda and X_flat.is_cuda):
             raise TypeError("x_flat and X_flat must be GPU tensors")
+        if not (x_flat.is_contiguous() and X_flat.is_contiguous()):
+            raise ValueError("x_flat and X_flat must be contiguous")
+        if x_flat.numel() < self.x_elems or X_flat.numel() < self.X_elems:
+            raise ValueError(f"the jobs reach {self.x_elems} samples and {self.X_elems} bins; got buffers of "
+                             f"{x_flat.numel()} and {X_flat.numel()}")
+        if x_flat.device != X_flat.device:
+            raise ValueError("x_flat and X_flat must be on the same GPU")
         if stream is None:
             stream = torch.cuda.current_stream(x_flat.device)
         _check(lib().tz_batch_launch(self._h, x_flat.data_ptr(), X_flat.data_ptr(),
                                      ctypes.c_void_p(stream.cuda_stream)))
         return X_flat
+
+    def wait(self, timeout_ms: float) -> bool:
+        """Wait at most timeout_ms for the last launch; False on TZ_ETIMEOUT."""
+        st = lib().tz_batch_wait(self._h, float(timeout_ms))
+        if st == TZ_ETIMEOUT:
+            return False
+        _check(st)
+        return True
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)

@@ -20,7 +20,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <memory>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -397,9 +399,14 @@ __global__ void k_batch_zoom_tables(float2 *arena, const ZoomTableJob *__restric
 // ===========================================================================
 using namespace tz;
 
+namespace tz {
+void free_batch(tz_batch *b);
+}
+
 struct tz_batch {
   int device = 0;
   int64_t n_jobs = 0;
+  int64_t x_extent = 0, X_extent = 0;  // elements of x_flat / X_flat the jobs reach
   std::vector<BatchItem> items;
   std::vector<BatchUnit> units;  // grouped by class; order inside a class chosen by the autotuner
   int cls_count[15] = {};                   // units per FFT-length class
@@ -417,6 +424,11 @@ struct tz_batch {
   void *last_X = nullptr;
   bool tuned = false;
   double tuned_ms[4] = {-1, -1, -1, -1};
+  hipEvent_t done = nullptr;  // recorded after every launch (tz_batch_wait)
+  bool launched = false;
+  // every device buffer and graph object is released here, so an error
+  // return anywhere in tz_batch_create frees what was allocated before it
+  ~tz_batch() { tz::free_batch(this); }
 };
 
 namespace {
@@ -575,18 +587,45 @@ tz_status upload_units(tz_batch *b, hipStream_t s) {
   return TZ_OK;
 }
 
+}  // namespace
+
+// a device allocation freed when it leaves scope (plan-time scratch)
+struct ScopedDev {
+  void *p = nullptr;
+  ScopedDev() = default;
+  ScopedDev(const ScopedDev &) = delete;
+  ScopedDev &operator=(const ScopedDev &) = delete;
+  ~ScopedDev() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+namespace tz {
 void free_batch(tz_batch *b) {
+  bool any = b->exec || b->graph || b->done || b->d_arena || b->d_items || b->d_units || b->d_zjobs || b->d_u ||
+             b->d_counter;
+  for (void *p : b->d_tw) any = any || p;
+  if (!any) return;
   (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  void *ptrs[] = {b->d_arena, b->d_items, b->d_units, b->d_zjobs, b->d_u, b->d_counter};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
-  for (void *p : b->d_tw)
-    if (p) (void)hipFree(p);
+  if (b->done) (void)hipEventDestroy(b->done);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->done = nullptr;
+  void **ptrs[] = {&b->d_arena, &b->d_items, &b->d_units, &b->d_zjobs, &b->d_u, &b->d_counter};
+  for (void **p : ptrs)
+    if (*p) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  for (void *&p : b->d_tw)
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
 }
-
-}  // namespace
+}  // namespace tz
 
 extern "C" {
 
@@ -616,6 +655,8 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
       snprintf(msg, sizeof msg, "job %lld: invalid kind, N, M, band or offsets", (long long)i);
       return bfail(TZ_EINVAL, msg);
     }
+    b->x_extent = std::max(b->x_extent, j.in_offset + j.N);
+    b->X_extent = std::max(b->X_extent, j.out_offset + j.M);
     PhaseParams p;
     int64_t Nin = j.N;
     int complex_in = 0;
@@ -738,19 +779,20 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
 
   // tables: chirps (one workgroup per job), V per FFT-length class in chunks
   {
-    TableJob *d_tj = nullptr;
-    BHIP(hipMalloc((void **)&d_tj, sizeof(TableJob) * tjobs.size()), "table jobs");
+    ScopedDev tj_buf;
+    BHIP(hipMalloc(&tj_buf.p, sizeof(TableJob) * tjobs.size()), "table jobs");
+    TableJob *d_tj = (TableJob *)tj_buf.p;
     BHIP(hipMemcpy(d_tj, tjobs.data(), sizeof(TableJob) * tjobs.size(), hipMemcpyHostToDevice), "table jobs");
     hipLaunchKernelGGL(k_batch_chirps, dim3((unsigned)tjobs.size()), dim3(256), 0, s, (float2 *)b->d_arena, d_tj);
     BHIP(hipGetLastError(), "chirp tables");
     BHIP(hipStreamSynchronize(s), "chirp tables");
-    BHIP(hipFree(d_tj), "table jobs");
     const int64_t chunk_points = (int64_t)1 << 25;  // FP64 scratch: 2 x 512 MiB
-    double2 *va = nullptr, *vb = nullptr;
-    BHIP(hipMalloc((void **)&va, sizeof(double2) * chunk_points), "V scratch");
-    BHIP(hipMalloc((void **)&vb, sizeof(double2) * chunk_points), "V scratch");
-    TableJob *d_chunk = nullptr;
-    BHIP(hipMalloc((void **)&d_chunk, sizeof(TableJob) * tjobs.size()), "V jobs");
+    ScopedDev va_buf, vb_buf, chunk_buf;
+    BHIP(hipMalloc(&va_buf.p, sizeof(double2) * chunk_points), "V scratch");
+    BHIP(hipMalloc(&vb_buf.p, sizeof(double2) * chunk_points), "V scratch");
+    BHIP(hipMalloc(&chunk_buf.p, sizeof(TableJob) * tjobs.size()), "V jobs");
+    double2 *va = (double2 *)va_buf.p, *vb = (double2 *)vb_buf.p;
+    TableJob *d_chunk = (TableJob *)chunk_buf.p;
     for (int c = 8; c <= 14; ++c) {
       const int64_t L = 1LL << c;
       std::vector<TableJob> cls;
@@ -780,19 +822,16 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
         BHIP(hipStreamSynchronize(s), "V tables");
       }
     }
-    (void)hipFree(va);
-    (void)hipFree(vb);
-    (void)hipFree(d_chunk);
     if (!ztjobs.empty()) {
-      ZoomTableJob *d_zt = nullptr;
-      BHIP(hipMalloc((void **)&d_zt, sizeof(ZoomTableJob) * ztjobs.size()), "zoom table jobs");
+      ScopedDev zt_buf;
+      BHIP(hipMalloc(&zt_buf.p, sizeof(ZoomTableJob) * ztjobs.size()), "zoom table jobs");
+      ZoomTableJob *d_zt = (ZoomTableJob *)zt_buf.p;
       BHIP(hipMemcpy(d_zt, ztjobs.data(), sizeof(ZoomTableJob) * ztjobs.size(), hipMemcpyHostToDevice),
            "zoom table jobs");
       hipLaunchKernelGGL(k_batch_zoom_tables, dim3((unsigned)ztjobs.size()), dim3(256), 0, s,
                          (float2 *)b->d_arena, d_zt);
       BHIP(hipGetLastError(), "zoom tables");
       BHIP(hipStreamSynchronize(s), "zoom tables");
-      (void)hipFree(d_zt);
     }
   }
 
@@ -800,6 +839,7 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
   hipDeviceProp_t prop;
   BHIP(hipGetDeviceProperties(&prop, b->device), "device properties");
   b->grid = prop.multiProcessorCount;
+  BHIP(hipEventCreateWithFlags(&b->done, hipEventDisableTiming), "batch event");
   *out = b.release();
   return TZ_OK;
 }
@@ -849,14 +889,38 @@ tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *s
     if (st) return st;
   }
   BHIP(hipGraphLaunch(b->exec, s), "batch launch");
+  BHIP(hipEventRecord(b->done, s), "batch launch");
+  b->launched = true;
   return TZ_OK;
 }
 
-void tz_batch_destroy(tz_batch *b) {
-  if (!b) return;
-  free_batch(b);
-  delete b;
+tz_status tz_batch_extents(const tz_batch *b, int64_t *x_elems, int64_t *X_elems) {
+  if (!b || !x_elems || !X_elems) return bfail(TZ_EINVAL, "batch and both outputs must not be NULL");
+  *x_elems = b->x_extent;
+  *X_elems = b->X_extent;
+  return TZ_OK;
 }
+
+tz_status tz_batch_wait(tz_batch *b, double timeout_ms) {
+  if (!b) return bfail(TZ_EINVAL, "batch is NULL");
+  if (!(timeout_ms >= 0.0)) return bfail(TZ_EINVAL, "timeout_ms must be >= 0");
+  if (!b->launched) return TZ_OK;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipEventQuery(b->done);
+    if (e == hipSuccess) return TZ_OK;
+    if (e != hipErrorNotReady) return bfail(TZ_EDEVICE, std::string("batch wait: ") + hipGetErrorString(e));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (ms >= timeout_ms) {
+      char msg[160];
+      snprintf(msg, sizeof msg, "the last launch of the batch had not finished after %.3f ms", ms);
+      return bfail(TZ_ETIMEOUT, msg);
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(timeout_ms - ms > 1.0 ? 200 : 20));
+  }
+}
+
+void tz_batch_destroy(tz_batch *b) { delete b; }
 
 int64_t tz_batch_describe(const tz_batch *b, char *buf, int64_t len) {
   if (!b) return -1;

@@ -323,3 +323,12 @@ def test_plan_invalid_arguments_rejected_before_device_work(tz):
     f = (ctypes.c_double * 100)()
     st, err = _raw(tz, L.tz_bin_freqs, ctypes.byref(p), None, f)
     assert st == tz.TZ_EINVAL and "time samples" in err
+
+
+def test_batch_wait_and_extents_reject_null(tz):
+    L = tz.lib()
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    assert L.tz_batch_extents(None, ctypes.byref(a), ctypes.byref(b)) == tz.TZ_EINVAL
+    assert L.tz_batch_wait(None, 1.0) == tz.TZ_EINVAL
+    assert "NULL" in L.tz_last_error().decode()
+    assert tz.TZ_ETIMEOUT == 5

@@ -149,3 +149,56 @@ def test_full_uneven_workload_sampled(tz, orc):
     say(f"  worst rel L2 over {len(rows)} sampled jobs {worst:.3e}")
     assert np.isfinite(X).all()
     b.close()
+
+
+def test_batch_extents_and_buffer_checks(tz):
+    """The batch reports the ranges its jobs reach, and the binding refuses
+    short, strided or misplaced buffers before launching anything."""
+    import torch
+    dev = torch.device("cuda:0")
+    jobs = [dict(kind="czt", N=300, M=40, fs_hz=20 * 10**12, f1_hz=2 * 10**11, f2_hz=25 * 10**11,
+                 in_offset=100, out_offset=7),
+            dict(kind="zoom", N=500, M=64, D=4, fs_hz=20 * 10**12, f1_hz=2 * 10**11, f2_hz=25 * 10**11,
+                 in_offset=0, out_offset=50)]
+    say("case: batch extents and buffer checks")
+    b = tz.Batch(jobs)
+    assert (b.x_elems, b.X_elems) == (500, 114)
+    x = torch.zeros(500, device=dev)
+    X = torch.zeros(114, dtype=torch.complex64, device=dev)
+    with pytest.raises(ValueError):
+        b.launch(x[:499], X)
+    with pytest.raises(ValueError):
+        b.launch(x, X[:113])
+    with pytest.raises(ValueError):
+        b.launch(torch.zeros(1000, device=dev)[::2], X)
+    with pytest.raises(TypeError):
+        b.launch(x.cpu(), X)
+    b.launch(x, X)
+    assert b.wait(60_000.0)
+    b.close()
+
+
+def test_batch_bounded_wait_times_out_then_completes(tz, orc):
+    """tz_batch_wait gives up with TZ_ETIMEOUT while the batch is still
+    queued behind a bounded spin kernel on the same stream (every kernel
+    ends normally), then succeeds once it has run, with correct output."""
+    import torch
+    x_flat, offs, meta = synth.uneven(B=6, seed=21, Nmin=500, Nmax=3000, Mmin=100, Mmax=800)
+    jobs, total = make_jobs(meta, offs)
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(x_flat).to(dev)
+    Xd = torch.zeros(total, dtype=torch.complex64, device=dev)
+    b = tz.Batch(jobs)
+    b.launch(xd, Xd)  # first launch: autotuned, synchronous
+    torch.cuda.synchronize()
+    Xd.zero_()
+    say("case: bounded wait behind a spin kernel")
+    t0 = time.time()
+    torch.cuda._sleep(200_000_000)  # a spin of a few hundred million clock ticks
+    b.launch(xd, Xd)
+    assert not b.wait(1.0), "the batch cannot have finished behind the spin kernel"
+    assert b.wait(120_000.0)
+    say(f"  waited {time.time() - t0:.2f} s in all")
+    X = Xd.cpu().numpy()
+    check_jobs(orc, x_flat, offs, jobs, X, range(len(jobs)), np.random.default_rng(2))
+    b.close()

@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import synth
+from transfer_checks import check_transfer
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-6
@@ -41,35 +42,32 @@ def check(tz, orc, x, M, W, A, what):
     import torch
     Hg = tz.czt_transfer(torch.from_numpy(x).cuda(), M, W, A).cpu().numpy()
     X = orc.czt(x.astype(np.float64), M, W, A)
-    Xr, Xs = X[0::2], X[1::2]
-    H = Xs / Xr
-    worst_w, worst_b = 0.0, 0.0
-    for p in range(H.shape[0]):
-        ew = np.linalg.norm(Xr[p] * (Hg[p] - H[p])) / np.linalg.norm(Xs[p])
-        strong = np.abs(Xr[p]) >= 0.1 * np.abs(Xr[p]).max()
-        eb = np.max(np.abs(Hg[p][strong] - H[p][strong]) / np.abs(H[p][strong]))
-        worst_w, worst_b = max(worst_w, ew), max(worst_b, eb)
-    say(f"  {what}: weighted rel L2 {worst_w:.3e}, strong-bin max rel {worst_b:.3e}")
-    assert worst_w <= TOL and worst_b <= 1e-5
+    check_transfer(Hg, X, TOL, 1e-5, say=say, what=what)
     return Hg
+
+
+def in_window_pairs(n_pairs, N, fs=20e12):
+    """Pairs whose reference pulse sits at 0.3 of the window, so that the
+    sample (2-8 ps later) also lies inside short windows."""
+    return synth.pairs(n_pairs, N=N, fs=fs, t0=min(15e-12, 0.3 * N / fs))
 
 
 @pytest.mark.parametrize("N,M", [(4096, 4096), (300, 200), (5000, 3000), (2000, 14000)])
 def test_transfer_pairs(tz, orc, N, M):
-    x = synth.pairs(3, N=N)
+    x = in_window_pairs(3, N)
     W, A = tz.czt_band(20e12, 0.2e12, 2.5e12, M)
     say(f"case: czt_transfer pairs N={N} M={M} plan {tz.czt_plan_shape(N, M)}")
     check(tz, orc, x, M, W, A, "pairs")
 
 
 def test_transfer_fp64_input(tz, orc):
-    x = synth.pairs(2, N=1500).astype(np.float64)
+    x = in_window_pairs(2, 1500).astype(np.float64)
     W, A = tz.czt_band(20e12, 0.3e12, 1.8e12, 900)
     say("case: czt_transfer f64 input")
     check(tz, orc, x, 900, W, A, "f64")
 
 
-def test_transfer_integer_delay_closed_form(tz):
+def test_transfer_integer_delay_closed_form(tz, orc):
     import torch
     rng = np.random.default_rng(31)
     N, d, g, M = 1000, 37, 0.6, 700
@@ -83,10 +81,16 @@ def test_transfer_integer_delay_closed_form(tz):
     Hg = tz.czt_transfer(torch.from_numpy(np.stack([xr, xs])).cuda(), M, W, A).cpu().numpy()[0]
     k = np.arange(M)
     ref = g * np.exp(-2j * np.pi * (a + k * w) * d)
+    assert np.isfinite(Hg).all()
+    Xr = orc.czt(xr[None].astype(np.float64), M, W, A)[0]
+    ew = np.linalg.norm(Xr * (Hg - ref)) / (g * np.linalg.norm(Xr))
     e = np.max(np.abs(Hg - ref)) / g
-    say(f"  max |H - g e^(-j 2 pi nu d)| / g = {e:.3e}")
-    # white reference: no weak bins, every bin is within reach of FP32
-    assert e <= 1e-4
+    say(f"  ||X_r (H - g e^(-j 2 pi nu d))|| / ||g X_r|| = {ew:.3e}; max |H - g e^(-j 2 pi nu d)| / g = {e:.3e}")
+    # white reference: the weighted error is the FP32 CZT error of the two
+    # rows; single bins where |X_r| dips far below its rms carry a few times
+    # more
+    assert ew <= 1e-6
+    assert e <= 1e-5
 
 
 def test_transfer_back_to_time_is_the_delay_impulse(tz):
@@ -108,9 +112,10 @@ def test_transfer_back_to_time_is_the_delay_impulse(tz):
     h = tz.ifft(H).cpu().numpy()[0]
     ref = np.zeros(M, complex)
     ref[d] = g * np.exp(-2j * np.pi * a * d)
+    assert np.isfinite(h).all()
     e = np.max(np.abs(h - ref)) / g
     say(f"  max |h - g e^(-j 2 pi a d) delta[n - d]| / g = {e:.3e}, |h[d]| = {abs(h[d]):.6f}")
-    assert e <= 1e-4
+    assert e <= 1e-6
 
 
 def test_transfer_rejects(tz):
