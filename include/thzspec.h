@@ -357,6 +357,27 @@ tz_status tz_plan_workspace(const tz_plan *plan, size_t *bytes);
 tz_status tz_plan_execute(const tz_plan *plan, const void *x, void *X, void *workspace, void *stream);
 /* Free the plan (synchronises the device first). */
 void tz_plan_destroy(tz_plan *plan);
+
+/* Bytes of the library's fixed device scratch array (one per GPU). */
+#define TZ_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * tz_plan_execute() without a workspace argument, for callers that cannot
+ * allocate device memory themselves (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the workspace is a fixed
+ * array of TZ_STATIC_SCRATCH_BYTES inside this library, one copy per GPU,
+ * held until the process ends.  Same outputs as tz_plan_execute(); the call
+ * allocates nothing (the first call on a device looks up that device's copy
+ * of the array).  The four-step path runs as many traces per chunk as fit
+ * the array.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents: calls whose executions overlap on one GPU (different
+ * streams, not ordered) race on it and give wrong results; order them on one
+ * stream.  TZ_EINVAL, with nothing launched, for NULL buffers, a current
+ * device other than the plan's, or a plan whose workspace cannot fit the
+ * array (a Zoom FFT whose decimated rows, B ceil(N/D) complex64, exceed it,
+ * or a four-step trace of more than TZ_STATIC_SCRATCH_BYTES / 8 points).
+ */
+tz_status tz_plan_execute_static(const tz_plan *plan, const void *x, void *X, void *stream);
 /* Frequency in hertz of every output bin of params (host only, no device
  * work): fft_zeropad k fs / N_fft (eq. (3)), k < N_fft or N_fft/2 + 1 with
  * TZ_HALF in opts->flags; czt fs (nu_A + k nu_W) for A = e^{j 2 pi nu_A},

@@ -91,7 +91,8 @@ EXPORTS = (
     "czt_points_for_resolution", "zoom_short_length", "czt_plan_shape", "tz_batch_create",
     "tz_batch_launch", "tz_batch_destroy", "tz_batch_describe", "tz_batch_extents", "tz_batch_wait",
     "tz_last_error", "tz_version",
-    "tz_release_plans", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute", "tz_plan_destroy",
+    "tz_release_plans", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute", "tz_plan_execute_static",
+    "tz_plan_destroy",
     "tz_bin_freqs",
 )
 
@@ -143,13 +144,14 @@ def lib() -> ctypes.CDLL:
         L.tz_plan_create.argtypes = [pp, po, ctypes.POINTER(vp)]
         L.tz_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.tz_plan_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.tz_plan_execute_static.argtypes = [vp, vp, vp, vp]
         L.tz_plan_destroy.argtypes = [vp]
         L.tz_plan_destroy.restype = None
         L.tz_bin_freqs.argtypes = [pp, po, ctypes.POINTER(ctypes.c_double)]
         for f in ("fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "ifft", "zoom_fft", "czt_band",
                   "czt_plan_shape",
                   "tz_batch_create", "tz_batch_launch", "tz_batch_extents", "tz_batch_wait", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute",
-                  "tz_bin_freqs"):
+                  "tz_plan_execute_static", "tz_bin_freqs"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         return L
@@ -565,10 +567,7 @@ class Plan:
         _check(lib().tz_plan_workspace(self._h, ctypes.byref(n)))
         self.workspace_bytes = n.value
 
-    def execute(self, x, out, workspace=None, stream=None):
-        """x: [batch, N] (rows in_stride apart), out: [batch, bins] complex64
-        (rows out_stride apart), workspace: a GPU tensor of at least
-        workspace_bytes bytes (None when that is 0).  Asynchronous."""
+    def _check_buffers(self, x, out):
         torch = _torch()
         if not (x.is_cuda and out.is_cuda) or x.dtype != self.dtype or out.dtype != torch.complex64:
             raise TypeError("x must be a GPU tensor of the plan's dtype and out a complex64 GPU tensor")
@@ -578,6 +577,13 @@ class Plan:
             raise ValueError("row strides must be the plan's in_stride / out_stride")
         if x.stride(-1) != 1 or out.stride(-1) != 1:
             raise ValueError("rows must be contiguous")
+
+    def execute(self, x, out, workspace=None, stream=None):
+        """x: [batch, N] (rows in_stride apart), out: [batch, bins] complex64
+        (rows out_stride apart), workspace: a GPU tensor of at least
+        workspace_bytes bytes (None when that is 0).  Asynchronous."""
+        torch = _torch()
+        self._check_buffers(x, out)
         ws = 0
         if self.workspace_bytes:
             if workspace is None or not workspace.is_cuda or \
@@ -587,6 +593,19 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream(x.device)
         _check(lib().tz_plan_execute(self._h, x.data_ptr(), out.data_ptr(), ws, ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def execute_static(self, x, out, stream=None):
+        """execute() with the library's fixed device scratch array as the
+        workspace (tz_plan_execute_static): no workspace argument and no
+        allocation.  Calls on one GPU share that array, so they must be
+        ordered on one stream.  Asynchronous."""
+        self._check_buffers(x, out)
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        _check(lib().tz_plan_execute_static(self._h, x.data_ptr(), out.data_ptr(),
+                                            ctypes.c_void_p(stream.cuda_stream)))
         return out
 
     def close(self):

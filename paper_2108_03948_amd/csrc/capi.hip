@@ -1278,6 +1278,100 @@ tz_status tz_plan_execute(const tz_plan *P, const void *x, void *X, void *worksp
   }
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free execution: the workspace is a fixed device array of this
+// library, one copy per GPU, shared by every call on that GPU
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[TZ_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch;  // device -> address of its copy of `scratch`
+
+// the device address of this GPU's copy, looked up once per device with that
+// device current (the array's name is only a host-side stand-in)
+tz_status static_scratch(int dev, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void *p = nullptr;
+    TZ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "static scratch address");
+    it = g_scratch.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return TZ_OK;
+}
+
+// Fit a Bluestein execution into `bytes` of workspace: single-pass plans
+// need none; the four-step path runs fewer traces per chunk (the chunk only
+// groups traces, every trace is computed the same way).  False if even one
+// trace's intermediates do not fit.
+bool fit_blue(BlueExec &e, size_t bytes) {
+  if (!e.ws) return true;
+  if (!e.pl->L1) return e.ws <= bytes;
+  const size_t per = sizeof(float2) * (size_t)e.pl->L;
+  const int64_t fit = (int64_t)(bytes / per);
+  if (fit < 1) return false;
+  if (e.chunk > fit) e.chunk = fit;
+  e.ws = per * (size_t)e.chunk;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+tz_status tz_plan_execute_static(const tz_plan *P, const void *x, void *X, void *stream) {
+  if (!P) return fail(TZ_EINVAL, "plan must not be NULL");
+  if (!x || !X) return fail(TZ_EINVAL, "x and X must be device pointers, got NULL");
+  const int dev = current_device();
+  if (dev != P->dev) return fail(TZ_EINVAL, "plan built on device %d, current device is %d", P->dev, dev);
+  const size_t cap = TZ_STATIC_SCRATCH_BYTES;
+  const hipStream_t s = (hipStream_t)stream;
+  const Common &c = P->c;
+  bool fits = true;
+  BlueExec b;
+  switch (P->kind) {
+    case TZ_PLAN_FFT_ZEROPAD: b = P->p.b; break;
+    case TZ_PLAN_IFFT: b = P->i.b; break;
+    case TZ_PLAN_ZOOM:
+      b = P->z.b;
+      fits = P->u_bytes <= cap;
+      break;
+    default: b = P->b; break;
+  }
+  const size_t rest = fits ? cap - (P->kind == TZ_PLAN_ZOOM ? P->u_bytes : 0) : 0;
+  if (!fits || !fit_blue(b, rest))
+    return fail(TZ_EINVAL,
+                "plan needs more workspace than the static scratch holds (%zu bytes; the plan's own execution "
+                "takes %zu): use tz_plan_execute with a workspace",
+                cap, P->ws);
+  void *ws = nullptr;
+  tz_status st = static_scratch(dev, &ws);
+  if (st) return st;
+  switch (P->kind) {
+    case TZ_PLAN_FFT_ZEROPAD: {
+      PadExec e = P->p;
+      e.b = b;
+      return exec_pad(e, x, c.in_kind, X, c, ws, s);
+    }
+    case TZ_PLAN_IFFT: {
+      IfftExec e = P->i;
+      e.b = b;
+      return exec_ifft(e, x, X, c, ws, s);
+    }
+    case TZ_PLAN_ZOOM: {
+      ZoomExec e = P->z;
+      e.b = b;
+      return exec_zoom(e, x, c.in_kind, X, c, ws, (char *)ws + P->u_bytes, s);
+    }
+    default: return exec_blue(b, x, c.in_kind, X, c, P->bins, ws, s);
+  }
+}
+
 void tz_plan_destroy(tz_plan *P) {
   if (!P) return;
   (void)hipDeviceSynchronize();  // work that reads its tables may be in flight
