@@ -336,12 +336,18 @@ __global__ void __launch_bounds__(64 * P)
     }
   };
 
+  // the wave's first thread index, pinned in a scalar register (the empty
+  // asm) for the whole kernel: no vector register carries a thread index
+  // across the trace loop, where it would be spilled and its reload, like
+  // any load, would wait for every store still in flight
+  unsigned w0 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
+  asm volatile("" : "+s"(w0));
   for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
     __syncthreads();  // tables filled / previous trace's staging reads done
-    // thread indices through an opaque zero: everything derived from them
-    // (twiddles, LDS addresses) is formed per trace instead of being hoisted
-    // out of the loop and kept live in registers across it
-    const unsigned tid = threadIdx.x + opaque_zero();
+    // thread indices through an opaque zero (the lane from mbcnt): everything
+    // derived from them (twiddles, LDS addresses) is formed per trace instead
+    // of being hoisted out of the loop and kept live in registers across it
+    const unsigned tid = w0 + (__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, opaque_zero())) & 63u);
     // the wave index is wave-uniform: it and what derives from it only need
     // scalar registers
     const unsigned r = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
