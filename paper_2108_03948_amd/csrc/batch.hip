@@ -61,6 +61,11 @@ struct ZoomJob {
   int32_t N, LD, D, T;
 };
 
+// one workgroup of the zoom front end: outputs [m0, m0 + opb) of one job
+struct ZoomTile {
+  int32_t job, m0;
+};
+
 // workgroup size of the class kernels: 512 threads (two waves per SIMD, so
 // the CZT body keeps its ~160 registers without spilling), or the FFT's own
 // thread count when that is larger
@@ -166,12 +171,13 @@ __global__ void k_batch_reset(unsigned *counters, int n) {
   if (blockIdx.x == 0 && (int)threadIdx.x < n) counters[threadIdx.x] = 0u;
 }
 
-// zoom front end for every zoom job (one workgroup per job):
+// zoom front end for every zoom job, one workgroup per tile of opb outputs
+// of one job (a job of L_D outputs spans ceil(L_D / opb) tiles, so short and
+// long jobs alike spread over the whole chip):
 // u[m] = e^{-j 2 pi nu_N m D} sum_t g[t] x[mD - t], FP64 taps, phasors and
-// sums (the T-term sum in FP32 would lose accuracy as sqrt(T)).  The job's
-// samples pass through an LDS tile in chunks of opb outputs (buffer loads:
-// zeros outside [0, N)); the tap index is the same across the wave, so the
-// taps come through scalar loads.  When D is a multiple of 4 the tile has two
+// sums (the T-term sum in FP32 would lose accuracy as sqrt(T)).  The tile's
+// samples pass through LDS (buffer loads: zeros outside [0, N)); the tap
+// index is the same across the wave, so the taps come through scalar loads.  When D is a multiple of 4 the tile has two
 // pad words after every D samples (sample i at word i + 2 floor(i/D)): output
 // j's base j (D + 2) then spreads the lanes over the banks, and the offset of
 // tap c, c + 2 floor(c/D), is the same in every lane, an immediate of the LDS
@@ -180,17 +186,28 @@ __global__ void k_batch_reset(unsigned *counters, int n) {
 // of 2^29 samples or more, read x and the taps straight from global memory.
 constexpr int kBZTile = 6144;  // samples per chunk
 
+// outputs per tile: their samples, (opb - 1) D + T, fit the LDS chunk
+// (opb >= 1); jobs on the global-memory path take tiles of 256 outputs
+__host__ __device__ inline int zoom_tile_outputs(int D, int T, int N) {
+  if (2 * T > kBZTile || N >= (1 << 29)) return 256;
+  const int o = (kBZTile - T) / D + 1;
+  return o < 256 ? o : 256;
+}
+
 __global__ void __launch_bounds__(256)
     k_batch_zoom_front(const float *__restrict__ x, float2 *__restrict__ u, const float2 *__restrict__ arena,
-                       const ZoomJob *__restrict__ jobs) {
+                       const ZoomJob *__restrict__ jobs, const ZoomTile *__restrict__ tiles) {
   __shared__ float xl[kBZTile + kBZTile / 2 + 1];
-  const ZoomJob j = jobs[blockIdx.x];
+  const ZoomTile tl = tiles[blockIdx.x];
+  const ZoomJob j = jobs[tl.job];
   const double2 *g = (const double2 *)(arena + j.g_off);
   const double2 *ph = (const double2 *)(arena + j.ph_off);
   const float *xb = x + j.x_off;
   const int D = j.D, T = j.T, N = j.N, LD = j.LD;
+  const int opb = zoom_tile_outputs(D, T, N);
+  const int m_end = tl.m0 + opb < LD ? tl.m0 + opb : LD;
   if (2 * T > kBZTile || N >= (1 << 29)) {
-    for (int m = threadIdx.x; m < LD; m += 256) {
+    for (int m = tl.m0 + (int)threadIdx.x; m < m_end; m += 256) {
       const int64_t base = (int64_t)m * D;
       double ar = 0.0, ai = 0.0;
       for (int tt = 0; tt < T; ++tt) {
@@ -210,15 +227,13 @@ __global__ void __launch_bounds__(256)
   const uint32_t dmagic = P ? (uint32_t)((((uint64_t)1 << 32) + D - 1) / D) : 0u;  // floor(i/D) = umulhi(i, dmagic)
   // reads past N return 0; n < 0 wraps to an offset above 2^31 (N * 4 < 2^31)
   const Rsrc rx = make_rsrc(xb, (uint64_t)N * 4);
-  // outputs per chunk: their samples, (opb - 1) D + T, fit the tile (opb >= 1)
-  const int opb = (kBZTile - T) / D + 1 < 256 ? (kBZTile - T) / D + 1 : 256;
   const int jt = (int)threadIdx.x;
   const float *base = xl + jt * (D + P);
   const double2 *gp = g + (T - 1);  // tap of tile sample c (c = T - 1 - t): gp[-c]
-  for (int m0 = 0; m0 < LD; m0 += opb) {
+  {
+    const int m0 = tl.m0;
     const int64_t n0 = (int64_t)m0 * D - (T - 1);
     const int span = (opb - 1) * D + T;
-    __syncthreads();  // the previous chunk's reads are done
 #pragma unroll 4
     for (int i = jt; i < span; i += 256)
       xl[i + (P ? P * __umulhi((unsigned)i, dmagic) : 0u)] = ld_f32(rx, (unsigned)((n0 + i) * 4));
@@ -412,7 +427,8 @@ struct tz_batch {
   int cls_count[15] = {};                   // units per FFT-length class
   int bkt_first[60] = {}, bkt_count[60] = {};  // bucket = class * 4 + flavor
   std::vector<ZoomJob> zjobs;
-  void *d_arena = nullptr, *d_items = nullptr, *d_units = nullptr, *d_zjobs = nullptr;
+  std::vector<ZoomTile> ztiles;
+  void *d_arena = nullptr, *d_items = nullptr, *d_units = nullptr, *d_zjobs = nullptr, *d_ztiles = nullptr;
   void *d_u = nullptr, *d_counter = nullptr;
   void *d_tw[15] = {};
   int grid = 0;
@@ -524,7 +540,7 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
     b->graph = nullptr;
   }
   BHIP(hipGraphCreate(&b->graph, 0), "graph create");
-  hipGraphNode_t reset, prev;
+  hipGraphNode_t reset, front = nullptr;
   {
     unsigned *ctr = (unsigned *)b->d_counter;
     int n = 60;
@@ -536,42 +552,53 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
     p.kernelParams = args;
     BHIP(hipGraphAddKernelNode(&reset, b->graph, nullptr, 0, &p), "graph reset node");
   }
-  prev = reset;
   const float *xf = (const float *)x;
   float2 *Xc = (float2 *)X;
   if (!b->zjobs.empty()) {
+    // the front end reads x and writes u only: it needs no counter reset
     float2 *u = (float2 *)b->d_u;
     const float2 *arena = (const float2 *)b->d_arena;
     const ZoomJob *zj = (const ZoomJob *)b->d_zjobs;
-    void *args[] = {(void *)&xf, (void *)&u, (void *)&arena, (void *)&zj};
+    const ZoomTile *zt = (const ZoomTile *)b->d_ztiles;
+    void *args[] = {(void *)&xf, (void *)&u, (void *)&arena, (void *)&zj, (void *)&zt};
     hipKernelNodeParams p{};
     p.func = (void *)k_batch_zoom_front;
-    p.gridDim = dim3((unsigned)b->zjobs.size());
+    p.gridDim = dim3((unsigned)b->ztiles.size());
     p.blockDim = dim3(256);
     p.kernelParams = args;
-    hipGraphNode_t front;
-    BHIP(hipGraphAddKernelNode(&front, b->graph, &prev, 1, &p), "graph front node");
-    prev = front;
+    BHIP(hipGraphAddKernelNode(&front, b->graph, nullptr, 0, &p), "graph front node");
   }
-  const hipGraphNode_t root = prev;
+  // Real-input classes (CZT jobs) wait only for the counter reset, so they
+  // run beside the zoom front end; complex-input classes (the zooms' short
+  // DFTs) also wait for the front end.  Topology 0 makes every class its own
+  // branch; topology 1 chains the classes of each input kind longest first.
+  hipGraphNode_t chain[2] = {nullptr, nullptr};
   for (int c = 14; c >= 8; --c)
     for (int fl = 0; fl < 4; ++fl) {
       const int bucket = c * 4 + fl;
       if (!b->bkt_count[bucket]) continue;
-      const hipGraphNode_t dep = (b->topology == 0) ? root : prev;
+      const int cin = fl & 1;
+      hipGraphNode_t deps[2];
+      int nd = 0;
+      if (b->topology == 1 && chain[cin]) {
+        deps[nd++] = chain[cin];
+      } else {
+        deps[nd++] = reset;
+        if (cin) deps[nd++] = front;
+      }
       hipGraphNode_t node;
       tz_status st = TZ_OK;
       switch (c) {
-        case 8: st = add_class_node<256>(b, bucket, xf, Xc, &dep, 1, &node); break;
-        case 9: st = add_class_node<512>(b, bucket, xf, Xc, &dep, 1, &node); break;
-        case 10: st = add_class_node<1024>(b, bucket, xf, Xc, &dep, 1, &node); break;
-        case 11: st = add_class_node<2048>(b, bucket, xf, Xc, &dep, 1, &node); break;
-        case 12: st = add_class_node<4096>(b, bucket, xf, Xc, &dep, 1, &node); break;
-        case 13: st = add_class_node<8192>(b, bucket, xf, Xc, &dep, 1, &node); break;
-        default: st = add_class_node<16384>(b, bucket, xf, Xc, &dep, 1, &node); break;
+        case 8: st = add_class_node<256>(b, bucket, xf, Xc, deps, nd, &node); break;
+        case 9: st = add_class_node<512>(b, bucket, xf, Xc, deps, nd, &node); break;
+        case 10: st = add_class_node<1024>(b, bucket, xf, Xc, deps, nd, &node); break;
+        case 11: st = add_class_node<2048>(b, bucket, xf, Xc, deps, nd, &node); break;
+        case 12: st = add_class_node<4096>(b, bucket, xf, Xc, deps, nd, &node); break;
+        case 13: st = add_class_node<8192>(b, bucket, xf, Xc, deps, nd, &node); break;
+        default: st = add_class_node<16384>(b, bucket, xf, Xc, deps, nd, &node); break;
       }
       if (st) return st;
-      prev = node;
+      chain[cin] = node;
     }
   BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
   b->last_x = x;
@@ -602,8 +629,8 @@ struct ScopedDev {
 
 namespace tz {
 void free_batch(tz_batch *b) {
-  bool any = b->exec || b->graph || b->done || b->d_arena || b->d_items || b->d_units || b->d_zjobs || b->d_u ||
-             b->d_counter;
+  bool any = b->exec || b->graph || b->done || b->d_arena || b->d_items || b->d_units || b->d_zjobs ||
+             b->d_ztiles || b->d_u || b->d_counter;
   for (void *p : b->d_tw) any = any || p;
   if (!any) return;
   (void)hipDeviceSynchronize();
@@ -613,7 +640,7 @@ void free_batch(tz_batch *b) {
   b->exec = nullptr;
   b->graph = nullptr;
   b->done = nullptr;
-  void **ptrs[] = {&b->d_arena, &b->d_items, &b->d_units, &b->d_zjobs, &b->d_u, &b->d_counter};
+  void **ptrs[] = {&b->d_arena, &b->d_items, &b->d_units, &b->d_zjobs, &b->d_ztiles, &b->d_u, &b->d_counter};
   for (void **p : ptrs)
     if (*p) {
       (void)hipFree(*p);
@@ -686,6 +713,9 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
       zt.nu_N = nuN - floor(nuN);
       zt.g_off = zj.g_off = take(2 * (int64_t)T);  // double2 = two float2 slots
       zt.ph_off = zj.ph_off = take(2 * LD);
+      const int opb = zoom_tile_outputs(zj.D, zj.T, zj.N);
+      for (int64_t m0 = 0; m0 < LD; m0 += opb)
+        b->ztiles.push_back(ZoomTile{(int32_t)b->zjobs.size(), (int32_t)m0});
       b->zjobs.push_back(zj);
       ztjobs.push_back(zt);
       p = zoom_phase(K, j.M);
@@ -765,6 +795,9 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
   if (!b->zjobs.empty()) {
     BHIP(hipMalloc(&b->d_zjobs, sizeof(ZoomJob) * b->zjobs.size()), "batch zoom jobs");
     BHIP(hipMemcpy(b->d_zjobs, b->zjobs.data(), sizeof(ZoomJob) * b->zjobs.size(), hipMemcpyHostToDevice),
+         "batch upload");
+    BHIP(hipMalloc(&b->d_ztiles, sizeof(ZoomTile) * b->ztiles.size()), "batch zoom tiles");
+    BHIP(hipMemcpy(b->d_ztiles, b->ztiles.data(), sizeof(ZoomTile) * b->ztiles.size(), hipMemcpyHostToDevice),
          "batch upload");
   }
   BHIP(hipMemcpy(b->d_items, b->items.data(), sizeof(BatchItem) * b->items.size(), hipMemcpyHostToDevice),
