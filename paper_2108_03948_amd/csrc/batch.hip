@@ -234,9 +234,18 @@ __global__ void __launch_bounds__(256)
     const int m0 = tl.m0;
     const int64_t n0 = (int64_t)m0 * D - (T - 1);
     const int span = (opb - 1) * D + T;
-#pragma unroll 4
-    for (int i = jt; i < span; i += 256)
-      xl[i + (P ? P * __umulhi((unsigned)i, dmagic) : 0u)] = ld_f32(rx, (unsigned)((n0 + i) * 4));
+    // every load of the tile is issued before the first LDS write (one
+    // memory round trip per tile instead of one per group of loads); loads
+    // past the span are harmless (read in range or as 0) and not stored
+    constexpr int kPer = kBZTile / 256;
+    float xv[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) xv[k] = ld_f32(rx, (unsigned)((n0 + jt + 256 * k) * 4));
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = jt + 256 * k;
+      if (i < span) xl[i + (P ? P * __umulhi((unsigned)i, dmagic) : 0u)] = xv[k];
+    }
     __syncthreads();
     const int m = m0 + jt;
     if (jt < opb && m < LD) {
@@ -600,6 +609,7 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
       if (st) return st;
       chain[cin] = node;
     }
+  if (fault_injected("graph")) return bfail(TZ_EDEVICE, "graph instantiate: injected failure (TZ_FAULT=graph)");
   BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
   b->last_x = x;
   b->last_X = X;
@@ -779,6 +789,8 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
       }
     }
   b->units = order_units(*b, units, 0);
+  tz_log("batch: %lld jobs (%zu zoom, %zu front-end tiles), %zu work items in %zu units", (long long)n_jobs,
+         b->zjobs.size(), b->ztiles.size(), b->items.size(), units.size());
   for (size_t i = 0; i < b->units.size(); ++i) {
     const int c = b->units[i].lclass, bk = c * 4 + b->units[i].flavor;
     if (!b->bkt_count[bk]) b->bkt_first[bk] = (int)i;
@@ -787,16 +799,16 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
   }
 
   // device buffers
-  BHIP(hipMalloc(&b->d_arena, sizeof(float2) * std::max<int64_t>(arena, 64)), "batch arena");
-  BHIP(hipMalloc(&b->d_items, sizeof(BatchItem) * b->items.size()), "batch items");
-  BHIP(hipMalloc(&b->d_units, sizeof(BatchUnit) * b->units.size()), "batch units");
-  BHIP(hipMalloc(&b->d_u, sizeof(float2) * std::max<int64_t>(uscratch, 64)), "batch zoom scratch");
-  BHIP(hipMalloc(&b->d_counter, sizeof(unsigned) * 64), "batch counters");
+  BHIP(dev_malloc((void **)&b->d_arena, sizeof(float2) * std::max<int64_t>(arena, 64)), "batch arena");
+  BHIP(dev_malloc((void **)&b->d_items, sizeof(BatchItem) * b->items.size()), "batch items");
+  BHIP(dev_malloc((void **)&b->d_units, sizeof(BatchUnit) * b->units.size()), "batch units");
+  BHIP(dev_malloc((void **)&b->d_u, sizeof(float2) * std::max<int64_t>(uscratch, 64)), "batch zoom scratch");
+  BHIP(dev_malloc((void **)&b->d_counter, sizeof(unsigned) * 64), "batch counters");
   if (!b->zjobs.empty()) {
-    BHIP(hipMalloc(&b->d_zjobs, sizeof(ZoomJob) * b->zjobs.size()), "batch zoom jobs");
+    BHIP(dev_malloc((void **)&b->d_zjobs, sizeof(ZoomJob) * b->zjobs.size()), "batch zoom jobs");
     BHIP(hipMemcpy(b->d_zjobs, b->zjobs.data(), sizeof(ZoomJob) * b->zjobs.size(), hipMemcpyHostToDevice),
          "batch upload");
-    BHIP(hipMalloc(&b->d_ztiles, sizeof(ZoomTile) * b->ztiles.size()), "batch zoom tiles");
+    BHIP(dev_malloc((void **)&b->d_ztiles, sizeof(ZoomTile) * b->ztiles.size()), "batch zoom tiles");
     BHIP(hipMemcpy(b->d_ztiles, b->ztiles.data(), sizeof(ZoomTile) * b->ztiles.size(), hipMemcpyHostToDevice),
          "batch upload");
   }
@@ -806,14 +818,14 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
        "batch upload");
   for (int c = 8; c <= 14; ++c) {
     const int64_t L = 1LL << c;
-    BHIP(hipMalloc(&b->d_tw[c], sizeof(float2) * L), "batch twiddles");
+    BHIP(dev_malloc((void **)&b->d_tw[c], sizeof(float2) * L), "batch twiddles");
     BHIP(build_twiddles((float2 *)b->d_tw[c], L, s), "batch twiddles");
   }
 
   // tables: chirps (one workgroup per job), V per FFT-length class in chunks
   {
     ScopedDev tj_buf;
-    BHIP(hipMalloc(&tj_buf.p, sizeof(TableJob) * tjobs.size()), "table jobs");
+    BHIP(dev_malloc((void **)&tj_buf.p, sizeof(TableJob) * tjobs.size()), "table jobs");
     TableJob *d_tj = (TableJob *)tj_buf.p;
     BHIP(hipMemcpy(d_tj, tjobs.data(), sizeof(TableJob) * tjobs.size(), hipMemcpyHostToDevice), "table jobs");
     hipLaunchKernelGGL(k_batch_chirps, dim3((unsigned)tjobs.size()), dim3(256), 0, s, (float2 *)b->d_arena, d_tj);
@@ -821,9 +833,9 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
     BHIP(hipStreamSynchronize(s), "chirp tables");
     const int64_t chunk_points = (int64_t)1 << 25;  // FP64 scratch: 2 x 512 MiB
     ScopedDev va_buf, vb_buf, chunk_buf;
-    BHIP(hipMalloc(&va_buf.p, sizeof(double2) * chunk_points), "V scratch");
-    BHIP(hipMalloc(&vb_buf.p, sizeof(double2) * chunk_points), "V scratch");
-    BHIP(hipMalloc(&chunk_buf.p, sizeof(TableJob) * tjobs.size()), "V jobs");
+    BHIP(dev_malloc((void **)&va_buf.p, sizeof(double2) * chunk_points), "V scratch");
+    BHIP(dev_malloc((void **)&vb_buf.p, sizeof(double2) * chunk_points), "V scratch");
+    BHIP(dev_malloc((void **)&chunk_buf.p, sizeof(TableJob) * tjobs.size()), "V jobs");
     double2 *va = (double2 *)va_buf.p, *vb = (double2 *)vb_buf.p;
     TableJob *d_chunk = (TableJob *)chunk_buf.p;
     for (int c = 8; c <= 14; ++c) {
@@ -857,7 +869,7 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
     }
     if (!ztjobs.empty()) {
       ScopedDev zt_buf;
-      BHIP(hipMalloc(&zt_buf.p, sizeof(ZoomTableJob) * ztjobs.size()), "zoom table jobs");
+      BHIP(dev_malloc((void **)&zt_buf.p, sizeof(ZoomTableJob) * ztjobs.size()), "zoom table jobs");
       ZoomTableJob *d_zt = (ZoomTableJob *)zt_buf.p;
       BHIP(hipMemcpy(d_zt, ztjobs.data(), sizeof(ZoomTableJob) * ztjobs.size(), hipMemcpyHostToDevice),
            "zoom table jobs");
@@ -905,6 +917,7 @@ tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *s
       float ms = 0.f;
       BHIP(hipEventElapsedTime(&ms, e0, e1), "autotune");
       b->tuned_ms[cand] = ms;
+      tz_log("batch autotune: topology %d, unit order %d: %.3f ms", b->topology, b->inner, ms);
       if (ms < b->tuned_ms[best]) best = cand;
     }
     (void)hipEventDestroy(e0);

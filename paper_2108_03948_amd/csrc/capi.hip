@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -58,7 +59,7 @@ struct DevMem {
       (void)hipFree(p);
       p = nullptr;
     }
-    return hipMalloc(&p, bytes ? bytes : 16);
+    return dev_malloc(&p, bytes ? bytes : 16);
   }
   template <class T>
   T *as() const { return (T *)p; }
@@ -106,14 +107,18 @@ struct PadPlan {
   int64_t N, Nfft;
   int F, P;
   int realF = 0, realP = 0;  // whole-spectrum real-input kernel (N_fft = 2 realP realF)
+  bool mixed = false;        // 7-smooth N_fft: mixed-radix FFT of the zero-padded row
+  MixPlan mix{};
   std::shared_ptr<BluePlan> blue;  // Nfft with no fast factorisation
 };
+
 
 struct Device {
   // shared: an explicit plan (tz_plan_create) keeps the tables it uses alive
   // past tz_release_plans()
   std::map<int64_t, std::shared_ptr<DevMem>> twiddles;  // L -> e^{-j 2 pi m/L}
   std::map<int64_t, std::shared_ptr<DevMem>> roots;     // Nfft -> e^{-j 2 pi m/Nfft}
+  std::map<int64_t, std::shared_ptr<DevMem>> mixtw;     // L -> per-pass twiddles of the mixed-radix FFT
   std::map<std::string, std::shared_ptr<BluePlan>> blue;
   std::map<std::string, std::shared_ptr<ZoomPlan>> zoom;
   std::map<std::string, std::shared_ptr<PadPlan>> pad;
@@ -176,6 +181,21 @@ tz_status get_roots(Device &d, int64_t Nfft, hipStream_t s, const float2 **out, 
   return TZ_OK;
 }
 
+// per-pass twiddle tables of a mixed-radix length, cached like the other tables
+tz_status get_mix_twiddles(Device &d, const MixPlan &pl, hipStream_t s, const float2 **out, Keep *keep) {
+  auto &slot = d.mixtw[pl.L];
+  if (!slot) {
+    auto m = std::make_shared<DevMem>();
+    TZ_HIP(m->alloc(sizeof(float2) * (size_t)std::max(pl.ntw, 1)), "mixed-radix twiddles");
+    TZ_HIP(build_mix_twiddles(m->as<float2>(), pl, s), "mixed-radix twiddles");
+    TZ_HIP(hipStreamSynchronize(s), "mixed-radix twiddles");
+    slot = m;
+  }
+  *out = slot->as<float2>();
+  if (keep) keep->push_back(slot);
+  return TZ_OK;
+}
+
 // Shape of a Bluestein plan: 1 = single-pass workgroup FFTs (with bin blocks
 // and input segments when N + M - 1 > 16384), 0 = four-step long path of
 // length *Llong, -1 = too long for either.  The long path is taken when the
@@ -228,6 +248,12 @@ tz_status get_blue(Device &d, int64_t N, int64_t M, const PhaseParams &p, hipStr
   if (seg < 0)
     return fail(TZ_EUNSUPPORTED, "N=%lld, M=%lld: N + M - 1 exceeds the longest FFT (2^24)", (long long)N,
                 (long long)M);
+  if (seg == 0)
+    tz_log("czt plan N=%lld M=%lld: four-step L=%lld = %d x %lld", (long long)N, (long long)M, (long long)Llong,
+           L1, (long long)(Llong / L1));
+  else
+    tz_log("czt plan N=%lld M=%lld: single-pass L=%d, %d segment(s) of %lld samples, %d block(s) of %lld bins",
+           (long long)N, (long long)M, pl->L, pl->nseg, (long long)pl->Ns, pl->nblk, (long long)pl->Mb);
   if (seg == 0) {
     pl->L = (int)Llong;
     pl->L1 = L1;
@@ -632,6 +658,31 @@ void reduce(__int128 &n, __int128 &d) {
 
 void set_last_error(const char *msg) { g_err = msg; }
 
+bool fault_injected(const char *what) {
+  const char *f = getenv("TZ_FAULT");
+  return f && strstr(f, what);
+}
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+  if (fault_injected("alloc")) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s) {
+  if (fault_injected("alloc")) return hipErrorOutOfMemory;
+  return hipMallocAsync(p, bytes, s);
+}
+
+void tz_log(const char *fmt, ...) {
+  if (!getenv("TZ_LOG")) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  fprintf(stderr, "thzspec: %s\n", buf);
+}
+
 PhaseParams band_phase(int64_t fs_hz, int64_t f1_hz, int64_t f2_hz, int64_t M) {
   __int128 na = f1_hz % fs_hz, da = fs_hz;
   __int128 nw = f2_hz - f1_hz, dw = (__int128)M * fs_hz;
@@ -708,7 +759,18 @@ tz_status get_pad(Device &d, int64_t N, int64_t nfft, hipStream_t s, std::shared
         pl->P = (int)(nfft / F);
         break;
       }
-    if (!pl->F) {  // no power-of-two factor >= N: evaluate the same bins as a CZT
+    if (!pl->realF && !pl->F) pl->mixed = mix_plan(nfft, &pl->mix);
+    if (pl->realF)
+      tz_log("fft_zeropad plan N=%lld N_fft=%lld: real-input kernel, %d FFTs of %d", (long long)N, (long long)nfft,
+             pl->realP, pl->realF);
+    else if (pl->F)
+      tz_log("fft_zeropad plan N=%lld N_fft=%lld: %d FFTs of %d", (long long)N, (long long)nfft, pl->P, pl->F);
+    else if (pl->mixed)
+      tz_log("fft_zeropad plan N=%lld N_fft=%lld: mixed radix, %d passes", (long long)N, (long long)nfft,
+             pl->mix.npass);
+    else
+      tz_log("fft_zeropad plan N=%lld N_fft=%lld: Bluestein", (long long)N, (long long)nfft);
+    if (!pl->F && !pl->mixed) {  // no fast factorisation: evaluate the same bins as a CZT
       PhaseParams p{};
       p.rational = 1;
       p.q = nfft;
@@ -740,6 +802,10 @@ tz_status prepare_pad(Device &d, const std::shared_ptr<PadPlan> &pp, int in_kind
   e->nout = half ? pp->Nfft / 2 + 1 : pp->Nfft;
   if (pp->blue) return prepare_blue(d, pp->blue, in_kind, c, s, &e->b, keep);
   tz_status st;
+  if (pp->mixed) {
+    if (c.B > INT32_MAX) return fail(TZ_EUNSUPPORTED, "more than 2^31 - 1 traces for N_fft = %lld", (long long)pp->Nfft);
+    return get_mix_twiddles(d, pp->mix, s, &e->root, keep);
+  }
   if (pp->realF) {
     if ((st = get_twiddles(d, pp->realF, s, &e->tw, keep))) return st;
     if ((st = get_roots(d, pp->Nfft / 2, s, &e->rh, keep))) return st;
@@ -754,6 +820,22 @@ tz_status exec_pad(const PadExec &e, const void *x, int in_kind, void *X, const 
   const PadPlan &pp = *e.pp;
   // a Bluestein plan evaluates all Nfft bins; with TZ_HALF only the first nout
   if (pp.blue) return exec_blue(e.b, x, in_kind, X, c, e.nout, ws, s);
+  if (pp.mixed) {
+    MixLaunch a;
+    a.mode = in_kind;
+    a.x = x;
+    a.xs = c.xs;
+    a.N = pp.N;
+    a.X = (float2 *)X;
+    a.os = c.os;
+    a.nout = e.nout;
+    a.plan = pp.mix;
+    a.tw = e.root;
+    a.scale = 1.0f;
+    a.B = c.B;
+    TZ_HIP(launch_fft_mixed(a, s), "fft_zeropad (mixed radix) launch");
+    return TZ_OK;
+  }
   if (pp.realF) {
     PadRealLaunch a;
     a.x = x;
@@ -920,7 +1002,9 @@ tz_status check_ifft(Common *c) {
 // Bluestein form (A = 1, W = e^{+j 2 pi / N}, 1/N in the chirp spectrum)
 struct IfftExec {
   int64_t N = 0;
-  bool direct = false;
+  bool direct = false;  // power of two, k_ifft_pow2
+  bool mixed = false;   // 7-smooth, mixed-radix FFT
+  MixPlan mix{};
   const float2 *tw = nullptr;
   BlueExec b;
 };
@@ -931,6 +1015,10 @@ tz_status prepare_ifft(Device &d, int64_t N, const Common &c, hipStream_t s, Iff
     e->direct = true;
     return get_twiddles(d, N, s, &e->tw, keep);
   }
+  if (c.B <= INT32_MAX && mix_plan(N, &e->mix)) {
+    e->mixed = true;
+    return get_mix_twiddles(d, e->mix, s, &e->tw, keep);
+  }
   std::shared_ptr<BluePlan> pl;
   tz_status st = get_blue(d, N, N, idft_phase(N), s, &pl, true);
   if (st) return st;
@@ -938,6 +1026,22 @@ tz_status prepare_ifft(Device &d, int64_t N, const Common &c, hipStream_t s, Iff
 }
 
 tz_status exec_ifft(const IfftExec &e, const void *X, void *x, const Common &c, void *ws, hipStream_t s) {
+  if (e.mixed) {
+    MixLaunch a;
+    a.mode = 2;
+    a.x = X;
+    a.xs = c.xs;
+    a.N = e.N;
+    a.X = (float2 *)x;
+    a.os = c.os;
+    a.nout = e.N;
+    a.plan = e.mix;
+    a.tw = e.tw;
+    a.scale = (float)(1.0 / (double)e.N);
+    a.B = c.B;
+    TZ_HIP(launch_fft_mixed(a, s), "ifft (mixed radix) launch");
+    return TZ_OK;
+  }
   if (!e.direct) return exec_blue(e.b, X, c.in_kind, x, c, e.N, ws, s);
   IfftLaunch a;
   a.X = (const float2 *)X;
@@ -964,7 +1068,7 @@ tz_status ifft(const void *X, int64_t N, void *x, const tz_opts *o) {
   IfftExec e;
   if ((st = prepare_ifft(d, N, c, c.stream, &e))) return st;
   void *ws = nullptr;
-  if (!e.direct && e.b.ws && (st = e.b.pl->work.get(c.stream, e.b.ws, &ws))) return st;
+  if (!e.direct && !e.mixed && e.b.ws && (st = e.b.pl->work.get(c.stream, e.b.ws, &ws))) return st;
   return exec_ifft(e, X, x, c, ws, c.stream);
 }
 

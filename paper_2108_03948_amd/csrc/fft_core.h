@@ -167,6 +167,53 @@ struct Dft<5> {
   }
 };
 
+// 3-point DFT: with t = x1 + x2, u = x1 - x2,
+//   X0 = x0 + t,  X1,2 = x0 - t/2 -/+ j (sqrt(3)/2) u
+template <>
+struct Dft<3> {
+  template <int S>
+  __device__ __forceinline__ static void run(float2 *v) {
+    constexpr float h = (float)0.86602540378443864676;  // sqrt(3)/2
+    const float2 x0 = v[0];
+    const float2 t = cadd(v[S], v[2 * S]), u = csub(v[S], v[2 * S]);
+    const float2 m = make_float2(fmaf(-0.5f, t.x, x0.x), fmaf(-0.5f, t.y, x0.y));
+    // -j h u = (h u.y, -h u.x)
+    const float2 b = make_float2(h * u.y, -h * u.x);
+    v[0] = cadd(x0, t);
+    v[S] = cadd(m, b);
+    v[2 * S] = csub(m, b);
+  }
+};
+
+// 7-point DFT over the symmetric pairs t_m = x_m + x_{7-m}, u_m = x_m - x_{7-m}
+// (m = 1, 2, 3):  X_k, X_{7-k} = x0 + sum_m c_{km} t_m -/+ j sum_m s_{km} u_m,
+// c_{km} = cos(2 pi k m / 7), s_{km} = sin(2 pi k m / 7)
+template <>
+struct Dft<7> {
+  template <int K, int S>
+  __device__ __forceinline__ static void out(float2 *v, float2 x0, const float2 (&t)[3], const float2 (&u)[3]) {
+    constexpr CS w1 = unit_root(K * 1, 7), w2 = unit_root(K * 2, 7), w3 = unit_root(K * 3, 7);
+    constexpr float c1 = (float)w1.c, c2 = (float)w2.c, c3 = (float)w3.c;
+    constexpr float s1 = (float)w1.s, s2 = (float)w2.s, s3 = (float)w3.s;
+    const float2 a = make_float2(fmaf(c3, t[2].x, fmaf(c2, t[1].x, fmaf(c1, t[0].x, x0.x))),
+                                 fmaf(c3, t[2].y, fmaf(c2, t[1].y, fmaf(c1, t[0].y, x0.y))));
+    const float2 bb = make_float2(fmaf(s3, u[2].x, fmaf(s2, u[1].x, s1 * u[0].x)),
+                                  fmaf(s3, u[2].y, fmaf(s2, u[1].y, s1 * u[0].y)));
+    v[K * S] = cadd(a, cmul_mj(bb));
+    v[(7 - K) * S] = csub(a, cmul_mj(bb));
+  }
+  template <int S>
+  __device__ __forceinline__ static void run(float2 *v) {
+    const float2 x0 = v[0];
+    const float2 t[3] = {cadd(v[S], v[6 * S]), cadd(v[2 * S], v[5 * S]), cadd(v[3 * S], v[4 * S])};
+    const float2 u[3] = {csub(v[S], v[6 * S]), csub(v[2 * S], v[5 * S]), csub(v[3 * S], v[4 * S])};
+    out<1, S>(v, x0, t, u);
+    out<2, S>(v, x0, t, u);
+    out<3, S>(v, x0, t, u);
+    v[0] = cadd(x0, cadd(t[0], cadd(t[1], t[2])));
+  }
+};
+
 // Generic R = R1 * R2 (R1 = 4 when possible, else 2), decimation in time by
 // index mapping: X[k1 + R1 k2] = sum_{n2} W_R2^{n2 k2} W_R^{n2 k1}
 //                                 sum_{n1} v[R2 n1 + n2] W_R1^{n1 k1}.
@@ -368,6 +415,11 @@ __device__ __forceinline__ void apply_twiddles(float2 *v, const TwLds &tw, unsig
 __device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
 template <int L>
 constexpr int lds_points() { return L + L / 16; }
+// lds_idx(i + d) - lds_idx(i) for a compile-time d when it does not depend
+// on i: d a multiple of 16 (d + d/16), or i mod 16 + d staying below 16 for
+// every i the caller passes (d).  Padded addresses of a butterfly's points
+// are then one base and immediate offsets.
+constexpr int lds_step16(int d) { return d + d / 16; }
 
 // register slot of element e (point t + NT*e) in the layout of a radix-R pass
 template <int E, int R>
@@ -414,20 +466,33 @@ struct Fft {
       constexpr int R2 = Plan::list[p + 1];
       constexpr int NB2 = E / R2;
       __syncthreads();  // previous readers of LDS are done
+      // the outputs of a butterfly sit NS apart from base: when NS is a
+      // multiple of 16, or the R outputs stay inside one aligned run of
+      // NS R <= 16 points (base mod NS R = j mod NS), their padded addresses
+      // are lds_idx(base) plus a compile-time offset
+      constexpr bool kLin = NS % 16 == 0 || (NS * R <= 16 && 16 % (NS * R) == 0);
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int j = t + i * NT;
         const int base = (j / NS) * NS * R + (j % NS);
+        if constexpr (kLin) {
+          float2 *pb = lds + lds_idx(base);
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lds_idx(base + r * NS)] = v[i * R + r];
+          for (int r = 0; r < R; ++r) pb[NS % 16 == 0 ? lds_step16(r * NS) : r * NS] = v[i * R + r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds[lds_idx(base + r * NS)] = v[i * R + r];
+        }
       }
       __syncthreads();
+      // inputs t + i NT + r L/R2: NT and L/R2 are multiples of 16, so every
+      // padded address is lds_idx(t) plus a compile-time offset
+      static_assert(NT % 16 == 0 && (L / R2) % 16 == 0, "read offsets must be multiples of 16");
+      const float2 *pt = lds + lds_idx(t);
 #pragma unroll
-      for (int i = 0; i < NB2; ++i) {
-        const int j = t + i * NT;
+      for (int i = 0; i < NB2; ++i)
 #pragma unroll
-        for (int r = 0; r < R2; ++r) v[i * R2 + r] = lds[lds_idx(j + r * (L / R2))];
-      }
+        for (int r = 0; r < R2; ++r) v[i * R2 + r] = pt[lds_step16(i * NT + r * (L / R2))];
     }
   }
 
@@ -549,7 +614,17 @@ struct WaveFft {
     constexpr int NS = ns_before(p);
     const int j = lane + i * NT;
     const int base = (j / NS) * NS * R + (j % NS) - h * HALF;
-    ((out_upper<p, i, rs>() == (h == 1) ? (void)(win[lds_idx(base + rs * NS)] = v[i * R + rs]) : (void)0), ...);
+    // as in Fft::pass: one padded base and compile-time offsets when the
+    // outputs' spacing allows it (HALF is a multiple of 16)
+    constexpr bool kLin = NS % 16 == 0 || (NS * R <= 16 && 16 % (NS * R) == 0);
+    if constexpr (kLin) {
+      float2 *pb = win + lds_idx(base);
+      ((out_upper<p, i, rs>() == (h == 1) ? (void)(pb[NS % 16 == 0 ? lds_step16(rs * NS) : rs * NS] = v[i * R + rs])
+                                          : (void)0),
+       ...);
+    } else {
+      ((out_upper<p, i, rs>() == (h == 1) ? (void)(win[lds_idx(base + rs * NS)] = v[i * R + rs]) : (void)0), ...);
+    }
   }
   template <int p, int h, int... is>
   __device__ __forceinline__ static void write_half(const float2 (&v)[E], float2 *win, int lane,
@@ -571,12 +646,14 @@ struct WaveFft {
     wave_sync();
     write_half<p, h>(v, win, lane, std::make_integer_sequence<int, NB>{});
     wave_sync();
+    // lane + i NT + r F/R2 - h HALF: every offset from lane is a multiple
+    // of 16, so the padded addresses are lds_idx(lane) plus constants
+    const float2 *pl = win + lds_idx(lane);
 #pragma unroll
     for (int i = 0; i < NB2; ++i) {
-      const int j = lane + i * NT;
 #pragma unroll
       for (int r = h * (R2 / PARTS); r < (h + 1) * (R2 / PARTS); ++r)
-        nv[i * R2 + r] = win[lds_idx(j + r * (F / R2) - h * HALF)];
+        nv[i * R2 + r] = pl[lds_step16(i * NT + r * (F / R2) - h * HALF)];
     }
   }
 

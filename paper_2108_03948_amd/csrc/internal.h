@@ -187,6 +187,35 @@ struct LongLaunch {
 bool long_shape(int64_t L, int *L1);
 hipError_t launch_czt_long(const LongLaunch &a, hipStream_t s);
 
+// ---- mixed-radix FFT of 7-smooth length, one row per workgroup (mixed.hip) ----
+constexpr int kMixMinL = 8;
+constexpr int kMixMaxL = 20480;  // the whole row in 160 KB of LDS
+constexpr int kMixMaxPasses = 16;
+struct MixPlan {
+  int L, npass;
+  int R[kMixMaxPasses];   // radix of each pass (2, 3, 4, 5, 7, 8), first pass first
+  int NS[kMixMaxPasses];  // product of the earlier radices
+  int TO[kMixMaxPasses];  // offset of the pass's twiddle table, (R - 1) NS entries
+  uint32_t nsm[kMixMaxPasses];  // ceil(2^32 / NS) for the division j / NS
+  int ntw;                // twiddle entries of all passes
+};
+// radices of a 7-smooth L in [kMixMinL, kMixMaxL]; false otherwise
+bool mix_plan(int64_t L, MixPlan *pl);
+// the per-pass twiddle tables of pl (pl.ntw float2), built in FP64
+hipError_t build_mix_twiddles(float2 *twp, const MixPlan &pl, hipStream_t s);
+struct MixLaunch {
+  int mode;  // 0: real f32 rows, 1: real f64 rows (zero-padded FFT); 2: complex rows, inverse DFT
+  const void *x;
+  int64_t xs, N;  // row stride (elements), samples per row (modes 0, 1)
+  float2 *X;
+  int64_t os, nout;  // output row stride, outputs written per row
+  MixPlan plan;
+  const float2 *tw;  // per-pass twiddle tables (build_mix_twiddles)
+  float scale;       // mode 2: 1/L
+  int64_t B;
+};
+hipError_t launch_fft_mixed(const MixLaunch &a, hipStream_t s);
+
 // ---- direct inverse DFT of power-of-two length (ifft.hip) ----
 struct IfftLaunch {
   const float2 *X;   // B rows of L complex, xs apart
@@ -260,5 +289,17 @@ bool fft_length_supported(int64_t L);
 
 // message returned by tz_last_error() on this thread
 void set_last_error(const char *msg);
+
+// Fault injection for tests of the error paths, read from the environment at
+// every check: TZ_FAULT containing "alloc" makes each device allocation of
+// the library fail as out of memory (before hipMalloc is called), "graph"
+// makes the uneven batch's graph instantiation fail.
+bool fault_injected(const char *what);
+// hipMalloc / hipMallocAsync through the allocation fault check
+hipError_t dev_malloc(void **p, size_t bytes);
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s);
+// One line on stderr, prefixed "thzspec: ", when TZ_LOG is set (plan shapes,
+// kernel paths, the batch's classes and schedule).
+void tz_log(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 
 }  // namespace tz

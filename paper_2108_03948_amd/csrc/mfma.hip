@@ -70,11 +70,22 @@ struct MfmaFft {
   static constexpr int Q = L / 16;           // stride between the inputs of a butterfly
   static_assert(L == 4096 || L == 8192 || L == 16384, "three radix-16 passes plus radix 1, 2 or 4");
 
-  // DFT-matrix operands of this lane: rows i = l%32, columns k = 8h + q;
-  // a1 multiplies Re x, a2 multiplies Im x (a?m used with NTERM = 3 only).
-  V a1h, a1m, a1l, a2h, a2m, a2l;
+  // DFT-matrix operands: for lane l, rows i = l%32, columns k = 8h + q; a1
+  // multiplies Re x, a2 multiplies Im x.  They are the same for every wave,
+  // so they live in LDS (NOPS vectors x 64 lanes, lane-contiguous, one
+  // conflict-free 16-byte read each) and are read right before each product
+  // instead of holding 16-24 registers through the whole transform.
+  static constexpr int NOPS = NTERM == 3 ? 6 : 4;  // a1h, a1l, a2h, a2l (+ a1m, a2m)
+  static constexpr int kOpsBytes = NOPS * 64 * 16;
+  const V *ops;
 
-  __device__ void init(int lane) {
+  // fill the operand table (the first wave of the workgroup); the caller
+  // synchronises the workgroup before the first transform
+  __device__ void init(void *lds_ops, int tid) {
+    ops = (const V *)lds_ops;
+    if (tid >= 64) return;
+    const int lane = tid;
+    V a1h, a1m, a1l, a2h, a2m, a2l;
     const int i = lane % 32, h = lane / 32;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -100,7 +111,21 @@ struct MfmaFft {
         a2l[q] = (S)(v2 - (float)h2);
       }
     }
+    V *o = (V *)lds_ops;
+    o[0 * 64 + lane] = a1h;
+    o[1 * 64 + lane] = a1l;
+    o[2 * 64 + lane] = a2h;
+    o[3 * 64 + lane] = a2l;
+    if constexpr (NTERM == 3) {
+      o[4 * 64 + lane] = a1m;
+      o[5 * 64 + lane] = a2m;
+    }
   }
+
+  // operand vector w of this lane; the index passes through an opaque zero
+  // so that the read stays next to its product rather than being hoisted
+  // and kept in registers
+  __device__ __forceinline__ V op(int w, int lane) const { return ops[w * 64 + lane + (int)opaque_zero()]; }
 
   // y = F16 x for this lane's butterfly: x[q] are inputs 8h+q, results are
   // outputs out_k(h, c), c < 8
@@ -121,6 +146,7 @@ struct MfmaFft {
       down = ldexpf(1.f, -sh);
     }
     float16v c = {};
+    const int lane = (int)(__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)));
     if constexpr (NTERM == 2) {
       V brh, brl, bih, bil;
 #pragma unroll
@@ -132,39 +158,51 @@ struct MfmaFft {
         bih[q] = hi;
         bil[q] = (S)(xi - (float)hi);
       }
+      const V a1h = op(0, lane), a1l = op(1, lane);
       c = SP::mfma(a1h, brh, c);
       c = SP::mfma(a1h, brl, c);
       c = SP::mfma(a1l, brh, c);
+      const V a2h = op(2, lane), a2l = op(3, lane);
       c = SP::mfma(a2h, bih, c);
       c = SP::mfma(a2h, bil, c);
       c = SP::mfma(a2l, bih, c);
     } else {
-      V brh, brm, brl, bih, bim, bil;
+      // the real parts' three operand vectors and their six products first,
+      // then the imaginary parts': 12 operand registers live instead of 24
+      auto split3 = [&](int comp, V &bh, V &bm, V &bl) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const float xr = kScale ? x[q].x * up : x[q].x, xi = kScale ? x[q].y * up : x[q].y;
-        const S hr = (S)xr, hi = (S)xi;
-        const float rr = xr - (float)hr, ri = xi - (float)hi;
-        const S mr = (S)rr, mi = (S)ri;
-        brh[q] = hr;
-        brm[q] = mr;
-        brl[q] = (S)(rr - (float)mr);
-        bih[q] = hi;
-        bim[q] = mi;
-        bil[q] = (S)(ri - (float)mi);
+        for (int q = 0; q < 8; ++q) {
+          const float xv = comp == 0 ? (kScale ? x[q].x * up : x[q].x) : (kScale ? x[q].y * up : x[q].y);
+          const S hv = (S)xv;
+          const float rv = xv - (float)hv;
+          const S mv = (S)rv;
+          bh[q] = hv;
+          bm[q] = mv;
+          bl[q] = (S)(rv - (float)mv);
+        }
+      };
+      {
+        V brh, brm, brl;
+        split3(0, brh, brm, brl);
+        const V a1h = op(0, lane), a1l = op(1, lane), a1m = op(4, lane);
+        c = SP::mfma(a1h, brh, c);
+        c = SP::mfma(a1h, brm, c);
+        c = SP::mfma(a1m, brh, c);
+        c = SP::mfma(a1h, brl, c);
+        c = SP::mfma(a1m, brm, c);
+        c = SP::mfma(a1l, brh, c);
       }
-      c = SP::mfma(a1h, brh, c);
-      c = SP::mfma(a1h, brm, c);
-      c = SP::mfma(a1m, brh, c);
-      c = SP::mfma(a1h, brl, c);
-      c = SP::mfma(a1m, brm, c);
-      c = SP::mfma(a1l, brh, c);
-      c = SP::mfma(a2h, bih, c);
-      c = SP::mfma(a2h, bim, c);
-      c = SP::mfma(a2m, bih, c);
-      c = SP::mfma(a2h, bil, c);
-      c = SP::mfma(a2m, bim, c);
-      c = SP::mfma(a2l, bih, c);
+      {
+        V bih, bim, bil;
+        split3(1, bih, bim, bil);
+        const V a2h = op(2, lane), a2l = op(3, lane), a2m = op(5, lane);
+        c = SP::mfma(a2h, bih, c);
+        c = SP::mfma(a2h, bim, c);
+        c = SP::mfma(a2m, bih, c);
+        c = SP::mfma(a2h, bil, c);
+        c = SP::mfma(a2m, bim, c);
+        c = SP::mfma(a2l, bih, c);
+      }
     }
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
@@ -232,7 +270,9 @@ struct MfmaFft {
   __device__ __forceinline__ void trailing(float2 (&v)[E], const TwLds &tw) const {
     if constexpr (RT > 1) {
       constexpr int NB = E / RT;
-      const int t = threadIdx.x;
+      // a fresh thread index: the twiddle addresses of this pass are formed
+      // here, not shared with (and held live from) the other transform's
+      const int t = (int)(threadIdx.x + opaque_zero());
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int j = t + i * NT;
@@ -260,11 +300,12 @@ __global__ void __launch_bounds__(L / 16, 4)
   constexpr int XB = KIND == 1 ? 8 : 4;
   __shared__ float2 lds[lds_points<L>()];
   __shared__ float2 twl[tw_lds_points<L>()];
+  __shared__ __attribute__((aligned(16))) char opl[MF::kOpsBytes];
   const int t = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64, h = lane / 32;
   const int64_t b = blockIdx.x;
   const TwLds twd = load_twiddles<L>(twl, tw, t, NT);
   MF mf;
-  mf.init(lane);
+  mf.init(opl, t);
   __syncthreads();
   const Rsrc rx = make_rsrc((const char *)x + b * xs * XB, (uint64_t)N * XB);
   const Rsrc rp = make_rsrc(c_pre, (uint64_t)N * 8);
@@ -342,6 +383,7 @@ __global__ void __launch_bounds__(L2 / 16, 4)
   constexpr int64_t L = (int64_t)L1 * L2;
   __shared__ float2 lds[lds_points<L2>()];
   __shared__ float2 twl[tw_lds_points<L2>()];
+  __shared__ __attribute__((aligned(16))) char opl[MF::kOpsBytes];
   const int t = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64, h = lane / 32;
   // rows of equal k1 (one V row) for the traces of the chunk run back to back
   const int64_t q = xcd_item(blockIdx.x, gridDim.x);
@@ -349,7 +391,7 @@ __global__ void __launch_bounds__(L2 / 16, 4)
   const int64_t b = q % nb;
   const TwLds twd = load_twiddles<L2>(twl, tw_row, t, NT);
   MF mf;
-  mf.init(lane);
+  mf.init(opl, t);
   __syncthreads();
   const Rsrc rz = make_rsrc(Z + b * L + (int64_t)k1 * L2, (uint64_t)L2 * 8);
   const Rsrc rv = make_rsrc(Vt + (int64_t)k1 * L2, (uint64_t)L2 * 8);

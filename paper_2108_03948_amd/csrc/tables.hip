@@ -209,8 +209,11 @@ hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, in
   hipLaunchKernelGGL(k_chirp_post, dim3(nblocks(Mb * nblk * nseg, 256)), dim3(256), 0, s, c_post, Ns,
                      nseg, Mb, nblk, p);
   double2 *a = nullptr, *b = nullptr;
-  if ((e = hipMallocAsync((void **)&a, sizeof(double2) * L, s)) != hipSuccess) return e;
-  if ((e = hipMallocAsync((void **)&b, sizeof(double2) * L, s)) != hipSuccess) return e;
+  if ((e = dev_malloc_async((void **)&a, sizeof(double2) * L, s)) != hipSuccess) return e;
+  if ((e = dev_malloc_async((void **)&b, sizeof(double2) * L, s)) != hipSuccess) {
+    hipFreeAsync(a, s);
+    return e;
+  }
   hipLaunchKernelGGL(k_chirp_conj, dim3(nblocks(L, 256)), dim3(256), 0, s, a, L, N, Mb, p);
   int rs[64];
   int np = radix_list(L, rs);
@@ -224,10 +227,10 @@ hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, in
   // V = FFT(v) / L (the 1/L of the inverse FFT folded in), times the output scale
   hipLaunchKernelGGL(k_to_float_scaled, dim3(nblocks(L, 256)), dim3(256), 0, s, a, V, L, p.out_scale / (double)L,
                      (int64_t)L1);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = hipGetLastError();
   hipFreeAsync(a, s);
   hipFreeAsync(b, s);
-  return hipGetLastError();
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t build_zoom_tables(double2 *g, int T, double nu_c, double nu_N, double2 *ph, int64_t LD,

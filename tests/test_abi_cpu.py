@@ -332,3 +332,56 @@ def test_batch_wait_and_extents_reject_null(tz):
     assert L.tz_batch_wait(None, 1.0) == tz.TZ_EINVAL
     assert "NULL" in L.tz_last_error().decode()
     assert tz.TZ_ETIMEOUT == 5
+
+
+def _no_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("passes stand-in device pointers: CPU only")
+
+
+def test_fault_injection_alloc_one_shot_and_batch(tz, monkeypatch):
+    """TZ_FAULT=alloc fails the first device allocation of a plan as out of
+    memory, before hipMalloc is called: the one-shot call and the batch return
+    TZ_ENOMEM with the allocation named (without the injection the same calls
+    on a machine with no GPU fail as TZ_EDEVICE instead)."""
+    _no_gpu()
+    L = tz.lib()
+    o = tz.tz_opts()
+    L.tz_opts_init(ctypes.byref(o))
+    fake_x, fake_X = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    monkeypatch.delenv("TZ_FAULT", raising=False)
+    L.tz_release_plans()
+    st, err = _raw(tz, L.fft_zeropad, fake_x, 100, 28, fake_X, ctypes.byref(o))
+    assert st == tz.TZ_EDEVICE, err
+    monkeypatch.setenv("TZ_FAULT", "alloc")
+    L.tz_release_plans()
+    st, err = _raw(tz, L.fft_zeropad, fake_x, 100, 28, fake_X, ctypes.byref(o))
+    assert st == tz.TZ_ENOMEM and "out of memory" in err, err
+    job = tz.tz_job(kind=0, fir_taps=0, N=300, M=40, D=1, fs_hz=20 * 10**12, f1_hz=2 * 10**11,
+                    f2_hz=25 * 10**11, in_offset=0, out_offset=0)
+    h = ctypes.c_void_p()
+    st, err = _raw(tz, L.tz_batch_create, ctypes.byref(job), 1, None, ctypes.byref(h))
+    assert st == tz.TZ_ENOMEM and "batch arena" in err and not h.value, err
+
+
+def test_log_names_plan_decisions():
+    """TZ_LOG=1 writes the library's plan decisions to stderr (here the
+    batch's work items, logged before its first allocation, which TZ_FAULT
+    makes fail so that no device is needed)."""
+    _no_gpu()
+    import subprocess
+    import sys
+    code = ("import ctypes, paper_2108_03948_amd as tz\n"
+            "L = tz.lib()\n"
+            "job = tz.tz_job(kind=1, fir_taps=0, N=3000, M=500, D=6, fs_hz=20 * 10**12, f1_hz=2 * 10**11, "
+            "f2_hz=25 * 10**11, in_offset=0, out_offset=0)\n"
+            "h = ctypes.c_void_p()\n"
+            "print(L.tz_batch_create(ctypes.byref(job), 1, None, ctypes.byref(h)))\n")
+    env = dict(os.environ, TZ_LOG="1", TZ_FAULT="alloc")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert r.stdout.strip().splitlines()[-1] == str(2), r.stdout + r.stderr   # TZ_ENOMEM
+    assert "thzspec: batch: 1 jobs (1 zoom, 2 front-end tiles), 1 work items in 1 units" in r.stderr, r.stderr
+    env.pop("TZ_LOG")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert "thzspec:" not in r.stderr

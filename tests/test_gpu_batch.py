@@ -204,3 +204,34 @@ def test_batch_bounded_wait_times_out_then_completes(tz, orc):
     X = Xd.cpu().numpy()
     check_jobs(orc, x_flat, offs, jobs, X, range(len(jobs)), np.random.default_rng(2))
     b.close()
+
+
+def test_batch_injected_faults_then_recovers(tz, orc, monkeypatch):
+    """TZ_FAULT=alloc: tz_batch_create fails at its first device allocation
+    (TZ_ENOMEM, everything allocated before it freed); TZ_FAULT=graph: the
+    first launch fails at graph instantiation (TZ_EDEVICE) before anything
+    is launched.  Without the fault the same batch then runs and matches the
+    oracle."""
+    import torch
+    x_flat, offs, meta = synth.uneven(B=5, seed=23, Nmin=500, Nmax=3000, Mmin=100, Mmax=800)
+    jobs, total = make_jobs(meta, offs)
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(x_flat).to(dev)
+    Xd = torch.full((total,), complex(3.0, 3.0), dtype=torch.complex64, device=dev)
+    say("case: batch with injected allocation and graph faults")
+    monkeypatch.setenv("TZ_FAULT", "alloc")
+    with pytest.raises(tz.ThzError) as e:
+        tz.Batch(jobs)
+    assert e.value.status == tz.TZ_ENOMEM
+    monkeypatch.setenv("TZ_FAULT", "graph")
+    b = tz.Batch(jobs)
+    with pytest.raises(tz.ThzError) as e:
+        b.launch(xd, Xd)
+    assert e.value.status == tz.TZ_EDEVICE and "injected" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool((Xd == complex(3.0, 3.0)).all().item()), "a failed launch wrote output"
+    monkeypatch.delenv("TZ_FAULT")
+    b.launch(xd, Xd)
+    torch.cuda.synchronize()
+    check_jobs(orc, x_flat, offs, jobs, Xd.cpu().numpy(), range(len(jobs)), np.random.default_rng(3))
+    b.close()

@@ -2,10 +2,12 @@
 
 The inverse transform closes the FFT convolution of eq. (12) and is timed on
 its own against the FFT in Section 4.  Power-of-two N from 256 to 16384 run
-as one FFT per row (conjugate, forward FFT, conjugate, scale); every other N
-runs as a CZT with A = 1, W = e^{+j 2 pi / N} and the 1/N folded into the
-chirp spectrum.  The cases cover both ends of the direct range, sizes just
-outside it, and every Bluestein shape: single pass (2N - 1 <= 16384), bin
+as one FFT per row (conjugate, forward FFT, conjugate, scale); other
+7-smooth N from 8 to 20480 as one mixed-radix FFT per row (radices 2, 3, 4,
+5, 7, 8; odd lengths included); every other N runs as a CZT with A = 1,
+W = e^{+j 2 pi / N} and the 1/N folded into the chirp spectrum.  The cases
+cover both ends of the direct range, sizes just outside it, both mixed-radix
+row kernels, and every Bluestein shape: single pass (2N - 1 <= 16384), bin
 blocks / input segments just past it, and the four-step path (2N - 1 up to a
 few times 2^17).  Rows are strided on both sides; large N are checked on
 sampled outputs.  A round trip through the zero-padded FFT must return the
@@ -41,7 +43,8 @@ def spectra(B, N, seed):
     return (rng.standard_normal((B, N)) + 1j * rng.standard_normal((B, N))).astype(np.complex64)
 
 
-@pytest.mark.parametrize("N", [1, 2, 7, 128, 256, 500, 1024, 4096, 8192, 8193, 12345, 16384, 65536, 100003])
+@pytest.mark.parametrize("N", [1, 2, 7, 128, 256, 500, 625, 1009, 1024, 1176, 2646, 3001, 4096, 6615, 8192, 8193,
+                               12345, 16384, 16807, 19683, 20000, 65536, 100003])
 def test_ifft_matches_oracle(tz, orc, N):
     import torch
     B = 3
@@ -52,7 +55,13 @@ def test_ifft_matches_oracle(tz, orc, N):
     Xbig[:, :N] = torch.from_numpy(X).to(dev)
     obig = torch.full((B, N + 5), complex(9.0, 9.0), dtype=torch.complex64, device=dev)
     direct = 256 <= N <= 16384 and N & (N - 1) == 0
-    say(f"case: ifft N={N} B={B} " + ("direct FFT" if direct else f"Bluestein (L, blocks) = {tz.czt_plan_shape(N, N)}"))
+    m = N
+    for f in (2, 3, 5, 7):
+        while m % f == 0:
+            m //= f
+    mixed = not direct and m == 1 and 8 <= N <= 20480
+    say(f"case: ifft N={N} B={B} " + ("direct FFT" if direct else "mixed radix" if mixed else
+                                      f"Bluestein (L, blocks) = {tz.czt_plan_shape(N, N)}"))
     tz.ifft(Xbig[:, :N], out=obig[:, :N])
     torch.cuda.synchronize()
     got = obig.cpu().numpy()

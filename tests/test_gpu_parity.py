@@ -171,6 +171,36 @@ def test_fft_zeropad_shapes(tz, dev, orc, N, nz, half):
     assert_close(F, orc.fft_zeropad(x.astype(np.float64), nz, bins), what=f"fft N={N} Nfft={nf}")
 
 
+# 7-smooth N_fft that no power-of-two factorisation covers: the mixed-radix
+# FFT (radices 2, 3, 4, 5, 7, 8) of the zero-padded row, both row kernels
+# (up to 2560 points and past it), odd lengths, f64 input and the half
+# spectrum
+@pytest.mark.parametrize("N,nfft,half,dtype", [
+    (500, 500, False, "float32"), (500, 1000, False, "float32"), (500, 588, True, "float32"),
+    (300, 625, False, "float64"), (500, 1176, False, "float32"), (500, 2500, True, "float32"),
+    (2000, 2646, False, "float32"), (500, 6615, False, "float32"), (4000, 10000, False, "float32"),
+    (500, 16807, False, "float32"), (500, 19683, True, "float32"), (500, 20000, False, "float64"),
+    (20000, 20000, False, "float32")])
+def test_fft_zeropad_mixed_radix(tz, dev, orc, N, nfft, half, dtype):
+    rng = np.random.default_rng(N + nfft)
+    x = rng.standard_normal((3, N)).astype(dtype)
+    nz = nfft - N
+    nout = nfft // 2 + 1 if half else nfft
+    say(f"case: fft_zeropad mixed radix N={N} N_fft={nfft} half={half} {dtype}")
+    full = torch_full(dev, (3, nout + 5))
+    tz.fft_zeropad(to_dev(x, dev), nz, half=half, out=full[:, :nout])
+    f = full.cpu().numpy()
+    assert np.all(f[:, nout:] == np.complex64(complex(7.0, -7.0))), "wrote past the row"
+    bins = np.arange(nout) if nout <= 4096 else \
+        np.unique(np.r_[0, 1, nout - 1, nout // 2, rng.integers(0, nout, 200)])
+    assert_close(f[:, bins], orc.fft_zeropad(x.astype(np.float64), nz, bins), what=f"fft mixed N={N} Nfft={nfft}")
+
+
+def torch_full(dev, shape):
+    import torch
+    return torch.full(shape, complex(7.0, -7.0), dtype=torch.complex64, device=dev)
+
+
 @pytest.mark.parametrize("N,M,D,T,band", [
     (1024, 1024, 8, 63, (0.1e12, 3.0e12)),
     (4096, 4096, 6, 63, (0.2e12, 2.5e12)),
