@@ -29,6 +29,9 @@ METRIC = "CZT outputs/s over batched THz traces; %HBM peak; MFMA vs FP32 at 1e-5
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# profiled durations of the dominant kernel over the timed steps of a
+# rocprofv3 run of this script (bench_profiles.py timed)
+PROFILED_FILE = os.path.join(ROOT, "profiles", "bench_batched8192x4096_fft_zeropad_timed.json")
 CSRC = os.path.join(ROOT, "paper_2108_03948_amd", "csrc")
 
 N_PAIRS, N, FS = 4096, 4096, 20e12
@@ -125,6 +128,140 @@ def _cpu_model():
     return "unknown"
 
 
+def _event_ms(stream, fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_single(tz, synth, oracle, dev, stream):
+    """One FP64 trace of 1024 samples at f_s = 20 THz: czt M = 1024 over
+    0.1 - 3.0 THz, fft_zeropad to 16384, zoom D = 8 with 63 taps; microseconds
+    per call (launch latency) and the relative L2 error of every bin."""
+    import numpy as np
+    import torch
+    x64 = synth.single_trace(N=1024).reshape(1, -1)
+    x = torch.from_numpy(x64).to(dev)
+    fs, f1, f2 = 20e12, 0.1e12, 3.0e12
+    W, A = tz.czt_band(fs, f1, f2, 1024)
+    Xc = torch.empty((1, 1024), dtype=torch.complex64, device=dev)
+    Xf = torch.empty((1, 16384), dtype=torch.complex64, device=dev)
+    Xz = torch.empty((1, 1024), dtype=torch.complex64, device=dev)
+    calls = {"czt": lambda: tz.czt(x, 1024, W, A, out=Xc, stream=stream),
+             "fft_zeropad": lambda: tz.fft_zeropad(x, 16384 - 1024, out=Xf, stream=stream),
+             "zoom_fft": lambda: tz.zoom_fft(x, fs, f1, f2, 1024, 8, taps=63, out=Xz, stream=stream)}
+    refs = {"czt": lambda: oracle.czt(x64, 1024, W, A),
+            "fft_zeropad": lambda: oracle.fft_zeropad(x64, 16384 - 1024),
+            "zoom_fft": lambda: oracle.zoom_fft(x64, fs, f1, f2, 1024, 8, taps=63)}
+    outs = {"czt": Xc, "fft_zeropad": Xf, "zoom_fft": Xz}
+    res = {}
+    for name, fn in calls.items():
+        us = _event_ms(stream, fn, 200) * 1e3
+        ref = refs[name]()
+        got = outs[name].cpu().numpy()
+        res[name] = {"us_per_call": us, "rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+    log("bench: single trace " + ", ".join(f"{k} {v['us_per_call']:.1f} us" for k, v in res.items()))
+    return res
+
+
+def bench_uneven(tz, synth, oracle, dev, stream, reps):
+    """The uneven batch: 20000 traces, N ~ U{512..16384}, own band and M ~
+    U{256..8192}, CZT / Zoom FFT 50/50, in one graph launch of the batch API.
+    Algorithmic bytes: every sample read once (4 B) and every bin written once
+    (8 B).  Sampled parity: 4 jobs against the FP64 oracle on 48 bins each."""
+    import numpy as np
+    import torch
+    t0 = time.time()
+    x_flat, offs, meta = synth.uneven(B=20000, seed=1003)
+    jobs, out = [], 0
+    for i, j in enumerate(meta):
+        jobs.append(dict(kind=j["kind"], N=j["N"], M=j["M"], D=j["D"], taps=j["taps"],
+                         fs_hz=int(round(j["fs"])), f1_hz=int(round(j["f1"])), f2_hz=int(round(j["f2"])),
+                         in_offset=int(offs[i]), out_offset=out))
+        out += j["M"]
+    log(f"bench: uneven batch of {len(jobs)} jobs generated in {time.time() - t0:.1f} s")
+    xd = torch.from_numpy(x_flat).to(dev)
+    Xd = torch.zeros(out, dtype=torch.complex64, device=dev)
+    b = tz.Batch(jobs)
+    b.launch(xd, Xd, stream=stream)  # first launch: the schedule autotuner
+    torch.cuda.synchronize()
+    ms = _event_ms(stream, lambda: b.launch(xd, Xd, stream=stream), reps)
+    nbytes = 4 * int(x_flat.size) + 8 * out
+    # FFT work of the shapes the batch runs: every bin block (x input
+    # segment) of a job is one Bluestein pair of length L, 2 x 5 L log2 L
+    # flops (zoom jobs: the short DFT on ceil(N/D) decimated samples)
+    flops = 0.0
+    for j in jobs:
+        n_in = j["N"] if j["kind"] == "czt" else -(-j["N"] // j["D"])
+        L, pieces = tz.czt_plan_shape(n_in, j["M"])
+        flops += pieces * 10.0 * L * np.log2(L)
+    X = Xd.cpu().numpy()
+    rng = np.random.default_rng(9)
+    worst = 0.0
+    for i in (0, 4999, 12345, 19999):
+        j = jobs[i]
+        x = x_flat[offs[i]:offs[i + 1]].astype(np.float64)
+        bins = np.unique(np.r_[0, j["M"] - 1, rng.integers(0, j["M"], 46)])
+        if j["kind"] == "czt":
+            ref = oracle.czt_band_exact(x, j["M"], j["fs_hz"], j["f1_hz"], j["f2_hz"], bins)[0]
+        else:
+            ref = oracle.zoom_fft(x, j["fs_hz"], j["f1_hz"], j["f2_hz"], j["M"], j["D"], taps=j["taps"],
+                                  bins=bins)[0]
+        got = X[j["out_offset"] + bins]
+        worst = max(worst, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    res = {"jobs": len(jobs), "samples": int(x_flat.size), "bins": out, "ms": ms, "bins_per_s": out / (ms * 1e-3),
+           "alg_bytes": nbytes, "alg_GBps": nbytes / (ms * 1e-3) / 1e9,
+           "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "fft_flops": flops,
+           "TFLOPs": flops / (ms * 1e-3) / 1e12, "fp32_frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+           "rel_l2_sampled": worst,
+           "schedule": b.describe()}
+    log(f"bench: uneven batch {ms:.3f} ms, {res['bins_per_s']:.3e} bins/s, {res['alg_GBps']:.0f} GB/s "
+        f"algorithmic, rel L2 {worst:.2e}")
+    b.close()
+    return res
+
+
+def bench_long(tz, synth, oracle, dev, stream, reps):
+    """Long scans: 256 traces x 2^20 samples at T_s = 0.01 ps; czt M = 2^18
+    over 0.05 - 0.10 THz with integer-hertz phases (FP32 and the two split
+    precisions) and the Zoom FFT with D = 64 and 255 taps.  Sampled parity:
+    one trace, 48 bins, against the FP64 oracle."""
+    import numpy as np
+    import torch
+    B, NL, ML, fs, f1, f2 = 256, 1 << 20, 1 << 18, 100 * 10**12, 5 * 10**10, 10**11
+    t0 = time.time()
+    xn = synth.echoes(B, NL)
+    log(f"bench: long scans generated in {time.time() - t0:.1f} s")
+    x = torch.from_numpy(xn).to(dev)
+    X = torch.empty((B, ML), dtype=torch.complex64, device=dev)
+    bins = np.unique(np.r_[0, ML - 1, np.random.default_rng(13).integers(0, ML, 46)])
+    ref_c = oracle.czt_band_exact(xn[77:78].astype(np.float64), ML, fs, f1, f2, bins)[0]
+    ref_z = oracle.zoom_fft(xn[77:78].astype(np.float64), fs, f1, f2, ML, 64, taps=255, bins=bins)[0]
+    res = {}
+    for prec in ("fp32", "split_fp16", "split_bf16"):
+        ms = _event_ms(stream, lambda: tz.czt_band_exact(x, ML, fs, f1, f2, out=X, precision=prec,
+                                                          stream=stream), reps)
+        got = X[77].cpu().numpy()[bins]
+        res["czt_" + prec] = {"ms": ms, "bins_per_s": B * ML / (ms * 1e-3),
+                              "rel_l2_sampled": float(np.linalg.norm(got - ref_c) / np.linalg.norm(ref_c))}
+    ms = _event_ms(stream, lambda: tz.zoom_fft(x, fs, f1, f2, ML, 64, taps=255, out=X, stream=stream), reps)
+    got = X[77].cpu().numpy()[bins]
+    res["zoom_fp32"] = {"ms": ms, "bins_per_s": B * ML / (ms * 1e-3),
+                        "rel_l2_sampled": float(np.linalg.norm(got - ref_z) / np.linalg.norm(ref_z))}
+    for k in ("czt_split_fp16", "czt_split_bf16"):
+        res[k]["speedup_vs_fp32"] = res["czt_fp32"]["ms"] / res[k]["ms"]
+    log("bench: long scans " + ", ".join(f"{k} {v['ms']:.3f} ms ({v['rel_l2_sampled']:.1e})" for k, v in res.items()))
+    del x, X
+    return res
+
+
 def bench_nd(tz, synth, oracle, dev, stream, reps):
     """Multi-dimensional CZT / Zoom FFT on THz images: 64 B-scans of 512
     pixels x 2048 samples (spatial band [-1/4, 1/4) cycles per pixel on 512
@@ -191,6 +328,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--step-only", action="store_true",
+                    help="skip the single-trace, uneven-batch and long-scan workloads")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -278,9 +417,23 @@ def main():
             traffic = t["kernels"][dom]["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
+    # the same kernel's average over the timed dispatches of the committed
+    # rocprofv3 run, if the sources still hash to the profiled ones
+    profiled = None
+    try:
+        t = json.load(open(PROFILED_FILE))
+        if t.get("source_hash") == kernel_source_hash() and t.get("kernel") == dom:
+            us = t["timed_average_us"]
+            profiled = {"avg_us": us, "median_us": t["timed_median_us"], "dispatches": t["timed_dispatches"],
+                        "achieved": dk["alg_bytes"] / (us * 1e-6) / 1e9,
+                        "frac": dk["alg_bytes"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                        "source": os.path.relpath(PROFILED_FILE, ROOT)}
+    except (OSError, ValueError, KeyError):
+        profiled = None
     if hbm_bound:
         roof = {"bound": "hbm", "achieved": dk["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["hbm_frac"], "traffic": traffic, "kernel": dom}
+                "frac": dk["hbm_frac"], "traffic": traffic, "kernel": dom,
+                "event_avg_us": dk["ms"] * 1e3, "profiled": profiled}
     else:
         roof = {"bound": "alu", "achieved": dk["TFLOPs"], "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": dk["fp32_frac"], "traffic": traffic, "kernel": dom}
@@ -360,6 +513,11 @@ def main():
     log(f"bench: ifft {ms_if:.3f} ms for {B} x {M}, {inverse['alg_GBps']:.0f} GB/s, rel L2 {ierr:.2e}")
 
     nd = bench_nd(tz, synth, oracle, dev, stream, max(3, args.steps // 4))
+    single = uneven = longs = None
+    if not args.step_only:
+        single = bench_single(tz, synth, oracle, dev, stream)
+        uneven = bench_uneven(tz, synth, oracle, dev, stream, max(5, args.steps // 2))
+        longs = bench_long(tz, synth, oracle, dev, stream, 5)
 
     out = {
         "metric": METRIC,
@@ -388,6 +546,9 @@ def main():
         "transfer": transfer,
         "ifft": inverse,
         "nd": nd,
+        "single_trace_1024_fp64": single,
+        "uneven_batch_20000": uneven,
+        "long_scans_256x2p20": longs,
         "czt_rel_l2_sampled": err,
     }
     if not args.no_cpu:

@@ -5,6 +5,7 @@
   python bench_profiles.py kernel-traffic <fetch_counter.csv> <write_counter.csv> <kernel_trace.csv>
          <calibration.json> <out.md> "<cmd>" <name-substring> ...
   python bench_profiles.py utilization <counter.csv> <out.md> "<cmd>" <name-substring> ...
+  python bench_profiles.py timed <kernel_trace.csv> <out.json> "<cmd>" <warmup> <steps>
 
 Byte counters are scaled by what the same counters read for the 1 GiB device
 copy that ``bench.py --calib-copy`` runs first (dispatch with the largest grid
@@ -129,8 +130,31 @@ def utilization(counter_csv, out, cmd, keys):
     open(out, "w").write("\n".join(lines) + "\n")
 
 
+def timed(trace_csv, out, cmd, warmup, steps, source_hash):
+    """Durations of the dominant kernel's dispatches in the timed steps of a
+    profiled bench.py run: the first `warmup` dispatches of the kernel (one
+    per warm-up step) are dropped, the next `steps` kept, so the average is
+    taken over the same launches the bench line's event timing covers."""
+    key, grid = KERNEL_KEYS["fft_zeropad"]
+    rows = [r for r in csv.DictReader(open(trace_csv)) if key in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+    if len(d) < warmup + steps:
+        raise SystemExit(f"{len(d)} dispatches of {key}, expected {warmup} warm-up + {steps} timed")
+    t = sorted(d[warmup:warmup + steps])
+    res = {"command": cmd, "source_hash": source_hash, "kernel": "fft_zeropad", "name": key,
+           "warmup_dispatches_us": d[:warmup], "timed_dispatches": steps,
+           "timed_average_us": sum(t) / len(t), "timed_median_us": t[len(t) // 2],
+           "timed_min_us": t[0], "timed_max_us": t[-1]}
+    json.dump(res, open(out, "w"), indent=1)
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "utilization":
+    if sys.argv[1] == "timed":
+        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+        import bench
+        timed(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]), bench.kernel_source_hash())
+    elif sys.argv[1] == "utilization":
         utilization(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:])
     elif sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])

@@ -53,6 +53,19 @@ def shapes(tz, df):
     return {"df_hz": df, "n_fft": nfft, "n_zeros": nfft - N, "M": M, "D": D, "K": K}
 
 
+def smooth7(n):
+    for f in (2, 3, 5, 7):
+        while n % f == 0:
+            n //= f
+    return n == 1
+
+
+def direct_ifft(n):
+    """ifft runs one FFT of length n (power of two 256..16384, or 7-smooth
+    8..20480 on the mixed-radix kernel) rather than the Bluestein form."""
+    return (256 <= n <= 16384 and n & (n - 1) == 0) or (8 <= n <= 20480 and smooth7(n))
+
+
 def theory(tz, s):
     """FFT work of each method: sum of L log2 L over the FFTs it runs."""
     def c(L):
@@ -60,8 +73,18 @@ def theory(tz, s):
     L_czt, _ = tz.czt_plan_shape(N, s["M"])
     LD = -(-N // s["D"])
     L_zoom, _ = tz.czt_plan_shape(LD, s["M"])
-    L_ifft, _ = tz.czt_plan_shape(s["n_fft"], s["n_fft"])
-    return {"fft": c(s["n_fft"]), "czt": 2 * c(L_czt), "zoom": 2 * c(L_zoom), "ifft": 2 * c(L_ifft)}
+    n = s["n_fft"]
+    L_ifft = n if direct_ifft(n) else tz.czt_plan_shape(n, n)[0]
+    return {"fft": c(n), "czt": 2 * c(L_czt), "zoom": 2 * c(L_zoom),
+            "ifft": c(L_ifft) * (1 if direct_ifft(n) else 2)}
+
+
+def pow2_neighbour(n):
+    """The power of two nearest to n in log scale, at least N."""
+    lo = 1 << int(math.floor(math.log2(n)))
+    hi = lo * 2
+    p = lo if math.log2(n) - math.log2(lo) <= math.log2(hi) - math.log2(n) else hi
+    return max(p, 1 << int(math.ceil(math.log2(N))))
 
 
 def main():
@@ -112,8 +135,14 @@ def main():
                                                   stream=stream), reps),
                 "ifft": timed(lambda: tz.ifft(Xf, out=Xi, stream=stream), reps),
             }
-            del Xf, Xc, Xz, Xi
-        row = dict(s, us=out, theory=theory(tz, s))
+            # the zero-padded FFT at the nearest power-of-two length, for the
+            # cost of a 7-smooth N_fft against it
+            n2 = pow2_neighbour(s["n_fft"])
+            X2 = torch.empty((x.shape[0], n2), dtype=torch.complex64, device=dev)
+            out[tag]["fft_pow2"] = timed(lambda: tz.fft_zeropad(x, n2 - N, out=X2, stream=stream), reps)
+            del Xf, Xc, Xz, Xi, X2
+        row = dict(s, us=out, theory=theory(tz, s), pow2=pow2_neighbour(s["n_fft"]),
+                   smooth7=smooth7(s["n_fft"]))
         rows.append(row)
         print(json.dumps(row), flush=True)
 
@@ -129,16 +158,22 @@ def main():
                  f"Command:\n\n    {cmd}\n",
                  f"N = {N} samples at f_s = {FS / 1e12:g} THz, band {F1 / 1e12:g}-{F2 / 1e12:g} THz, "
                  f"zoom {TAPS} taps; single trace ({args.reps} calls per point) and "
-                 f"{args.batch} traces; times in microseconds, rel = time / time at 20 GHz.", "",
-                 "| df (GHz) | N_fft | M | D | K | fft 1 | czt 1 | zoom 1 | ifft 1 | fft B | czt B | zoom B | "
-                 "ifft B | rel fft B | rel czt B | rel zoom B | rel ifft B | theory fft | theory czt | "
-                 "theory zoom | theory ifft |",
-                 "|" + "---|" * 21]
+                 f"{args.batch} traces; times in microseconds, rel = time / time at 20 GHz.  "
+                 "7s: N_fft is 7-smooth (mixed-radix FFT and IFFT); pow2: the nearest power-of-two "
+                 "N_fft, fft 2^k B its batched zero-padded FFT time; fft/2^k and ifft/fft are ratios of "
+                 "the batched times.", "",
+                 "| df (GHz) | N_fft | 7s | M | D | K | fft 1 | czt 1 | zoom 1 | ifft 1 | fft B | czt B | zoom B | "
+                 "ifft B | pow2 | fft 2^k B | fft/2^k | ifft/fft | rel fft B | rel czt B | rel zoom B | "
+                 "rel ifft B | theory fft | theory czt | theory zoom | theory ifft |",
+                 "|" + "---|" * 26]
         for r in rows:
             u1, ub, rb, th = r["us"]["single"], r["us"]["batch"], r["rel"]["batch"], r["rel_theory"]
-            lines.append(f"| {r['df_hz'] / 1e9:.1f} | {r['n_fft']} | {r['M']} | {r['D']} | {r['K']} | "
+            lines.append(f"| {r['df_hz'] / 1e9:.1f} | {r['n_fft']} | {'y' if r['smooth7'] else ''} | {r['M']} | "
+                         f"{r['D']} | {r['K']} | "
                          f"{u1['fft']:.1f} | {u1['czt']:.1f} | {u1['zoom']:.1f} | {u1['ifft']:.1f} | "
                          f"{ub['fft']:.1f} | {ub['czt']:.1f} | {ub['zoom']:.1f} | {ub['ifft']:.1f} | "
+                         f"{r['pow2']} | {ub['fft_pow2']:.1f} | {ub['fft'] / ub['fft_pow2']:.2f} | "
+                         f"{ub['ifft'] / ub['fft']:.2f} | "
                          f"{rb['fft']:.2f} | {rb['czt']:.2f} | {rb['zoom']:.2f} | {rb['ifft']:.2f} | "
                          f"{th['fft']:.2f} | {th['czt']:.2f} | {th['zoom']:.2f} | {th['ifft']:.2f} |")
         with open(args.out, "w") as f:
