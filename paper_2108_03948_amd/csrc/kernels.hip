@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(Fft<L>::NT, 4)
     k_czt(const void *__restrict__ x, int64_t xs, int64_t N, int64_t Ns, int nseg,
           const float2 *__restrict__ c_pre, const float2 *__restrict__ c_post,
           const float2 *__restrict__ V, const float2 *__restrict__ tw, float2 *__restrict__ X,
-          int64_t os, int64_t M, int64_t Mb, int nblk) {
+          int64_t os, int64_t M, int64_t Mb, int nblk, int64_t nitems) {
   using F = Fft<L>;
   constexpr int NT = F::NT, E = F::E;
   constexpr int XB = KIND == 1 ? 8 : (KIND == 2 ? 8 : 4);  // bytes per input sample
@@ -52,8 +52,14 @@ __global__ void __launch_bounds__(Fft<L>::NT, 4)
   __shared__ float2 lds[lds_points<L>()];
   __shared__ float2 twl[kHalf ? L / 2 : tw_lds_points<L>()];
   const unsigned t = threadIdx.x;
-  const int64_t b = blockIdx.x / nblk;
-  const int blk = blockIdx.x % nblk;
+  // With bin blocks every block of a trace reads the same samples: the grid
+  // (padded to a multiple of 8) is numbered so that the blocks of one trace
+  // run on one XCD and share its L2 instead of fetching the trace once per
+  // block from HBM.  Padding workgroups leave before any barrier.
+  const int64_t q = nblk > 1 ? xcd_item(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  if (q >= nitems) return;
+  const int64_t b = q / nblk;
+  const int blk = (int)(q % nblk);
   const int64_t k0 = (int64_t)blk * Mb;
   // a block wholly past the bins asked for (M below the plan's bin count)
   // has nothing to write: the whole workgroup leaves before any barrier
@@ -324,17 +330,31 @@ __global__ void __launch_bounds__(64 * P)
   // W_NU^j / 2: the 1/2 of the combine below rides on the input twiddle
   for (unsigned i = threadIdx.x; i < NU; i += NTH) rul[i] = cscale(root_h[64 * i], 0.5f);
 
-  // raw samples (x[2m], x[2m+1]) of trace tb in input-slot order
-  float2 v[E];
-  // (loaded at the top of each trace)
-  auto fetch = [&](int64_t tb, unsigned lane_) {
-    const Rsrc rx = make_rsrc((const char *)x + tb * xs * XB, (uint64_t)N * XB);
+  // The samples of the next trace are fetched cooperatively (SPT per thread)
+  // before the first store of the current one and parked in LDS once the
+  // current trace's combine no longer needs it.  Loads and stores retire in
+  // issue order on one counter, so a fetch issued after the stores (at the
+  // top of the next trace) would wait for all of them to drain before the
+  // next FFT could start; issued before them, it lets the next FFT run while
+  // they drain.
+  constexpr int SPT = 2 * F / NTH;
+  static_assert(SPT * NTH == 2 * F, "the trace must split evenly over the threads");
+  auto prefetch = [&](int64_t tb, unsigned tid_, float (&pre)[SPT]) {
+    const Rsrc rx = make_rsrc((const char *)x + tb * xs * XB, tb < B ? (uint64_t)N * XB : 0);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const unsigned m = lane_ + 64 * e;  // samples past N read as 0
-      v[FF::in_slot(e)] = make_float2(ld_real<KIND>(rx, 2 * m), ld_real<KIND>(rx, 2 * m + 1));
-    }
+    for (int j = 0; j < SPT; ++j) pre[j] = ld_real<KIND>(rx, tid_ + NTH * j);  // past N (or B): 0
   };
+  auto park = [&](const float (&pre)[SPT], unsigned tid_) {
+    float *xl = (float *)lds;  // samples 0 .. 2F-1 in the first F points of LDS
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) xl[tid_ + NTH * j] = pre[j];
+  };
+  {
+    float pre[SPT];
+    prefetch(blockIdx.x, threadIdx.x, pre);
+    park(pre, threadIdx.x);
+  }
+  float2 v[E];
 
   // the wave's first thread index, pinned in a scalar register (the empty
   // asm) for the whole kernel: no vector register carries a thread index
@@ -351,7 +371,10 @@ __global__ void __launch_bounds__(64 * P)
     // the wave index is wave-uniform: it and what derives from it only need
     // scalar registers
     const unsigned r = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
-    fetch(b, lane);
+    // (x[2m], x[2m+1]), m = lane + 64 e, from the samples parked in LDS
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[FF::in_slot(e)] = lds[lane + 64 * e];
+    __syncthreads();  // every wave holds its samples before the FFT windows reuse the space
     // z[m] W_Nh^{r m} / 2 with m = lane + 64 e: W_Nh^{r lane} W_NU^{r e} / 2
     {
       const float2 wl = rtd(r * lane);
@@ -361,6 +384,7 @@ __global__ void __launch_bounds__(64 * P)
     }
     FF::forward(v, lds + r * FF::window(), lane, twd);  // Z/2
 
+    float pre[SPT];  // the next trace's samples (fetched in phase 0, parked after phase 1)
     const Rsrc rX = make_rsrc(X + b * os, (uint64_t)(half ? NH + 1 : NF) * 8);
     using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(rX, 0, 0, 0));
     auto st2 = [&](unsigned voff, float2 a, float2 c) {
@@ -402,6 +426,7 @@ __global__ void __launch_bounds__(64 * P)
         }
       }
       __syncthreads();
+      if (ph == 1) prefetch(b + gridDim.x, tid + opaque_zero(), pre);
 
       // wave r takes pairs (k, k+1), k even, k = k0 + 128 it (it < IT):
       // phase 0: k0 = 2 r PPW + 2 lane (r < P/2), 3Q4 + 2 + 2 (r PPW - Q4/2) + 2 lane;
@@ -454,6 +479,8 @@ __global__ void __launch_bounds__(64 * P)
         if (!half) st2(8 * (NF - k), cconj(x0), cconj(xm));
       }
     }
+    __syncthreads();  // the combine's reads of the staged spectrum are done
+    park(pre, tid + opaque_zero());
   }  // traces
 }
 
@@ -809,13 +836,15 @@ bool fft_length_supported(int64_t L) {
 
 template <int L, int KIND>
 static void czt_dispatch_seg(const CztLaunch &a, hipStream_t s) {
-  const dim3 grid((unsigned)(a.B * a.nblk)), block(Fft<L>::NT);
+  const int64_t items = a.B * a.nblk;
+  // blocked plans: a multiple of 8 workgroups for the XCD-aware numbering
+  const dim3 grid((unsigned)(a.nblk > 1 ? (items + 7) / 8 * 8 : items)), block(Fft<L>::NT);
   if (a.nseg > 1)
     hipLaunchKernelGGL((k_czt<L, KIND, true>), grid, block, 0, s, a.x, a.xs, a.N, a.Ns, a.nseg,
-                       a.c_pre, a.c_post, a.V, a.tw, a.X, a.os, a.M, a.Mb, a.nblk);
+                       a.c_pre, a.c_post, a.V, a.tw, a.X, a.os, a.M, a.Mb, a.nblk, items);
   else
     hipLaunchKernelGGL((k_czt<L, KIND, false>), grid, block, 0, s, a.x, a.xs, a.N, a.Ns, a.nseg,
-                       a.c_pre, a.c_post, a.V, a.tw, a.X, a.os, a.M, a.Mb, a.nblk);
+                       a.c_pre, a.c_post, a.V, a.tw, a.X, a.os, a.M, a.Mb, a.nblk, items);
 }
 
 template <int L>
