@@ -11,6 +11,10 @@ Section 3.2; a synthetic pulse here) the plotting resolution df runs from
                63-tap low-pass; short DFT length K = round(M f_s / (D (f2 - f1)))
   ifft         the N_fft-point inverse DFT of the fft_zeropad spectrum back to
                N_fft time samples (the FFT/IFFT comparison of Section 4, Fig. 12)
+  fft / ifft   for 7-smooth N_fft (up to 20480): also the half spectrum, bins
+  half         0 .. N_fft/2 (fft_zeropad with TZ_HALF), and its inverse back
+               to the real trace (ifft with TZ_HALF), the pair a real THz
+               trace goes through
 
 Each method is timed (HIP events on the launch stream, plans built before the
 timed region) for one trace, as the paper does, and for a batch of 8192
@@ -135,6 +139,16 @@ def main():
                                                   stream=stream), reps),
                 "ifft": timed(lambda: tz.ifft(Xf, out=Xi, stream=stream), reps),
             }
+            if s["n_fft"] <= 20480 and smooth7(s["n_fft"]):
+                nh = s["n_fft"] // 2 + 1
+                Xh = torch.empty((x.shape[0], nh), dtype=torch.complex64, device=dev)
+                xr = torch.empty((x.shape[0], s["n_fft"]), dtype=torch.float32, device=dev)
+                tz.fft_zeropad(x, s["n_zeros"], half=True, out=Xh, stream=stream)
+                out[tag]["fft_half"] = timed(lambda: tz.fft_zeropad(x, s["n_zeros"], half=True, out=Xh,
+                                                                    stream=stream), reps)
+                out[tag]["ifft_half"] = timed(lambda: tz.ifft(Xh, half=True, N=s["n_fft"], out=xr,
+                                                              stream=stream), reps)
+                del Xh, xr
             # the zero-padded FFT at the nearest power-of-two length, for the
             # cost of a 7-smooth N_fft against it
             n2 = pow2_neighbour(s["n_fft"])
@@ -161,11 +175,13 @@ def main():
                  f"{args.batch} traces; times in microseconds, rel = time / time at 20 GHz.  "
                  "7s: N_fft is 7-smooth (mixed-radix FFT and IFFT); pow2: the nearest power-of-two "
                  "N_fft, fft 2^k B its batched zero-padded FFT time; fft/2^k and ifft/fft are ratios of "
-                 "the batched times.", "",
+                 "the batched times; fft h B / ifft h B: the half spectrum and its inverse to the real "
+                 "trace (7-smooth N_fft), ih/fh their ratio.", "",
                  "| df (GHz) | N_fft | 7s | M | D | K | fft 1 | czt 1 | zoom 1 | ifft 1 | fft B | czt B | zoom B | "
-                 "ifft B | pow2 | fft 2^k B | fft/2^k | ifft/fft | rel fft B | rel czt B | rel zoom B | "
+                 "ifft B | pow2 | fft 2^k B | fft/2^k | ifft/fft | fft h B | ifft h B | ih/fh | "
+                 "rel fft B | rel czt B | rel zoom B | "
                  "rel ifft B | theory fft | theory czt | theory zoom | theory ifft |",
-                 "|" + "---|" * 26]
+                 "|" + "---|" * 29]
         for r in rows:
             u1, ub, rb, th = r["us"]["single"], r["us"]["batch"], r["rel"]["batch"], r["rel_theory"]
             lines.append(f"| {r['df_hz'] / 1e9:.1f} | {r['n_fft']} | {'y' if r['smooth7'] else ''} | {r['M']} | "
@@ -174,6 +190,8 @@ def main():
                          f"{ub['fft']:.1f} | {ub['czt']:.1f} | {ub['zoom']:.1f} | {ub['ifft']:.1f} | "
                          f"{r['pow2']} | {ub['fft_pow2']:.1f} | {ub['fft'] / ub['fft_pow2']:.2f} | "
                          f"{ub['ifft'] / ub['fft']:.2f} | "
+                         + (f"{ub['fft_half']:.1f} | {ub['ifft_half']:.1f} | {ub['ifft_half'] / ub['fft_half']:.2f} | "
+                            if "fft_half" in ub else " |  |  | ") +
                          f"{rb['fft']:.2f} | {rb['czt']:.2f} | {rb['zoom']:.2f} | {rb['ifft']:.2f} | "
                          f"{th['fft']:.2f} | {th['czt']:.2f} | {th['zoom']:.2f} | {th['ifft']:.2f} |")
         with open(args.out, "w") as f:

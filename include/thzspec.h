@@ -66,7 +66,8 @@ enum { TZ_F32 = 0, TZ_F64 = 1 };
 enum { TZ_FP32 = 0, TZ_SPLIT_FP16 = 1, TZ_SPLIT_BF16 = 2 };
 /* flags */
 enum {
-    TZ_HALF = 1  /* fft_zeropad: write bins 0 .. N_fft/2 only (real input) */
+    TZ_HALF = 1  /* fft_zeropad: write bins 0 .. N_fft/2 only (real input);
+                    ifft: Hermitian half spectra in, real traces out */
 };
 /* job kinds for the uneven batch */
 enum { TZ_JOB_CZT = 0, TZ_JOB_ZOOM = 1 };
@@ -172,12 +173,22 @@ tz_status czt_transfer(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, 
  * out_stride complex elements apart (0 means N).  Both are device memory
  * owned by the caller; X is only read.  Power-of-two N from 256 to 16384
  * run as one FFT per row (conjugate, forward FFT, conjugate, exact 1/N);
- * any other N with 2N - 1 <= 2^24 as the CZT of eq. (11) with A = 1,
+ * other 7-smooth N from 8 to 20480 as one mixed-radix FFT per row; any
+ * other N with 2N - 1 <= 2^24 as the CZT of eq. (11) with A = 1,
  * W = e^{+j 2 pi / N} and exact integer chirp phases, the 1/N folded into
  * the plan's chirp spectrum.
+ * With TZ_HALF in opts->flags, X holds the Hermitian half spectra of real
+ * traces (the output of fft_zeropad with TZ_HALF): rows of N/2 + 1 complex64
+ * bins 0 .. N/2 (in_stride 0 means N/2 + 1), bin k > N/2 being
+ * conj(X[N - k]) and the imaginary parts of bin 0 and, for even N, bin N/2
+ * taken as 0; x receives B real rows of N float32 samples (out_stride float
+ * elements apart, 0 means N).  Two rows go through one complex mixed-radix
+ * FFT (x_a = Re, x_b = Im of the inverse of X_a + j X_b); N must be 7-smooth
+ * from 8 to 20480.
  * in_dtype must be TZ_F32 (the components of complex64).
- * Errors: TZ_EINVAL for NULL pointers, N < 1, strides below N, in_dtype
- * TZ_F64; TZ_EUNSUPPORTED for split precision or 2N - 1 > 2^24.
+ * Errors: TZ_EINVAL for NULL pointers, N < 1, strides below the row
+ * lengths, in_dtype TZ_F64; TZ_EUNSUPPORTED for split precision,
+ * 2N - 1 > 2^24, or TZ_HALF with N outside the 7-smooth range above.
  */
 tz_status ifft(const void *X, int64_t N, void *x, const tz_opts *opts);
 
@@ -386,6 +397,33 @@ tz_status tz_plan_execute_static(const tz_plan *plan, const void *x, void *X, vo
  * and K = zoom_short_length().  f_out holds one double per bin.  TZ_EINVAL
  * for TZ_PLAN_IFFT, whose outputs are time samples. */
 tz_status tz_bin_freqs(const tz_plan_params *params, const tz_opts *opts, double *f_out);
+
+/* ---------------------------------------------------------------------- */
+/* Autotuner.  tz_autotune() times one Bluestein FFT pair (eq. (15)) of    */
+/* every single-workgroup length 256 .. 16384 on the current device, on    */
+/* opts->stream (synchronising it), and makes plans created afterwards     */
+/* choose their FFT length and bin blocks from those times instead of the  */
+/* built-in cost table (any FFT length >= N + M - 1 gives the same bins,   */
+/* so only speed changes).  It allocates about 200 MB of device memory     */
+/* while it runs and drops the one-shot calls' cached plans; explicit      */
+/* plans keep their shape.  The uneven batch times its candidate schedules */
+/* at its first launch (tz_batch_launch).  Both results persist in a JSON  */
+/* file named by the environment variable TZ_TUNE_CACHE (default           */
+/* $XDG_CACHE_HOME/thzspec/tune.json, else $HOME/.cache/thzspec/tune.json; */
+/* "off" or an empty value disables reading and writing it), under the key */
+/* "<device architecture name>/<tz_version()>": a later process on the     */
+/* same architecture and library starts from them.  Entries under another  */
+/* key are kept but not used; a file that does not parse is ignored (the  */
+/* built-in defaults apply) and rewritten at the next save.  A file that   */
+/* cannot be written leaves the results in memory for this process only.   */
+/* Errors: TZ_EDEVICE / TZ_ENOMEM from the timing runs.                    */
+tz_status tz_autotune(const tz_opts *opts);
+/* One-line description of the tuning state: cache path and what loading   */
+/* or saving it did, the device key, the FFT-pair times in use (measured   */
+/* or built-in) and how many batch schedules are stored for this device.   */
+/* Writes at most len bytes (NUL-terminated) and returns the full length;  */
+/* needs no device (then device=none and the built-in costs).              */
+int64_t tz_tune_describe(char *buf, int64_t len);
 
 /* ---------------------------------------------------------------------- */
 const char *tz_last_error(void);   /* thread-local message of the last failure */

@@ -93,7 +93,7 @@ EXPORTS = (
     "tz_last_error", "tz_version",
     "tz_release_plans", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute", "tz_plan_execute_static",
     "tz_plan_destroy",
-    "tz_bin_freqs",
+    "tz_bin_freqs", "tz_autotune", "tz_tune_describe",
 )
 
 _lock = threading.Lock()
@@ -148,10 +148,13 @@ def lib() -> ctypes.CDLL:
         L.tz_plan_destroy.argtypes = [vp]
         L.tz_plan_destroy.restype = None
         L.tz_bin_freqs.argtypes = [pp, po, ctypes.POINTER(ctypes.c_double)]
+        L.tz_autotune.argtypes = [po]
+        L.tz_tune_describe.argtypes = [ctypes.c_char_p, i64]
+        L.tz_tune_describe.restype = i64
         for f in ("fft_zeropad", "czt", "czt_band_exact", "czt_transfer", "ifft", "zoom_fft", "czt_band",
                   "czt_plan_shape",
                   "tz_batch_create", "tz_batch_launch", "tz_batch_extents", "tz_batch_wait", "tz_plan_create", "tz_plan_workspace", "tz_plan_execute",
-                  "tz_plan_execute_static", "tz_bin_freqs"):
+                  "tz_plan_execute_static", "tz_bin_freqs", "tz_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         return L
@@ -168,6 +171,27 @@ def version() -> str:
 
 def release_plans():
     lib().tz_release_plans()
+
+
+def autotune(stream=None):
+    """Time one Bluestein FFT pair of every single-workgroup length on the
+    current device; later plans pick FFT lengths and bin blocks from these
+    times, which persist in the tune cache (TZ_TUNE_CACHE)."""
+    torch = _torch()
+    o = tz_opts()
+    lib().tz_opts_init(ctypes.byref(o))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    _check(lib().tz_autotune(ctypes.byref(o)))
+
+
+def tune_describe() -> str:
+    """Cache path, load/save outcome, device key and the FFT-pair costs in use."""
+    n = lib().tz_tune_describe(None, 0)
+    buf = ctypes.create_string_buffer(int(n) + 1)
+    lib().tz_tune_describe(buf, len(buf))
+    return buf.value.decode()
 
 
 # ---------------------------------------------------------------------------
@@ -247,9 +271,12 @@ def czt(x, M: int, W: complex, A: complex, *, out=None, precision="fp32", stream
     return out
 
 
-def ifft(X, *, out=None, stream=None):
+def ifft(X, *, out=None, stream=None, half=False, N=None):
     """x[n] = (1/N) sum_k X[k] exp(+j 2 pi k n / N) for each row of the
-    complex64 spectra X ([N] or [B, N]); returns [B, N] complex64."""
+    complex64 spectra X ([N] or [B, N]); returns [B, N] complex64.
+    half=True: X holds the Hermitian half spectra of real traces ([B, N/2 + 1]
+    bins, as fft_zeropad(..., half=True) writes them) and the result is the
+    real traces [B, N] float32; N (default 2 (bins - 1)) picks odd lengths."""
     torch = _torch()
     if not isinstance(X, torch.Tensor) or not X.is_cuda:
         raise TypeError("X must be a torch tensor on the GPU")
@@ -259,13 +286,24 @@ def ifft(X, *, out=None, stream=None):
         raise TypeError("X must be a complex64 tensor [N] or [B, N]")
     if X.stride(1) != 1:
         X = X.contiguous()
-    B, N = X.shape
-    out = _out(X, N, out)
+    B, nb = X.shape
+    if half:
+        N = int(N) if N is not None else 2 * (nb - 1)
+        if N // 2 + 1 != nb:
+            raise ValueError(f"{nb} bins are not the half spectrum of N = {N}")
+        if out is None:
+            out = torch.empty((B, N), dtype=torch.float32, device=X.device)
+        elif out.dtype != torch.float32 or not out.is_cuda or out.shape != (B, N) or out.stride(1) != 1:
+            raise ValueError("out must be a float32 GPU tensor [B, N] with unit inner stride")
+    else:
+        N = nb
+        out = _out(X, N, out)
     o = tz_opts()
     lib().tz_opts_init(ctypes.byref(o))
     o.batch = B
-    o.in_stride = X.stride(0) if B > 1 else N
+    o.in_stride = X.stride(0) if B > 1 else nb
     o.out_stride = out.stride(0)
+    o.flags = TZ_HALF if half else 0
     if stream is None:
         stream = torch.cuda.current_stream(X.device)
     o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
@@ -535,7 +573,8 @@ class Plan:
 
     kind: "fft_zeropad" (N, n_zeros, half), "czt" (N, M, W, A),
     "czt_band_exact" (N, M, fs_hz, f1_hz, f2_hz) or "zoom" (N, M, fs, f1, f2,
-    D, taps, cutoff_hz) or "ifft" (N: complex64 spectra in, N samples out);
+    D, taps, cutoff_hz) or "ifft" (N: complex64 spectra in, N samples out;
+    with half, N/2 + 1 Hermitian bins in and N float32 samples out);
     batch traces of dtype, rows in_stride / out_stride elements apart
     (0 = packed)."""
 
@@ -548,14 +587,19 @@ class Plan:
             stream = torch.cuda.current_stream()
         self.kind, self.N, self.batch = kind, int(N), int(batch)
         self.dtype = torch.float64 if str(dtype).endswith("float64") else torch.float32
+        self.out_dtype = torch.complex64
+        self.in_len = self.N
         if kind == "ifft":
             self.dtype = torch.complex64
             self.bins = int(N)
+            if half:
+                self.in_len = self.N // 2 + 1
+                self.out_dtype = torch.float32
         elif kind == "fft_zeropad":
             self.bins = N + n_zeros if not half else (N + n_zeros) // 2 + 1
         else:
             self.bins = int(M)
-        self.in_stride = int(in_stride) or self.N
+        self.in_stride = int(in_stride) or self.in_len
         self.out_stride = int(out_stride) or self.bins
         p = _plan_params(kind, N, M, n_zeros, W, A, fs, f1, f2, D, fs_hz, f1_hz, f2_hz)
         o = _plan_opts(batch, in_stride, out_stride, "float32" if kind == "ifft" else dtype, precision, half, taps,
@@ -569,10 +613,10 @@ class Plan:
 
     def _check_buffers(self, x, out):
         torch = _torch()
-        if not (x.is_cuda and out.is_cuda) or x.dtype != self.dtype or out.dtype != torch.complex64:
-            raise TypeError("x must be a GPU tensor of the plan's dtype and out a complex64 GPU tensor")
-        if x.shape[0] != self.batch or x.shape[-1] != self.N or out.shape != (self.batch, self.bins):
-            raise ValueError("x must be [batch, N] and out [batch, bins] of the plan")
+        if not (x.is_cuda and out.is_cuda) or x.dtype != self.dtype or out.dtype != self.out_dtype:
+            raise TypeError("x and out must be GPU tensors of the plan's input and output dtypes")
+        if x.shape[0] != self.batch or x.shape[-1] != self.in_len or out.shape != (self.batch, self.bins):
+            raise ValueError("x must be [batch, N] (ifft half: N/2 + 1) and out [batch, bins] of the plan")
         if self.batch > 1 and (x.stride(0) != self.in_stride or out.stride(0) != self.out_stride):
             raise ValueError("row strides must be the plan's in_stride / out_stride")
         if x.stride(-1) != 1 or out.stride(-1) != 1:

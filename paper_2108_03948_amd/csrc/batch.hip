@@ -448,7 +448,9 @@ struct tz_batch {
   const void *last_x = nullptr;
   void *last_X = nullptr;
   bool tuned = false;
+  bool tuned_from_cache = false;  // schedule read from the tune cache, no candidates timed
   double tuned_ms[4] = {-1, -1, -1, -1};
+  std::string sig;  // hash of the job table: the key of its schedule in the tune cache
   hipEvent_t done = nullptr;  // recorded after every launch (tz_batch_wait)
   bool launched = false;
   // every device buffer and graph object is released here, so an error
@@ -770,6 +772,15 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
       by_class[ilog2(L) * 4 + complex_in + (nseg > 1 ? 2 : 0)].push_back(it);
     }
   }
+  {
+    // FNV-1a over the job records: equal job tables share a tuned schedule
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char *pj = (const unsigned char *)jobs;
+    for (size_t i = 0; i < sizeof(tz_job) * (size_t)n_jobs; ++i) h = (h ^ pj[i]) * 1099511628211ull;
+    char hx[40];
+    snprintf(hx, sizeof hx, "%016llx-%lld", (unsigned long long)h, (long long)n_jobs);
+    b->sig = hx;
+  }
   // units of G same-class items (segmented items only occur at L = 16384, G = 1)
   static const int kG[15] = {0, 0, 0, 0, 0, 0, 0, 0, group_size<256>(), group_size<512>(), group_size<1024>(),
                              group_size<2048>(), group_size<4096>(), group_size<8192>(), group_size<16384>()};
@@ -893,7 +904,20 @@ tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *s
   if (!b) return bfail(TZ_EINVAL, "batch is NULL");
   if (!x_flat || !X_flat) return bfail(TZ_EINVAL, "x_flat and X_flat must be device pointers");
   hipStream_t s = (hipStream_t)stream;
-  if (!b->tuned) {
+  BatchTune cached;
+  if (!b->tuned && tune_batch_lookup(b->sig, &cached)) {
+    // a schedule this job table was tuned to before (this or an earlier process)
+    b->topology = cached.topology;
+    b->inner = cached.inner;
+    b->units = order_units(*b, b->units, b->inner);
+    tz_status st = upload_units(b, s);
+    if (st) return st;
+    st = build_graph(b, x_flat, X_flat);
+    if (st) return st;
+    b->tuned = true;
+    b->tuned_from_cache = true;
+    tz_log("batch autotune: schedule from the tune cache: topology %d, unit order %d", b->topology, b->inner);
+  } else if (!b->tuned) {
     // first launch: time each candidate schedule on these buffers and keep
     // the fastest (every candidate computes the same outputs)
     const std::vector<BatchUnit> base = b->units;
@@ -930,6 +954,11 @@ tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *s
     st = build_graph(b, x_flat, X_flat);
     if (st) return st;
     b->tuned = true;
+    BatchTune t;
+    t.topology = b->topology;
+    t.inner = b->inner;
+    t.ms = b->tuned_ms[best];
+    tune_batch_store(b->sig, t);
   } else if (x_flat != b->last_x || X_flat != b->last_X) {
     tz_status st = build_graph(b, x_flat, X_flat);
     if (st) return st;
@@ -975,7 +1004,9 @@ int64_t tz_batch_describe(const tz_batch *b, char *buf, int64_t len) {
     if (b->cls_count[c]) d += " L" + std::to_string(1 << c) + "=" + std::to_string(b->cls_count[c]);
   static const char *names[4] = {"parallel/longest-first", "parallel/creation-order", "chained/longest-first",
                                  "chained/creation-order"};
-  if (b->tuned) {
+  if (b->tuned && b->tuned_from_cache) {
+    d += std::string(" schedule=") + names[b->topology * 2 + b->inner] + " (tune cache)";
+  } else if (b->tuned) {
     d += std::string(" schedule=") + names[b->topology * 2 + b->inner] + " candidates_ms:";
     for (int i = 0; i < 4; ++i) {
       char t[48];

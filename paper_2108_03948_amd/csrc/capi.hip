@@ -109,6 +109,8 @@ struct PadPlan {
   int realF = 0, realP = 0;  // whole-spectrum real-input kernel (N_fft = 2 realP realF)
   bool mixed = false;        // 7-smooth N_fft: mixed-radix FFT of the zero-padded row
   MixPlan mix{};
+  int subF = 0, subP = 0;    // N_fft = subP subF: subP sub-transforms of subF points (mix)
+  int subPairs = 0;          // ... as conjugate pairs (real rows, subP = 16 or 32)
   std::shared_ptr<BluePlan> blue;  // Nfft with no fast factorisation
 };
 
@@ -759,10 +761,23 @@ tz_status get_pad(Device &d, int64_t N, int64_t nfft, hipStream_t s, std::shared
         pl->P = (int)(nfft / F);
         break;
       }
-    if (!pl->realF && !pl->F) pl->mixed = mix_plan(nfft, &pl->mix);
+    // sub-transforms of a short 7-smooth F (whole 128-byte runs of bins per
+    // workgroup) before the power-of-two FFTs of F >= N, whose P workgroups
+    // per trace each write every P-th bin
+    if (!pl->realF && nfft < ((int64_t)1 << 28)) {
+      const int sp = sub_plan(N, nfft, &pl->subF, &pl->subP, &pl->mix);
+      if (sp) {
+        pl->F = 0;
+        pl->subPairs = sp == 2;
+      }
+    }
+    if (!pl->realF && !pl->subF && !pl->F) pl->mixed = mix_plan(nfft, &pl->mix);
     if (pl->realF)
       tz_log("fft_zeropad plan N=%lld N_fft=%lld: real-input kernel, %d FFTs of %d", (long long)N, (long long)nfft,
              pl->realP, pl->realF);
+    else if (pl->subF)
+      tz_log("fft_zeropad plan N=%lld N_fft=%lld: %d sub-transforms of %d (mixed radix, %d passes%s)", (long long)N,
+             (long long)nfft, pl->subP, pl->subF, pl->mix.npass, pl->subPairs ? ", conjugate pairs" : "");
     else if (pl->F)
       tz_log("fft_zeropad plan N=%lld N_fft=%lld: %d FFTs of %d", (long long)N, (long long)nfft, pl->P, pl->F);
     else if (pl->mixed)
@@ -770,7 +785,7 @@ tz_status get_pad(Device &d, int64_t N, int64_t nfft, hipStream_t s, std::shared
              pl->mix.npass);
     else
       tz_log("fft_zeropad plan N=%lld N_fft=%lld: Bluestein", (long long)N, (long long)nfft);
-    if (!pl->F && !pl->mixed) {  // no fast factorisation: evaluate the same bins as a CZT
+    if (!pl->F && !pl->subF && !pl->mixed) {  // no fast factorisation: evaluate the same bins as a CZT
       PhaseParams p{};
       p.rational = 1;
       p.q = nfft;
@@ -806,6 +821,12 @@ tz_status prepare_pad(Device &d, const std::shared_ptr<PadPlan> &pp, int in_kind
     if (c.B > INT32_MAX) return fail(TZ_EUNSUPPORTED, "more than 2^31 - 1 traces for N_fft = %lld", (long long)pp->Nfft);
     return get_mix_twiddles(d, pp->mix, s, &e->root, keep);
   }
+  if (pp->subF) {
+    if (c.B * (pp->subPairs ? 1 : pp->subP / 8) > INT32_MAX)
+      return fail(TZ_EUNSUPPORTED, "too many traces for N_fft = %lld in one launch", (long long)pp->Nfft);
+    if ((st = get_mix_twiddles(d, pp->mix, s, &e->tw, keep))) return st;
+    return get_roots(d, pp->Nfft, s, &e->root, keep);
+  }
   if (pp->realF) {
     if ((st = get_twiddles(d, pp->realF, s, &e->tw, keep))) return st;
     if ((st = get_roots(d, pp->Nfft / 2, s, &e->rh, keep))) return st;
@@ -834,6 +855,24 @@ tz_status exec_pad(const PadExec &e, const void *x, int in_kind, void *X, const 
     a.scale = 1.0f;
     a.B = c.B;
     TZ_HIP(launch_fft_mixed(a, s), "fft_zeropad (mixed radix) launch");
+    return TZ_OK;
+  }
+  if (pp.subF) {
+    SubLaunch a;
+    a.in_kind = in_kind;
+    a.pairs = pp.subPairs;
+    a.x = x;
+    a.xs = c.xs;
+    a.N = pp.N;
+    a.P = pp.subP;
+    a.X = (float2 *)X;
+    a.os = c.os;
+    a.nout = e.nout;
+    a.plan = pp.mix;
+    a.tw = e.tw;
+    a.root = e.root;
+    a.B = c.B;
+    TZ_HIP(launch_fftpad_sub(a, s), "fft_zeropad (sub-transforms) launch");
     return TZ_OK;
   }
   if (pp.realF) {
@@ -887,7 +926,7 @@ void tz_opts_init(tz_opts *o) {
 }
 
 const char *tz_last_error(void) { return g_err.c_str(); }
-const char *tz_version(void) { return "thzspec 0.1 gfx950"; }
+const char *tz_version(void) { return "thzspec 0.2 gfx950"; }
 
 tz_status czt(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *X, const tz_opts *o) {
   if (M < 1) return fail(TZ_EINVAL, "M must be >= 1 (got %lld)", (long long)M);
@@ -1004,13 +1043,23 @@ struct IfftExec {
   int64_t N = 0;
   bool direct = false;  // power of two, k_ifft_pow2
   bool mixed = false;   // 7-smooth, mixed-radix FFT
+  bool half = false;    // Hermitian half spectra to real rows (mixed radix, two rows per FFT)
   MixPlan mix{};
   const float2 *tw = nullptr;
   BlueExec b;
 };
 
-tz_status prepare_ifft(Device &d, int64_t N, const Common &c, hipStream_t s, IfftExec *e, Keep *keep = nullptr) {
+tz_status prepare_ifft(Device &d, int64_t N, const Common &c, hipStream_t s, IfftExec *e, Keep *keep = nullptr,
+                       bool half = false) {
   e->N = N;
+  e->half = half;
+  if (half) {
+    if (c.B > INT32_MAX || !mix_plan(N, &e->mix))
+      return fail(TZ_EUNSUPPORTED, "the half-spectrum ifft needs a 7-smooth N from %d to %d (got %lld)", kMixMinL,
+                  kMixMaxL, (long long)N);
+    e->mixed = true;
+    return get_mix_twiddles(d, e->mix, s, &e->tw, keep);
+  }
   if (ifft_direct_supported(N) && c.B <= INT32_MAX) {
     e->direct = true;
     return get_twiddles(d, N, s, &e->tw, keep);
@@ -1028,7 +1077,7 @@ tz_status prepare_ifft(Device &d, int64_t N, const Common &c, hipStream_t s, Iff
 tz_status exec_ifft(const IfftExec &e, const void *X, void *x, const Common &c, void *ws, hipStream_t s) {
   if (e.mixed) {
     MixLaunch a;
-    a.mode = 2;
+    a.mode = e.half ? 3 : 2;
     a.x = X;
     a.xs = c.xs;
     a.N = e.N;
@@ -1059,14 +1108,17 @@ tz_status exec_ifft(const IfftExec &e, const void *X, void *x, const Common &c, 
 extern "C" {
 
 tz_status ifft(const void *X, int64_t N, void *x, const tz_opts *o) {
+  const bool half = o && (o->flags & TZ_HALF);
   Common c;
-  tz_status st = check_common(X, N, x, o, N, &c);
+  // half: input rows of N/2 + 1 bins, output rows of N floats
+  tz_status st = check_common(X, half ? N / 2 + 1 : N, x, o, N, &c);
   if (st) return st;
+  if (N < 1) return fail(TZ_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
   if ((st = check_ifft(&c))) return st;
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
   IfftExec e;
-  if ((st = prepare_ifft(d, N, c, c.stream, &e))) return st;
+  if ((st = prepare_ifft(d, N, c, c.stream, &e, nullptr, half))) return st;
   void *ws = nullptr;
   if (!e.direct && !e.mixed && e.b.ws && (st = e.b.pl->work.get(c.stream, e.b.ws, &ws))) return st;
   return exec_ifft(e, X, x, c, ws, c.stream);
@@ -1342,12 +1394,14 @@ tz_status tz_plan_create(const tz_plan_params *pp, const tz_opts *o, tz_plan **o
       break;
     }
     case TZ_PLAN_IFFT: {
+      const bool half = o && (o->flags & TZ_HALF);
       P->bins = pp->N;
-      if ((st = check_common(nb, pp->N, (void *)nb, o, pp->N, &c))) return st;
+      if (pp->N < 1) return fail(TZ_EINVAL, "N must be >= 1 (got %lld)", (long long)pp->N);
+      if ((st = check_common(nb, half ? pp->N / 2 + 1 : pp->N, (void *)nb, o, pp->N, &c))) return st;
       if ((st = check_ifft(&c))) return st;
       std::lock_guard<std::mutex> lk(g_mu);
       Device &d = device_state(current_device());
-      if ((st = prepare_ifft(d, pp->N, c, c.stream, &P->i, &P->keep))) return st;
+      if ((st = prepare_ifft(d, pp->N, c, c.stream, &P->i, &P->keep, half))) return st;
       P->ws = P->i.direct ? 0 : P->i.b.ws;
       break;
     }
@@ -1523,6 +1577,59 @@ tz_status tz_bin_freqs(const tz_plan_params *pp, const tz_opts *o, double *f) {
     default:
       return fail(TZ_EINVAL, "unknown plan kind %d", pp->kind);
   }
+}
+
+tz_status tz_autotune(const tz_opts *o) {
+  tz_opts def;
+  tz_opts_init(&def);
+  if (!o) o = &def;
+  hipStream_t s = (hipStream_t)o->stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Device &d = device_state(current_device());
+  // one single-block Bluestein pair per length, N = M = L/2, on 2^25 points
+  // of zero samples (the time does not depend on the values): best of three
+  double ns[15] = {};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TZ_HIP(hipEventCreate(&e0), "autotune events");
+  std::unique_ptr<void, void (*)(void *)> g0(e0, [](void *e) { (void)hipEventDestroy((hipEvent_t)e); });
+  TZ_HIP(hipEventCreate(&e1), "autotune events");
+  std::unique_ptr<void, void (*)(void *)> g1(e1, [](void *e) { (void)hipEventDestroy((hipEvent_t)e); });
+  for (int lc = 8; lc <= 14; ++lc) {
+    const int64_t L = (int64_t)1 << lc, N = L / 2, M = L / 2, B = ((int64_t)1 << 25) / L;
+    const PhaseParams p = band_phase(1000000, 0, 500000, M);
+    std::shared_ptr<BluePlan> pl;
+    tz_status st = get_blue(d, N, M, p, s, &pl, false);
+    if (st) return st;
+    if (pl->L != L || pl->nblk != 1 || pl->nseg != 1)
+      return fail(TZ_EDEVICE, "autotune: unexpected plan for L=%lld", (long long)L);
+    Common c{B, N, M, 0, TZ_FP32, 0, s};
+    BlueExec e;
+    if ((st = prepare_blue(d, pl, 0, c, s, &e))) return st;
+    DevMem x, X;
+    TZ_HIP(x.alloc(sizeof(float) * (size_t)(B * N)), "autotune input");
+    TZ_HIP(X.alloc(sizeof(float2) * (size_t)(B * M)), "autotune output");
+    TZ_HIP(hipMemsetAsync(x.p, 0, sizeof(float) * (size_t)(B * N), s), "autotune input");
+    if ((st = exec_blue(e, x.p, 0, X.p, c, M, nullptr, s))) return st;  // warm
+    float best = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      TZ_HIP(hipEventRecord(e0, s), "autotune");
+      if ((st = exec_blue(e, x.p, 0, X.p, c, M, nullptr, s))) return st;
+      TZ_HIP(hipEventRecord(e1, s), "autotune");
+      TZ_HIP(hipEventSynchronize(e1), "autotune");
+      float ms = 0.f;
+      TZ_HIP(hipEventElapsedTime(&ms, e0, e1), "autotune");
+      if (rep == 0 || ms < best) best = ms;
+    }
+    ns[lc] = (double)best * 1e6 / (double)B;
+    tz_log("autotune: FFT pair of %lld points: %.1f ns (%lld traces)", (long long)L, ns[lc], (long long)B);
+  }
+  tune_set_pair_costs(ns);
+  // one-shot plans made with the old costs are dropped (explicit plans keep
+  // the shape they were created with)
+  d.blue.clear();
+  d.pad.clear();
+  d.zoom.clear();
+  return TZ_OK;
 }
 
 void tz_release_plans(void) {

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace tz {
 
 // Unit-circle chirp parameters: A = e^{j 2 pi a}, W = e^{-j 2 pi w}.
@@ -29,10 +31,10 @@ inline int64_t next_pow2(int64_t v) {
   return p;
 }
 
-// Relative time of one workgroup FFT pair of length L: about the same per
-// point up to 4096, about 1.35x per point at 8192 and 2.1x at 16384 (the
-// register and LDS pressure of the longest single-workgroup transforms).
-inline double fft_pair_cost(int64_t L) { return (double)L * (L <= 4096 ? 1.0 : (L <= 8192 ? 1.35 : 2.1)); }
+// Relative time of one workgroup FFT pair of length L (a power of two in
+// [kMinL, kMaxL]): measured on the device by tz_autotune() or read from the
+// tune cache, else a built-in table (tune.hip).
+double fft_pair_cost(int64_t L);
 
 // Bin blocks of one segment on an FFT shorter than *L that cost less than
 // `cost`: blocks of at least 256 bins (narrower ones re-read the input too
@@ -204,7 +206,8 @@ bool mix_plan(int64_t L, MixPlan *pl);
 // the per-pass twiddle tables of pl (pl.ntw float2), built in FP64
 hipError_t build_mix_twiddles(float2 *twp, const MixPlan &pl, hipStream_t s);
 struct MixLaunch {
-  int mode;  // 0: real f32 rows, 1: real f64 rows (zero-padded FFT); 2: complex rows, inverse DFT
+  int mode;  // 0: real f32 rows, 1: real f64 rows (zero-padded FFT); 2: complex rows, inverse DFT;
+             // 3: Hermitian half spectra (L/2 + 1 bins) to real rows (X then holds floats)
   const void *x;
   int64_t xs, N;  // row stride (elements), samples per row (modes 0, 1)
   float2 *X;
@@ -215,6 +218,25 @@ struct MixLaunch {
   int64_t B;
 };
 hipError_t launch_fft_mixed(const MixLaunch &a, hipStream_t s);
+// zero-padded FFT as P sub-transforms of F points (N_fft = P F, F >= N,
+// 7-smooth F in [64, 1024], P a multiple of the tile's 8 or 16 rows)
+struct SubLaunch {
+  int in_kind;  // 0: f32 rows, 1: f64 rows
+  int pairs;    // conjugate pairs (P = 16 or 32, F <= 640, one workgroup per row)
+  const void *x;
+  int64_t xs, N;
+  int P;
+  float2 *X;
+  int64_t os, nout;
+  MixPlan plan;       // the F-point FFT
+  const float2 *tw;   // its per-pass twiddles
+  const float2 *root; // W_{N_fft}^m, m < N_fft
+  int64_t B;
+};
+// F and P for N and N_fft, with the plan of F: 2 = conjugate pairs,
+// 1 = tiles of independent sub-transforms, 0 = no F fits
+int sub_plan(int64_t N, int64_t nfft, int *F, int *P, MixPlan *pl);
+hipError_t launch_fftpad_sub(const SubLaunch &a, hipStream_t s);
 
 // ---- direct inverse DFT of power-of-two length (ifft.hip) ----
 struct IfftLaunch {
@@ -286,6 +308,17 @@ struct TransposeLaunch {
 hipError_t launch_transpose(const TransposeLaunch &a, hipStream_t s);
 
 bool fft_length_supported(int64_t L);
+
+// the uneven batch's schedule for one job table, as the autotuner left it
+struct BatchTune {
+  int topology = 0, inner = 0;
+  double ms = -1.0;
+};
+// the schedule persisted for the job table with this signature (tune.hip)
+bool tune_batch_lookup(const std::string &sig, BatchTune *out);
+void tune_batch_store(const std::string &sig, const BatchTune &t);
+// per log2 L (8 .. 14): measured time of one FFT pair, made current and saved
+void tune_set_pair_costs(const double ns[15]);
 
 // message returned by tz_last_error() on this thread
 void set_last_error(const char *msg);

@@ -385,3 +385,30 @@ def test_log_names_plan_decisions():
     env.pop("TZ_LOG")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
     assert "thzspec:" not in r.stderr
+
+
+def test_tune_cache_states_without_a_device(tz, tmp_path, monkeypatch):
+    """tz_tune_describe needs no device: with the cache switched off, with a
+    file that does not parse (ignored: the built-in costs stay), and with a
+    well-formed file for some device, which is read (its entry is used only
+    under the current device's key)."""
+    import json
+    monkeypatch.setenv("TZ_TUNE_CACHE", "off")
+    d = tz.tune_describe()
+    assert "cache=off" in d and "persistence off" in d and "fft_pair_ns=built-in" in d, d
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"format": 1, "entries": {')
+    monkeypatch.setenv("TZ_TUNE_CACHE", str(bad))
+    d = tz.tune_describe()
+    assert f"cache={bad}" in d and "cache ignored" in d and "fft_pair_ns=built-in" in d, d
+    monkeypatch.setenv("TZ_TUNE_CACHE", str(tmp_path / "bad2.json"))
+    (tmp_path / "bad2.json").write_text('{"format": 2, "entries": {}}')  # another format: ignored as a whole
+    assert "cache ignored" in tz.tune_describe()
+    good = tmp_path / "good.json"
+    good.write_text(json.dumps({"format": 1, "entries": {"gfx000:test/thzspec 0.0": {
+        "fft_pair_ns": {str(1 << c): float(c) for c in range(8, 15)}, "batches": {}}}}))
+    monkeypatch.setenv("TZ_TUNE_CACHE", str(good))
+    d = tz.tune_describe()
+    assert "cache ignored" not in d and "fft_pair_ns=built-in" in d, d  # no entry for this device
+    monkeypatch.setenv("TZ_TUNE_CACHE", str(tmp_path / "absent.json"))
+    assert "no cache file" in tz.tune_describe()

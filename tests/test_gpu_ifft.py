@@ -11,7 +11,9 @@ row kernels, and every Bluestein shape: single pass (2N - 1 <= 16384), bin
 blocks / input segments just past it, and the four-step path (2N - 1 up to a
 few times 2^17).  Rows are strided on both sides; large N are checked on
 sampled outputs.  A round trip through the zero-padded FFT must return the
-trace.  Tolerance: relative L2 1e-6 per row (FP32 path).
+trace.  With TZ_HALF the input is the Hermitian half spectrum of real traces
+and the output the real traces, checked against the oracle's inverse of the
+full Hermitian spectrum.  Tolerance: relative L2 1e-6 per row (FP32 path).
 """
 import sys
 
@@ -84,3 +86,69 @@ def test_ifft_inverts_fft_zeropad(tz, N):
     r = np.linalg.norm(back - x, axis=1) / np.linalg.norm(x, axis=1)
     say(f"case: ifft(fft_zeropad(x)) N={N}: max rel L2 {r.max():.3e}")
     assert r.max() <= TOL
+
+
+def hermitian_full(H, N):
+    """The full spectrum of N bins whose half H (bins 0 .. N/2) is given:
+    bin k > N/2 is conj(H[N - k]); bin 0 and, for even N, bin N/2 keep only
+    their real parts."""
+    Hc = H.astype(np.complex128).copy()
+    Hc[:, 0] = Hc[:, 0].real
+    if N % 2 == 0:
+        Hc[:, N // 2] = Hc[:, N // 2].real
+    full = np.empty((H.shape[0], N), dtype=np.complex128)
+    full[:, :N // 2 + 1] = Hc
+    k = np.arange(N // 2 + 1, N)
+    full[:, k] = np.conj(Hc[:, N - k])
+    return full
+
+
+# Hermitian half spectra to real traces (ifft with TZ_HALF): two rows per
+# mixed-radix FFT, so odd batches leave the last FFT with one row; odd and
+# even N, the four row-kernel sizes, N = 20480 (the longest), strided rows,
+# general half spectra (not from a real trace: bins 0 and N/2 carry
+# imaginary parts the inverse must ignore)
+@pytest.mark.parametrize("N,B", [(8, 3), (500, 3), (625, 4), (1176, 5), (2646, 2), (6615, 3), (10000, 1),
+                                 (16807, 3), (20000, 2), (20480, 3)])
+def test_ifft_half_spectrum_matches_oracle(tz, orc, N, B):
+    import torch
+    nb = N // 2 + 1
+    H = spectra(B, nb, 900 + N % 1000)
+    dev = torch.device("cuda:0")
+    Hbig = torch.zeros((B, nb + 3), dtype=torch.complex64, device=dev)
+    Hbig[:, :nb] = torch.from_numpy(H).to(dev)
+    obig = torch.full((B, N + 5), 9.0, dtype=torch.float32, device=dev)
+    say(f"case: ifft half spectrum N={N} B={B}")
+    tz.ifft(Hbig[:, :nb], out=obig[:, :N], half=True, N=N)
+    torch.cuda.synchronize()
+    got = obig.cpu().numpy()
+    assert np.all(got[:, N:] == np.float32(9.0)), "wrote past the row"
+    samples = np.arange(N) if N <= 4096 else np.unique(np.r_[0, 1, N - 1, np.random.default_rng(N).integers(0, N, 61)])
+    ref = orc.ifft(hermitian_full(H, N), samples=samples)
+    assert np.max(np.abs(ref.imag)) <= 1e-12 * max(1.0, np.max(np.abs(ref.real)))  # a real trace
+    g = got[:, samples]
+    r = np.linalg.norm(g - ref.real, axis=1) / np.linalg.norm(ref.real, axis=1)
+    say(f"  max rel L2 {r.max():.3e} over {samples.size} samples per row")
+    assert np.isfinite(g).all() and r.max() <= TOL
+
+
+def test_ifft_half_spectrum_inverts_fft_zeropad(tz):
+    """ifft(fft_zeropad(x, z, half=True), half=True) returns the trace padded
+    with z zeros (N_fft = 10000, an odd batch)."""
+    import torch
+    N, z = 4000, 6000
+    x = np.random.default_rng(4).standard_normal((5, N)).astype(np.float32)
+    back = tz.ifft(tz.fft_zeropad(torch.from_numpy(x).cuda(), z, half=True), half=True, N=N + z).cpu().numpy()
+    ref = np.concatenate([x, np.zeros((5, z), np.float32)], axis=1)
+    r = np.linalg.norm(back - ref, axis=1) / np.linalg.norm(x, axis=1)
+    say(f"case: ifft_half(fft_zeropad_half(x)) N={N} N_fft={N + z}: max rel L2 {r.max():.3e}")
+    assert r.max() <= TOL
+
+
+def test_ifft_half_spectrum_refuses_other_lengths(tz):
+    import torch
+    H = torch.zeros((1, 6), dtype=torch.complex64, device="cuda")
+    with pytest.raises(tz.ThzError, match="7-smooth"):
+        tz.ifft(H, half=True, N=11)
+    with pytest.raises(tz.ThzError, match="7-smooth"):
+        tz.ifft(torch.zeros((1, 20481 // 2 + 1), dtype=torch.complex64, device="cuda"), half=True, N=20481)

@@ -196,6 +196,43 @@ def test_fft_zeropad_mixed_radix(tz, dev, orc, N, nfft, half, dtype):
     assert_close(f[:, bins], orc.fft_zeropad(x.astype(np.float64), nz, bins), what=f"fft mixed N={N} Nfft={nfft}")
 
 
+# N_fft = P F with a 7-smooth F >= N: sub-transforms of F points.  P = 16
+# or 32 with F <= 640: conjugate pairs (columns 1 .. P/2 - 1 transformed,
+# their mirrors conjugated, columns 0 and P/2 from one 2F-point real FFT);
+# other multiples of 16: tiles of 16 independent sub-transforms; power-of-
+# two N_fft: tiles of 8 up to F = 1024; other shapes keep the whole-row or
+# Bluestein plans.  Odd and even F, the largest F of each kernel, N = 1,
+# f64 input, the half spectrum, the sweep's N_fft = 20000 at N = 500
+@pytest.mark.parametrize("N,nfft,half,dtype", [
+    (500, 20000, False, "float32"),   # pairs: F = 625, P = 32
+    (500, 10000, True, "float32"),    # pairs: F = 625, P = 16
+    (300, 4800, False, "float64"),    # pairs: F = 300 (even), P = 16
+    (100, 8192, False, "float32"),    # pairs: F = 256, P = 32
+    (1, 1024, False, "float32"),      # pairs: F = 64, P = 16
+    (640, 10240, True, "float32"),    # pairs: F = 640, P = 16: the largest F
+    (500, 30000, False, "float32"),   # 16-row tiles: F = 625, P = 48
+    (1000, 8192, True, "float32"),    # 8-row tiles: F = 1024, P = 8: the largest F
+    (64, 512, False, "float32"),      # 8-row tiles: F = 64, P = 8
+    (700, 131072, False, "float64"),  # 8-row tiles: F = 1024, P = 128
+    (400, 4000, False, "float32"),    # no tile, not a power of two: whole-row FFT
+    (999, 63 * 1000, False, "float32")])  # no tile fits (Bluestein plan)
+def test_fft_zeropad_sub_transforms(tz, dev, orc, N, nfft, half, dtype):
+    rng = np.random.default_rng(3 * N + nfft)
+    x = rng.standard_normal((3, N)).astype(dtype)
+    nz = nfft - N
+    nout = nfft // 2 + 1 if half else nfft
+    say(f"case: fft_zeropad sub-transforms N={N} N_fft={nfft} half={half} {dtype}")
+    full = torch_full(dev, (3, nout + 5))
+    tz.fft_zeropad(to_dev(x, dev), nz, half=half, out=full[:, :nout])
+    f = full.cpu().numpy()
+    assert np.isfinite(f).all()
+    assert np.all(f[:, nout:] == np.complex64(complex(7.0, -7.0))), "wrote past the row"
+    bins = np.arange(nout) if nout <= 8192 else \
+        np.unique(np.r_[0, 1, nout - 1, nout // 2, rng.integers(0, nout, 300)])
+    assert_close(f[:, bins], orc.fft_zeropad(x.astype(np.float64), nz, bins),
+                 what=f"fft sub-transforms N={N} Nfft={nfft}")
+
+
 def torch_full(dev, shape):
     import torch
     return torch.full(shape, complex(7.0, -7.0), dtype=torch.complex64, device=dev)

@@ -49,7 +49,7 @@ def traces(B, N, seed, dev, dtype=np.float32):
 
 def run_plan(plan, x):
     import torch
-    out = torch.empty((plan.batch, plan.bins), dtype=torch.complex64, device=x.device)
+    out = torch.empty((plan.batch, plan.bins), dtype=plan.out_dtype, device=x.device)
     ws = None
     if plan.workspace_bytes:
         ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=x.device)
@@ -120,6 +120,28 @@ def test_ifft_plan_equals_one_shot(tz, dev, N):
     got = run_plan(plan, X).cpu().numpy()
     ref = tz.ifft(X).cpu().numpy()
     assert np.array_equal(got, ref)
+    plan.close()
+
+
+@pytest.mark.parametrize("N", [10000, 945])
+def test_ifft_half_plan_equals_one_shot(tz, dev, N):
+    """The half-spectrum inverse plan (Hermitian bins in, real traces out)
+    equals the one-shot ifft(..., half=True) bit for bit, through both
+    execute() and execute_static()."""
+    import torch
+    rng = np.random.default_rng(N)
+    nb = N // 2 + 1
+    H = torch.from_numpy((rng.standard_normal((3, nb)) + 1j * rng.standard_normal((3, nb))).astype(np.complex64))
+    H = H.to(dev)
+    plan = tz.Plan("ifft", N=N, batch=3, half=True)
+    assert plan.workspace_bytes == 0
+    say(f"case: ifft half plan N={N}")
+    got = run_plan(plan, H).cpu().numpy()
+    ref = tz.ifft(H, half=True, N=N).cpu().numpy()
+    assert got.dtype == np.float32 and np.array_equal(got, ref)
+    out = torch.empty((3, N), dtype=torch.float32, device=dev)
+    plan.execute_static(H, out)
+    assert np.array_equal(out.cpu().numpy(), ref)
     plan.close()
 
 
