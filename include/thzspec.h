@@ -62,8 +62,14 @@ enum { TZ_F32 = 0, TZ_F64 = 1 };
  * to 2^24) whose row FFTs have length 4096, 8192 or 16384 (there BF16 splits
  * each operand into three parts); the four-step column FFTs, chirps and
  * twiddles stay FP32.  Other shapes and the other transforms return
- * TZ_EUNSUPPORTED. */
-enum { TZ_FP32 = 0, TZ_SPLIT_FP16 = 1, TZ_SPLIT_BF16 = 2 };
+ * TZ_EUNSUPPORTED.  TZ_FP64 evaluates czt() (one-shot or plan) by direct
+ * summation of eq. (11) in FP64, X[k] = sum_n x[n] (A^{-1} W^k)^n, and
+ * writes complex128 bins (X rows of M pairs of doubles, out_stride complex
+ * elements apart): O(N M) work per trace, for any contour whose terms FP64
+ * can hold (|ln| of every term's magnitude below 700), including the
+ * spirals of eqs. (16)-(17) too steep for the FP32 tables; the other
+ * transforms return TZ_EUNSUPPORTED for it. */
+enum { TZ_FP32 = 0, TZ_SPLIT_FP16 = 1, TZ_SPLIT_BF16 = 2, TZ_FP64 = 3 };
 /* flags */
 enum {
     TZ_HALF = 1  /* fft_zeropad: write bins 0 .. N_fft/2 only (real input);
@@ -78,7 +84,7 @@ typedef struct {
     int64_t out_stride;     /* complex elements between spectrum rows
                                (0 means the number of bins written)           */
     int32_t in_dtype;       /* TZ_F32 or TZ_F64                               */
-    int32_t precision;      /* TZ_FP32, TZ_SPLIT_FP16 or TZ_SPLIT_BF16        */
+    int32_t precision;      /* TZ_FP32, TZ_SPLIT_FP16, TZ_SPLIT_BF16, TZ_FP64 */
     int32_t flags;          /* TZ_HALF                                        */
     int32_t fir_taps;       /* zoom_fft low-pass length T (0 means 63)        */
     double fir_cutoff_hz;   /* zoom_fft cut-off f_c (0 means f_s / (2 D))     */

@@ -26,10 +26,10 @@ LIB_PATH = os.path.join(_HERE, "libthzspec.so")
 
 TZ_OK, TZ_EINVAL, TZ_ENOMEM, TZ_EDEVICE, TZ_EUNSUPPORTED, TZ_ETIMEOUT = range(6)
 TZ_F32, TZ_F64 = 0, 1
-TZ_FP32, TZ_SPLIT_FP16, TZ_SPLIT_BF16 = 0, 1, 2
+TZ_FP32, TZ_SPLIT_FP16, TZ_SPLIT_BF16, TZ_FP64 = 0, 1, 2, 3
 TZ_HALF = 1
 TZ_JOB_CZT, TZ_JOB_ZOOM = 0, 1
-PRECISIONS = {"fp32": TZ_FP32, "split_fp16": TZ_SPLIT_FP16, "split_bf16": TZ_SPLIT_BF16}
+PRECISIONS = {"fp32": TZ_FP32, "split_fp16": TZ_SPLIT_FP16, "split_bf16": TZ_SPLIT_BF16, "fp64": TZ_FP64}
 _STATUS = {1: "TZ_EINVAL", 2: "TZ_ENOMEM", 3: "TZ_EDEVICE", 4: "TZ_EUNSUPPORTED", 5: "TZ_ETIMEOUT"}
 
 
@@ -235,12 +235,13 @@ def _opts(x, out_stride=0, precision="fp32", flags=0, taps=0, cutoff=0.0, stream
     return o
 
 
-def _out(x, bins, out):
+def _out(x, bins, out, dtype=None):
     torch = _torch()
+    dtype = dtype or torch.complex64
     if out is None:
-        return torch.empty((x.shape[0], bins), dtype=torch.complex64, device=x.device)
-    if out.dtype != torch.complex64 or not out.is_cuda or out.shape != (x.shape[0], bins) or out.stride(1) != 1:
-        raise ValueError("out must be a complex64 GPU tensor [B, bins] with unit inner stride")
+        return torch.empty((x.shape[0], bins), dtype=dtype, device=x.device)
+    if out.dtype != dtype or not out.is_cuda or out.shape != (x.shape[0], bins) or out.stride(1) != 1:
+        raise ValueError(f"out must be a {dtype} GPU tensor [B, bins] with unit inner stride")
     return out
 
 
@@ -260,9 +261,10 @@ def fft_zeropad(x, n_zeros: int, *, half: bool = False, out=None, stream=None):
 
 
 def czt(x, M: int, W: complex, A: complex, *, out=None, precision="fp32", stream=None):
-    """X[k] = sum_n x[n] A^-n W^(kn), k < M, for each row of x (unit circle)."""
+    """X[k] = sum_n x[n] A^-n W^(kn), k < M, for each row of x; complex64, or
+    complex128 with precision="fp64" (direct FP64 summation, any contour)."""
     x = _traces(x)
-    out = _out(x, int(M), out)
+    out = _out(x, int(M), out, _torch().complex128 if precision == "fp64" else None)
     o = _opts(x, out.stride(0), precision=precision, stream=stream)
     W, A = complex(W), complex(A)
     with _torch().cuda.device(x.device):
@@ -587,7 +589,7 @@ class Plan:
             stream = torch.cuda.current_stream()
         self.kind, self.N, self.batch = kind, int(N), int(batch)
         self.dtype = torch.float64 if str(dtype).endswith("float64") else torch.float32
-        self.out_dtype = torch.complex64
+        self.out_dtype = torch.complex128 if (kind == "czt" and precision == "fp64") else torch.complex64
         self.in_len = self.N
         if kind == "ifft":
             self.dtype = torch.complex64

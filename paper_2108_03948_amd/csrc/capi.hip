@@ -302,7 +302,8 @@ tz_status check_common(const void *x, int64_t N, void *X, const tz_opts *o, int6
     return fail(TZ_EINVAL, "in_dtype must be TZ_F32 or TZ_F64");
   c->in_kind = o->in_dtype == TZ_F64 ? 1 : 0;
   c->precision = o->precision;
-  if (c->precision != TZ_FP32 && c->precision != TZ_SPLIT_FP16 && c->precision != TZ_SPLIT_BF16)
+  if (c->precision != TZ_FP32 && c->precision != TZ_SPLIT_FP16 && c->precision != TZ_SPLIT_BF16 &&
+      c->precision != TZ_FP64)
     return fail(TZ_EINVAL, "unknown precision %d", c->precision);
   c->flags = o->flags;
   c->stream = (hipStream_t)o->stream;
@@ -374,6 +375,7 @@ struct BlueExec {
 tz_status prepare_blue(Device &d, const std::shared_ptr<BluePlan> &pl, int in_kind, const Common &c,
                        hipStream_t s, BlueExec *e, Keep *keep = nullptr) {
   e->pl = pl;
+  if (c.precision == TZ_FP64) return fail(TZ_EUNSUPPORTED, "TZ_FP64 evaluates czt() only");
   if (pl->L1) {
     const int L2 = pl->L / pl->L1;
     if (c.precision != TZ_FP32 && !long_rows_mfma_supported(pl->L1, L2))
@@ -910,6 +912,37 @@ tz_status exec_pad(const PadExec &e, const void *x, int in_kind, void *X, const 
   return TZ_OK;
 }
 
+tz_status exec_direct(DirectLaunch a, const void *x, void *X, hipStream_t s) {
+  a.x = x;
+  a.X = (double2 *)X;
+  TZ_HIP(launch_czt_direct64(a, s), "czt (FP64 direct) launch");
+  return TZ_OK;
+}
+
+// launch parameters of the FP64 direct CZT: the contour's logarithms, and a
+// check that every term's magnitude |A^{-n} W^{nk}| = e^{-n ln|A| + n k ln|W|}
+// (extreme at the corners n in {0, N-1}, k in {0, M-1}) stays in FP64's range
+tz_status direct_params(int64_t N, int64_t M, tz_c64 W, tz_c64 A, const Common &c, DirectLaunch *a) {
+  if (N > ((int64_t)1 << 28)) return fail(TZ_EUNSUPPORTED, "TZ_FP64 czt takes N up to 2^28");
+  if ((M + 255) / 256 * c.B > INT32_MAX) return fail(TZ_EUNSUPPORTED, "too many bins x traces for one launch");
+  const double ma = log(hypot(A.re, A.im)), mw = log(hypot(W.re, W.im));
+  const double n1 = (double)(N - 1), k1 = (double)(M - 1);
+  for (double v : {-n1 * ma, -n1 * ma + n1 * k1 * mw})
+    if (!(fabs(v) < 700.0))
+      return fail(TZ_EUNSUPPORTED, "contour terms reach e^%.0f, outside FP64's range", v);
+  a->in_kind = c.in_kind;
+  a->xs = c.xs;
+  a->N = N;
+  a->os = c.os;
+  a->M = M;
+  a->B = c.B;
+  a->ma = ma;
+  a->ta = atan2(A.im, A.re);
+  a->mw = mw;
+  a->tw = atan2(W.im, W.re);
+  return TZ_OK;
+}
+
 }  // namespace tz
 
 using namespace tz;
@@ -934,6 +967,14 @@ tz_status czt(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, void *X, 
   Common c;
   tz_status st = check_common(x, N, X, o, M, &c);
   if (st) return st;
+  if (c.precision == TZ_FP64) {
+    DirectLaunch a;
+    if ((st = direct_params(N, M, W, A, c, &a))) return st;
+    a.x = x;
+    a.X = (double2 *)X;
+    TZ_HIP(launch_czt_direct64(a, c.stream), "czt (FP64 direct) launch");
+    return TZ_OK;
+  }
   PhaseParams p{};
   p.rational = 0;
   p.a = frac01(atan2(A.im, A.re) / (2.0 * M_PI));
@@ -1298,6 +1339,8 @@ struct tz_plan {
   ZoomExec z;
   PadExec p;
   IfftExec i;
+  bool direct = false;  // czt with TZ_FP64: direct summation
+  DirectLaunch dl{};
   Keep keep;            // twiddle / root tables, held past tz_release_plans()
   size_t ws = 0;        // workspace bytes
   size_t u_bytes = 0;   // zoom: the workspace starts with the decimated rows
@@ -1359,6 +1402,14 @@ tz_status tz_plan_create(const tz_plan_params *pp, const tz_opts *o, tz_plan **o
       P->bins = pp->M;
       if ((st = check_common(nb, pp->N, (void *)nb, o, pp->M < 1 ? 1 : pp->M, &c))) return st;
       bool fast = c.precision == TZ_FP32;
+      if (pp->kind == TZ_PLAN_CZT && c.precision == TZ_FP64) {
+        if (pp->M < 1) return fail(TZ_EINVAL, "M must be >= 1 (got %lld)", (long long)pp->M);
+        if (!finite_nonzero(pp->W) || !finite_nonzero(pp->A))
+          return fail(TZ_EINVAL, "W and A must be finite and non-zero");
+        if ((st = direct_params(pp->N, pp->M, pp->W, pp->A, c, &P->dl))) return st;
+        P->direct = true;
+        break;
+      }
       if (pp->kind == TZ_PLAN_CZT) {
         if ((st = plan_czt_phase(*pp, c, &ph))) return st;
         fast = fast && ph.ma == 0.0 && ph.mw == 0.0;
@@ -1427,6 +1478,7 @@ tz_status tz_plan_execute(const tz_plan *P, const void *x, void *X, void *worksp
   if (dev != P->dev) return fail(TZ_EINVAL, "plan built on device %d, current device is %d", P->dev, dev);
   const hipStream_t s = (hipStream_t)stream;
   const Common &c = P->c;
+  if (P->direct) return exec_direct(P->dl, x, X, s);
   switch (P->kind) {
     case TZ_PLAN_FFT_ZEROPAD: return exec_pad(P->p, x, c.in_kind, X, c, workspace, s);
     case TZ_PLAN_IFFT: return exec_ifft(P->i, x, X, c, workspace, s);
@@ -1490,6 +1542,7 @@ tz_status tz_plan_execute_static(const tz_plan *P, const void *x, void *X, void 
   const size_t cap = TZ_STATIC_SCRATCH_BYTES;
   const hipStream_t s = (hipStream_t)stream;
   const Common &c = P->c;
+  if (P->direct) return exec_direct(P->dl, x, X, s);  // no scratch
   bool fits = true;
   BlueExec b;
   switch (P->kind) {

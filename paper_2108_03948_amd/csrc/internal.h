@@ -238,6 +238,18 @@ struct SubLaunch {
 int sub_plan(int64_t N, int64_t nfft, int *F, int *P, MixPlan *pl);
 hipError_t launch_fftpad_sub(const SubLaunch &a, hipStream_t s);
 
+// ---- FP64 direct-summation CZT for any contour (direct.hip) ----
+struct DirectLaunch {
+  int in_kind;  // 0: f32 traces, 1: f64
+  const void *x;
+  int64_t xs, N;
+  double2 *X;  // complex128 bins
+  int64_t os, M, B;
+  double ma, ta;  // ln|A|, arg A
+  double mw, tw;  // ln|W|, arg W
+};
+hipError_t launch_czt_direct64(const DirectLaunch &a, hipStream_t s);
+
 // ---- direct inverse DFT of power-of-two length (ifft.hip) ----
 struct IfftLaunch {
   const float2 *X;   // B rows of L complex, xs apart

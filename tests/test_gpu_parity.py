@@ -397,6 +397,56 @@ def test_czt_spiral(tz, dev, orc, N, M, A0, W0):
         assert_close(X[:, bins], ref, what="spiral czt sampled")
 
 
+# TZ_FP64: direct summation in FP64 for contours the FP32 tables cannot carry
+# (bins spanning up to e^200, beyond FP32's range) and for the unit circle;
+# complex128 bins, every one within 1e-9 of the oracle
+@pytest.mark.parametrize("N,M,A0,W0,dtype", [(500, 400, 1.0, 1.001, "float32"),
+                                              (2000, 1500, 0.99, 1.000003, "float64"),
+                                              (300, 300, 1.02, 0.9999, "float32"),
+                                              (1000, 700, 1.0, 1.0, "float32"),
+                                              (1, 5, 1.0, 1.0, "float32")])
+def test_czt_fp64_direct(tz, dev, orc, N, M, A0, W0, dtype):
+    rng = np.random.default_rng(7 * N + M)
+    x = rng.standard_normal((3, N)).astype(dtype)
+    W = W0 * np.exp(-2j * np.pi * 0.37 / max(N, M))
+    A = A0 * np.exp(2j * np.pi * 0.0123)
+    xd = to_dev(x, dev)
+    say(f"case: FP64 czt N={N} M={M} A0={A0} W0={W0} {dtype}")
+    if (A0, W0) != (1.0, 1.0) and N > 1:
+        with pytest.raises(tz.ThzError) as e:   # beyond the FP32 tables
+            tz.czt(xd, M, W, A)
+        assert e.value.status == tz.TZ_EUNSUPPORTED
+    X = tz.czt(xd, M, W, A, precision="fp64").cpu().numpy()
+    assert X.dtype == np.complex128
+    ref = orc.czt(x.astype(np.float64), M, W, A)
+    assert np.isfinite(X).all()
+    err = np.abs(X - ref) / np.abs(ref)
+    say(f"  max per-bin relative error {err.max():.3e}; |X| spans {np.abs(ref).min():.1e} .. {np.abs(ref).max():.1e}")
+    assert err.max() <= 1e-9
+
+
+def test_czt_fp64_plan_and_limits(tz, dev):
+    x = to_dev(np.random.default_rng(5).standard_normal((2, 700)).astype(np.float32), dev)
+    W, A = 1.0005 * np.exp(-0.003j), 0.999 * np.exp(0.1j)
+    one = tz.czt(x, 600, W, A, precision="fp64").cpu().numpy()
+    plan = tz.Plan("czt", N=700, batch=2, M=600, W=W, A=A, precision="fp64")
+    assert plan.workspace_bytes == 0
+    import torch
+    out = torch.empty((2, 600), dtype=torch.complex128, device=dev)
+    plan.execute(x, out)
+    assert np.array_equal(out.cpu().numpy(), one)
+    plan.close()
+    with pytest.raises(tz.ThzError) as e:          # terms reach e^9950: outside FP64
+        tz.czt(to_dev(np.ones((1, 1000), np.float32), dev), 1000, 1.01, 1.0, precision="fp64")
+    assert e.value.status == tz.TZ_EUNSUPPORTED
+    with pytest.raises(tz.ThzError) as e:          # FP64 is czt() only
+        tz.czt_band_exact(x, 500, 20 * 10**12, 2 * 10**11, 25 * 10**11, precision="fp64")
+    assert e.value.status == tz.TZ_EUNSUPPORTED
+    with pytest.raises(tz.ThzError) as e:
+        tz.zoom_fft(x, 20e12, 0.2e12, 2.5e12, 500, 6, precision="fp64")
+    assert e.value.status == tz.TZ_EUNSUPPORTED
+
+
 def test_czt_spiral_too_steep(tz, dev):
     x = to_dev(np.ones((1, 3000), np.float32), dev)
     with pytest.raises(tz.ThzError) as e:
