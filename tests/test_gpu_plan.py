@@ -87,6 +87,8 @@ def cases(tz):
          dict(kind="fft_zeropad", n_zeros=537, half=True), lambda x: tz.fft_zeropad(x, 537, half=True), False),
         ("zoom", 4, 4096, np.float32, dict(kind="zoom", M=4096, taps=63, **zoom_short),
          lambda x: tz.zoom_fft(x, 20e12, 0.2e12, 2.5e12, 4096, 6, taps=63), True),
+        ("zoom f64 input", 3, 4096, np.float64, dict(kind="zoom", M=4096, taps=63, **zoom_short),
+         lambda x: tz.zoom_fft(x, 20e12, 0.2e12, 2.5e12, 4096, 6, taps=63), True),
         ("zoom, long short-DFT, 255 taps", 2, 300000, np.float32, dict(kind="zoom", M=20000, taps=255, **zoom_long),
          lambda x: tz.zoom_fft(x, 100e12, 0.05e12, 0.1e12, 20000, 16, taps=255), True),
     ]
