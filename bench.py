@@ -230,8 +230,8 @@ def bench_uneven(tz, synth, oracle, dev, stream, reps):
 
 def bench_long(tz, synth, oracle, dev, stream, reps):
     """Long scans: 256 traces x 2^20 samples at T_s = 0.01 ps; czt M = 2^18
-    over 0.05 - 0.10 THz with integer-hertz phases (FP32 and the two split
-    precisions) and the Zoom FFT with D = 64 and 255 taps.  Sampled parity:
+    over 0.05 - 0.10 THz with integer-hertz phases and the Zoom FFT with
+    D = 64 and 255 taps, each in FP32 and the two split precisions.  Sampled parity:
     one trace, 48 bins, against the FP64 oracle."""
     import numpy as np
     import torch
@@ -251,12 +251,15 @@ def bench_long(tz, synth, oracle, dev, stream, reps):
         got = X[77].cpu().numpy()[bins]
         res["czt_" + prec] = {"ms": ms, "bins_per_s": B * ML / (ms * 1e-3),
                               "rel_l2_sampled": float(np.linalg.norm(got - ref_c) / np.linalg.norm(ref_c))}
-    ms = _event_ms(stream, lambda: tz.zoom_fft(x, fs, f1, f2, ML, 64, taps=255, out=X, stream=stream), reps)
-    got = X[77].cpu().numpy()[bins]
-    res["zoom_fp32"] = {"ms": ms, "bins_per_s": B * ML / (ms * 1e-3),
-                        "rel_l2_sampled": float(np.linalg.norm(got - ref_z) / np.linalg.norm(ref_z))}
-    for k in ("czt_split_fp16", "czt_split_bf16"):
-        res[k]["speedup_vs_fp32"] = res["czt_fp32"]["ms"] / res[k]["ms"]
+    for prec in ("fp32", "split_fp16", "split_bf16"):
+        ms = _event_ms(stream, lambda: tz.zoom_fft(x, fs, f1, f2, ML, 64, taps=255, out=X, precision=prec,
+                                                   stream=stream), reps)
+        got = X[77].cpu().numpy()[bins]
+        res["zoom_" + prec] = {"ms": ms, "bins_per_s": B * ML / (ms * 1e-3),
+                               "rel_l2_sampled": float(np.linalg.norm(got - ref_z) / np.linalg.norm(ref_z))}
+    for t in ("czt", "zoom"):
+        for k in (t + "_split_fp16", t + "_split_bf16"):
+            res[k]["speedup_vs_fp32"] = res[t + "_fp32"]["ms"] / res[k]["ms"]
     log("bench: long scans " + ", ".join(f"{k} {v['ms']:.3f} ms ({v['rel_l2_sampled']:.1e})" for k, v in res.items()))
     del x, X
     return res

@@ -59,10 +59,11 @@ enum { TZ_F32 = 0, TZ_F64 = 1 };
  * 16-point DFT-matrix products with operands split into high and low 16-bit
  * parts and FP32 accumulation: single-pass plans of FFT length 4096, 8192 or
  * 16384 with one bin block and real input, and four-step plans (N + M - 1 up
- * to 2^24) whose row FFTs have length 4096, 8192 or 16384 (there BF16 splits
- * each operand into three parts); the four-step column FFTs, chirps and
- * twiddles stay FP32.  Other shapes and the other transforms return
- * TZ_EUNSUPPORTED.  TZ_FP64 evaluates czt() (one-shot or plan) by direct
+ * to 2^24) whose row FFTs have length 1024, 2048, 4096, 8192 or 16384 (there
+ * BF16 splits each operand into three parts); the four-step column FFTs,
+ * chirps and twiddles stay FP32.  zoom_fft() takes them for its short DFT
+ * when that runs on the four-step path (its front end is FP64 either way).
+ * Other shapes and the other transforms return TZ_EUNSUPPORTED.  TZ_FP64 evaluates czt() (one-shot or plan) by direct
  * summation of eq. (11) in FP64, X[k] = sum_n x[n] (A^{-1} W^k)^n, and
  * writes complex128 bins (X rows of M pairs of doubles, out_stride complex
  * elements apart): O(N M) work per trace, for any contour whose terms FP64

@@ -379,8 +379,8 @@ tz_status prepare_blue(Device &d, const std::shared_ptr<BluePlan> &pl, int in_ki
   if (pl->L1) {
     const int L2 = pl->L / pl->L1;
     if (c.precision != TZ_FP32 && !long_rows_mfma_supported(pl->L1, L2))
-      return fail(TZ_EUNSUPPORTED, "split precision on the four-step path needs rows of L2 in {4096, 8192, "
-                                   "16384}; N=%lld, M=%lld has L=%d = %d x %d",
+      return fail(TZ_EUNSUPPORTED, "split precision on the four-step path needs rows of L2 in {1024, 2048, "
+                                   "4096, 8192, 16384}; N=%lld, M=%lld has L=%d = %d x %d",
                   (long long)pl->N, (long long)pl->M, pl->L, pl->L1, L2);
     tz_status st = get_twiddles(d, pl->L1, s, &e->tw_col, keep);
     if (st) return st;
@@ -1174,7 +1174,9 @@ tz_status zoom_fft(const void *x, int64_t N, double fs, double f1, double f2, in
   if (st) return st;
   Common c;
   if ((st = check_common(x, N, X, o, M, &c))) return st;
-  if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "zoom_fft runs in FP32 only");
+  if (c.precision == TZ_FP64) return fail(TZ_EUNSUPPORTED, "TZ_FP64 evaluates czt() only");
+  // split precision: the short DFT's four-step rows (prepare_blue refuses
+  // the shapes without split kernels); the front end is FP64 either way
   std::lock_guard<std::mutex> lk(g_mu);
   Device &d = device_state(current_device());
   std::shared_ptr<ZoomPlan> zp;
@@ -1434,7 +1436,7 @@ tz_status tz_plan_create(const tz_plan_params *pp, const tz_opts *o, tz_plan **o
       if ((st = check_zoom(pp->fs, pp->f1, pp->f2, pp->M, pp->D, T, fc, &K))) return st;
       P->bins = pp->M;
       if ((st = check_common(nb, pp->N, (void *)nb, o, pp->M, &c))) return st;
-      if (c.precision != TZ_FP32) return fail(TZ_EUNSUPPORTED, "zoom_fft runs in FP32 only");
+      if (c.precision == TZ_FP64) return fail(TZ_EUNSUPPORTED, "TZ_FP64 evaluates czt() only");
       std::lock_guard<std::mutex> lk(g_mu);
       Device &d = device_state(current_device());
       std::shared_ptr<ZoomPlan> zp;

@@ -66,9 +66,14 @@ struct MfmaFft {
   using S = typename SP::S;
   static constexpr int NT = L / 16;          // threads: one radix-16 butterfly each
   static constexpr int E = 16;               // points per thread
-  static constexpr int RT = L / 4096;        // trailing VALU radix (1, 2 or 4)
+  // radix-16 passes on the matrix cores: three over 4096-point
+  // sub-transforms from L = 4096 up, two over 256-point ones below
+  static constexpr int NP = L >= 4096 ? 3 : 2;
+  static constexpr int SUB = NP == 3 ? 4096 : 256;
+  static constexpr int RT = L / SUB;         // trailing VALU radix (1, 2, 4 or 8)
   static constexpr int Q = L / 16;           // stride between the inputs of a butterfly
-  static_assert(L == 4096 || L == 8192 || L == 16384, "three radix-16 passes plus radix 1, 2 or 4");
+  static_assert(L == 1024 || L == 2048 || L == 4096 || L == 8192 || L == 16384,
+                "radix-16 passes on the matrix cores plus a trailing radix of 1, 2, 4 or 8");
 
   // DFT-matrix operands: for lane l, rows i = l%32, columns k = 8h + q; a1
   // multiplies Re x, a2 multiplies Im x.  They are the same for every wave,
@@ -218,8 +223,8 @@ struct MfmaFft {
 
   // one radix-16 pass p on the matrix cores: twiddle, product, exchange.
   // xin[g][q] = input 8h+q of butterfly j(g); on return xin holds the inputs
-  // of pass p+1 in the same layout (p < 2), or of the trailing pass in the
-  // VALU layout v (p == 2).
+  // of pass p+1 in the same layout (p < NP - 1), or of the trailing pass in
+  // the VALU layout v (the last one).
   template <int p>
   __device__ __forceinline__ void pass(float2 (&xin)[2][8], float2 (&v)[E], float2 *lds, int wave, int lane,
                                        const TwLds &tw) const {
@@ -246,7 +251,7 @@ struct MfmaFft {
       for (int c = 0; c < 8; ++c) lds[lds_idx(base + out_k(h, c) * NS)] = y[g][c];
     }
     __syncthreads();
-    if constexpr (p < 2) {
+    if constexpr (p < NP - 1) {
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
         const int j = 64 * wave + 32 * g + lane % 32;
@@ -266,7 +271,15 @@ struct MfmaFft {
     }
   }
 
-  // trailing VALU pass of radix RT over the 4096-point sub-transforms
+  // the matrix-core passes of one transform, xin in, v (trailing layout) out
+  __device__ __forceinline__ void passes(float2 (&xin)[2][8], float2 (&v)[E], float2 *lds, int wave, int lane,
+                                         const TwLds &tw) const {
+    pass<0>(xin, v, lds, wave, lane, tw);
+    pass<1>(xin, v, lds, wave, lane, tw);
+    if constexpr (NP == 3) pass<2>(xin, v, lds, wave, lane, tw);
+  }
+
+  // trailing VALU pass of radix RT over the SUB-point sub-transforms
   __device__ __forceinline__ void trailing(float2 (&v)[E], const TwLds &tw) const {
     if constexpr (RT > 1) {
       constexpr int NB = E / RT;
@@ -276,7 +289,7 @@ struct MfmaFft {
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int j = t + i * NT;
-        apply_twiddles<RT>(&v[i * RT], tw, (unsigned)(j % 4096));
+        apply_twiddles<RT>(&v[i * RT], tw, (unsigned)(j % SUB));
         Dft<RT>::template run<1>(&v[i * RT]);
       }
     }
@@ -330,9 +343,7 @@ __global__ void __launch_bounds__(L / 16, 4)
       xin[g][q] = cscale(ld_c64(rp, 8 * n), xv);
     }
   }
-  mf.template pass<0>(xin, v, lds, wave, lane, twd);
-  mf.template pass<1>(xin, v, lds, wave, lane, twd);
-  mf.template pass<2>(xin, v, lds, wave, lane, twd);
+  mf.passes(xin, v, lds, wave, lane, twd);
   mf.trailing(v, twd);
   // spectral product with the conjugate chirp, then the inverse FFT as the
   // conjugate of a forward FFT of the conjugate
@@ -355,9 +366,7 @@ __global__ void __launch_bounds__(L / 16, 4)
 #pragma unroll
     for (int q = 0; q < 8; ++q) xin[g][q] = lds[lds_idx(j + (8 * h2 + q) * Q)];
   }
-  mf.template pass<0>(xin, v, lds, wave2, lane2, twd);
-  mf.template pass<1>(xin, v, lds, wave2, lane2, twd);
-  mf.template pass<2>(xin, v, lds, wave2, lane2, twd);
+  mf.passes(xin, v, lds, wave2, lane2, twd);
   mf.trailing(v, twd);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -407,9 +416,7 @@ __global__ void __launch_bounds__(L2 / 16, 4)
       xin[g][qq] = cmul(ld_c64(rz, 8 * n2), big_twiddle(tbig, k1 * n2));
     }
   }
-  mf.template pass<0>(xin, v, lds, wave, lane, twd);
-  mf.template pass<1>(xin, v, lds, wave, lane, twd);
-  mf.template pass<2>(xin, v, lds, wave, lane, twd);
+  mf.passes(xin, v, lds, wave, lane, twd);
   mf.trailing(v, twd);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -429,9 +436,7 @@ __global__ void __launch_bounds__(L2 / 16, 4)
 #pragma unroll
     for (int qq = 0; qq < 8; ++qq) xin[g][qq] = lds[lds_idx(j + (8 * h2 + qq) * Q)];
   }
-  mf.template pass<0>(xin, v, lds, wave2, lane2, twd);
-  mf.template pass<1>(xin, v, lds, wave2, lane2, twd);
-  mf.template pass<2>(xin, v, lds, wave2, lane2, twd);
+  mf.passes(xin, v, lds, wave2, lane2, twd);
   mf.trailing(v, twd);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -441,7 +446,8 @@ __global__ void __launch_bounds__(L2 / 16, 4)
 }
 
 bool long_rows_mfma_supported(int L1, int L2) {
-  return (L1 == 320 || L1 == 512 || L1 == 1024) && (L2 == 4096 || L2 == 8192 || L2 == 16384);
+  return (L1 == 320 || L1 == 512 || L1 == 1024) &&
+         (L2 == 1024 || L2 == 2048 || L2 == 4096 || L2 == 8192 || L2 == 16384);
 }
 
 template <int L1, int L2>
@@ -458,6 +464,8 @@ static void long_rows_mfma_dispatch(const LongLaunch &a, int64_t nb, hipStream_t
 template <int L1>
 static hipError_t long_rows_mfma_l2(const LongLaunch &a, int64_t nb, hipStream_t s) {
   switch (a.L2) {
+    case 1024: long_rows_mfma_dispatch<L1, 1024>(a, nb, s); break;
+    case 2048: long_rows_mfma_dispatch<L1, 2048>(a, nb, s); break;
     case 4096: long_rows_mfma_dispatch<L1, 4096>(a, nb, s); break;
     case 8192: long_rows_mfma_dispatch<L1, 8192>(a, nb, s); break;
     case 16384: long_rows_mfma_dispatch<L1, 16384>(a, nb, s); break;

@@ -191,9 +191,12 @@ TOL_SPLIT = 1e-5
 
 
 @pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
-@pytest.mark.parametrize("N,M", [(1000000, 200000), (1500000, 100000), (2400000, 100000)])
+@pytest.mark.parametrize("N,M", [(1000000, 200000), (1500000, 100000), (2400000, 100000), (200000, 100000),
+                                 (400000, 200000)])
 def test_long_czt_split_precision(tz, orc, prec, N, M):
-    """Rows of 4096 (L = 320 x 4096 and 512 x 4096) and of 8192 (320 x 8192)."""
+    """Rows of 4096 (L = 320 x 4096 and 512 x 4096), of 8192 (320 x 8192),
+    and of 1024 and 2048 (320 x 1024, 320 x 2048: two matrix-core passes over
+    256-point sub-transforms and a trailing radix 4 or 8)."""
     import torch
     L, blocks = tz.czt_plan_shape(N, M)
     say(f"case: long czt {prec} N={N} M={M} plan L={L} blocks={blocks}")
@@ -209,6 +212,38 @@ def test_long_czt_split_precision(tz, orc, prec, N, M):
         e = rel(X[b, bins], ref[b])
         say(f"  trace {b}: rel L2 {e:.3e}")
         assert e <= TOL_SPLIT
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+def test_long_scans_zoom_split(tz, orc, long_scans, prec):
+    """The long-scan Zoom FFT with its short DFT (four-step, rows of 1024) at
+    split precision; the front end stays FP64."""
+    x, xd = long_scans
+    D, T = 64, 255
+    say(f"case: long scans zoom {prec} B={B_LONG} N={N_LONG} M={M_LONG} D={D} T={T}")
+    X, ms = timed(lambda: tz.zoom_fft(xd, FS, F1, F2, M_LONG, D, taps=T, precision=prec))
+    _, ms32 = timed(lambda: tz.zoom_fft(xd, FS, F1, F2, M_LONG, D, taps=T))
+    say(f"  {prec} {ms:.3f} ms per batch, FP32 {ms32:.3f} ms ({ms32 / ms:.2f}x)")
+    Xh = X.cpu().numpy()
+    assert np.isfinite(Xh).all()
+    rng = np.random.default_rng(14)
+    worst = 0.0
+    for b in (0, 128, 255):
+        bins = sample_bins(M_LONG, rng, 64)
+        ref = orc.zoom_fft(x[b:b + 1].astype(np.float64), FS, F1, F2, M_LONG, D, taps=T, bins=bins)[0]
+        e = rel(Xh[b, bins], ref)
+        worst = max(worst, e)
+        assert e <= TOL_SPLIT, (b, e)
+    say(f"  worst sampled rel L2 {worst:.3e}")
+
+
+def test_zoom_split_refuses_single_pass_short_dft(tz):
+    """A short DFT that runs single-pass on complex u has no split kernel."""
+    import torch
+    x = torch.zeros((2, 4096), device="cuda")
+    with pytest.raises(tz.ThzError) as e:
+        tz.zoom_fft(x, 20e12, 0.2e12, 2.5e12, 4096, 6, precision="split_fp16")
+    assert e.value.status == tz.TZ_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
