@@ -441,7 +441,10 @@ struct tz_batch {
   void *d_u = nullptr, *d_counter = nullptr;
   void *d_tw[15] = {};
   int grid = 0;
-  int topology = 0;  // 0: class kernels as independent graph branches, 1: chained longest class first
+  // 0: class kernels as independent graph branches; 1: two chains (real and
+  // complex input) longest class first; 2: the same chains, both after the
+  // zoom front end; 3: one chain, longest class first, after the front end
+  int topology = 0;
   int inner = 0;     // 0: longest unit first inside a class, 1: creation order
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -449,7 +452,7 @@ struct tz_batch {
   void *last_X = nullptr;
   bool tuned = false;
   bool tuned_from_cache = false;  // schedule read from the tune cache, no candidates timed
-  double tuned_ms[4] = {-1, -1, -1, -1};
+  double tuned_ms[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   std::string sig;  // hash of the job table: the key of its schedule in the tune cache
   hipEvent_t done = nullptr;  // recorded after every launch (tz_batch_wait)
   bool launched = false;
@@ -582,20 +585,25 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
   // Real-input classes (CZT jobs) wait only for the counter reset, so they
   // run beside the zoom front end; complex-input classes (the zooms' short
   // DFTs) also wait for the front end.  Topology 0 makes every class its own
-  // branch; topology 1 chains the classes of each input kind longest first.
+  // branch; 1 chains the classes of each input kind longest first; 2 is 1
+  // with the real-input chain also after the front end (which then has the
+  // GPU to itself instead of starving beside a persistent class kernel); 3
+  // runs every class in one chain after the front end.
   hipGraphNode_t chain[2] = {nullptr, nullptr};
+  const int topo = b->topology;
   for (int c = 14; c >= 8; --c)
     for (int fl = 0; fl < 4; ++fl) {
       const int bucket = c * 4 + fl;
       if (!b->bkt_count[bucket]) continue;
       const int cin = fl & 1;
+      const int ch = topo == 3 ? 0 : cin;  // the chain this class joins
       hipGraphNode_t deps[2];
       int nd = 0;
-      if (b->topology == 1 && chain[cin]) {
-        deps[nd++] = chain[cin];
+      if (topo >= 1 && chain[ch]) {
+        deps[nd++] = chain[ch];
       } else {
         deps[nd++] = reset;
-        if (cin) deps[nd++] = front;
+        if (front && (cin || topo >= 2)) deps[nd++] = front;
       }
       hipGraphNode_t node;
       tz_status st = TZ_OK;
@@ -609,7 +617,7 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
         default: st = add_class_node<16384>(b, bucket, xf, Xc, deps, nd, &node); break;
       }
       if (st) return st;
-      chain[cin] = node;
+      chain[ch] = node;
     }
   if (fault_injected("graph")) return bfail(TZ_EDEVICE, "graph instantiate: injected failure (TZ_FAULT=graph)");
   BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
@@ -925,7 +933,7 @@ tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *s
     BHIP(hipEventCreate(&e0), "autotune events");
     BHIP(hipEventCreate(&e1), "autotune events");
     int best = 0;
-    for (int cand = 0; cand < 4; ++cand) {
+    for (int cand = 0; cand < 8; ++cand) {
       b->topology = cand / 2;
       b->inner = cand % 2;
       b->units = order_units(*b, base, b->inner);
@@ -1002,14 +1010,16 @@ int64_t tz_batch_describe(const tz_batch *b, char *buf, int64_t len) {
   std::string d = "jobs=" + std::to_string(b->n_jobs) + " items=" + std::to_string(b->items.size()) + " units:";
   for (int c = 8; c <= 14; ++c)
     if (b->cls_count[c]) d += " L" + std::to_string(1 << c) + "=" + std::to_string(b->cls_count[c]);
-  static const char *names[4] = {"parallel/longest-first", "parallel/creation-order", "chained/longest-first",
-                                 "chained/creation-order"};
+  static const char *names[8] = {"parallel/longest-first",   "parallel/creation-order",
+                                 "chained/longest-first",    "chained/creation-order",
+                                 "front-first/longest-first", "front-first/creation-order",
+                                 "one-chain/longest-first",  "one-chain/creation-order"};
   if (b->tuned && b->tuned_from_cache) {
     d += std::string(" schedule=") + names[b->topology * 2 + b->inner] + " (tune cache)";
   } else if (b->tuned) {
     d += std::string(" schedule=") + names[b->topology * 2 + b->inner] + " candidates_ms:";
-    for (int i = 0; i < 4; ++i) {
-      char t[48];
+    for (int i = 0; i < 8; ++i) {
+      char t[64];
       snprintf(t, sizeof t, " %s=%.3f", names[i], b->tuned_ms[i]);
       d += t;
     }

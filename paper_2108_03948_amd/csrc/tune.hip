@@ -271,7 +271,7 @@ void absorb(const JVal &root, TuneState &s) {
         bt.topology = (int)tp->num;
         bt.inner = (int)in->num;
         bt.ms = ms && ms->kind == JVal::Num ? ms->num : -1.0;
-        if (bt.topology < 0 || bt.topology > 1 || bt.inner < 0 || bt.inner > 1) continue;
+        if (bt.topology < 0 || bt.topology > 3 || bt.inner < 0 || bt.inner > 1) continue;
         t.batches[b.first] = bt;
       }
     s.arch[kv.first] = t;
