@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(Fft<FL>::NT)
 // X[k-1] taken from lane l-1 (lane 63 of the previous step for lane 0).
 //
 // Persistent: each workgroup fills its twiddle tables once and then takes
-// traces b = blockIdx.x, + gridDim.x, ...; stores are never waited for at
+// traces g, g + gridDim.x, ... (g: blockIdx.x renumbered per XCD); stores are never waited for at
 // barriers, so the writes of one trace drain while the next is loaded and
 // transformed.  (Fetching the next trace during the writes was measured
 // slower: its samples push FFT outputs into scratch, and loads and stores
@@ -349,9 +349,14 @@ __global__ void __launch_bounds__(64 * P)
 #pragma unroll
     for (int j = 0; j < SPT; ++j) xl[tid_ + NTH * j] = pre[j];
   };
+  // traces g, g + G, ... with g numbered so that each XCD takes a contiguous
+  // run of traces per round: its workgroups' concurrent stores then stay
+  // within a few contiguous MB instead of spreading over the whole round
+  // (measured on plain 512 KB row writes: 5.2 TB/s against 4.6 TB/s)
+  const int64_t g = (gridDim.x & 7u) == 0 ? xcd_item(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   {
     float pre[SPT];
-    prefetch(blockIdx.x, threadIdx.x, pre);
+    prefetch(g, threadIdx.x, pre);
     park(pre, threadIdx.x);
   }
   float2 v[E];
@@ -362,7 +367,7 @@ __global__ void __launch_bounds__(64 * P)
   // any load, would wait for every store still in flight
   unsigned w0 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
   asm volatile("" : "+s"(w0));
-  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+  for (int64_t b = g; b < B; b += gridDim.x) {
     __syncthreads();  // tables filled / previous trace's staging reads done
     // thread indices through an opaque zero (the lane from mbcnt): everything
     // derived from them (twiddles, LDS addresses) is formed per trace instead

@@ -18,9 +18,11 @@
 //   A (32 x 16): lane l holds row l%32, k = 8(l/32) + q, q < 8;
 //   B (16 x 32): lane l holds column l%32, k = 8(l/32) + q;
 //   C (32 x 32): lane l holds column l%32, rows (r%4) + 8(r/4) + 4(l/32), r < 16.
-// Wave w owns butterflies j = 64 w + 32 g + l%32 (g = 0, 1); lane half h = l/32
-// holds inputs 8h .. 8h+7 of its butterfly and, after the product, outputs
-// {4h .. 4h+3} and {8+4h .. 8+4h+3}.
+// The DFT matrix's rows are interleaved (row 2o: Re y_o, row 2o + 1: Im y_o),
+// so accumulator registers 2c and 2c + 1 of a lane are the two parts of one
+// output.  Wave w owns butterflies j = 64 w + 32 g + l%32 (g = 0, 1); lane
+// half h = l/32 holds inputs 8h .. 8h+7 of its butterfly and, after the
+// product, outputs 4(c/2) + 2h + c%2, c < 8.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -49,8 +51,15 @@ struct Split<TZ_SPLIT_BF16> {
   __device__ static float16v mfma(V a, V b, float16v c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
 };
 
-// index of output c (c < 8) held by lane half h
-__device__ __forceinline__ int out_k(int h, int c) { return (c < 4) ? 4 * h + c : 8 + 4 * h + (c - 4); }
+// cos(pi m / 8), m < 16, rounded to FP32: the entries of the 16-point DFT matrix
+__constant__ float kCosPi8[16] = {
+    1.0f, 0.92387953251128675613f, 0.70710678118654752440f, 0.38268343236508977173f,
+    0.0f, -0.38268343236508977173f, -0.70710678118654752440f, -0.92387953251128675613f,
+    -1.0f, -0.92387953251128675613f, -0.70710678118654752440f, -0.38268343236508977173f,
+    0.0f, 0.38268343236508977173f, 0.70710678118654752440f, 0.92387953251128675613f};
+
+// index of output c (c < 8) held by lane half h: 2h plus out_k0(c)
+__device__ __forceinline__ constexpr int out_k0(int c) { return 4 * (c / 2) + c % 2; }
 
 // NTERM = 2: operands split x = x_hi + x_lo, product A_hi B_hi + A_hi B_lo +
 // A_lo B_hi (about 16 significant bits per BF16 operand, 22 per FP16 one).
@@ -95,12 +104,11 @@ struct MfmaFft {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int k = 8 * h + q;
-      const int m = ((i % 16) * k) % 16;
-      double s, c;
-      sincospi((double)m / 8.0, &s, &c);    // e^{-j 2 pi m/16} = c - j s
-      const float fr = (float)c, fi = (float)(-s);
-      const float v1 = (i < 16) ? fr : fi;  // coefficient of Re x[k]
-      const float v2 = (i < 16) ? -fi : fr; // coefficient of Im x[k]
+      const int m = ((i / 2) * k) % 16;        // row i: part i % 2 of output i / 2
+      // e^{-j 2 pi m/16} = cos(pi m/8) - j sin(pi m/8), sin(pi m/8) = cos(pi (m-4)/8)
+      const float fr = kCosPi8[m], fi = -kCosPi8[(m + 12) % 16];
+      const float v1 = (i % 2 == 0) ? fr : fi;  // coefficient of Re x[k]
+      const float v2 = (i % 2 == 0) ? -fi : fr; // coefficient of Im x[k]
       const S h1 = (S)v1, h2 = (S)v2;
       a1h[q] = h1;
       a2h[q] = h2;
@@ -132,9 +140,22 @@ struct MfmaFft {
   // and kept in registers
   __device__ __forceinline__ V op(int w, int lane) const { return ops[w * 64 + lane + (int)opaque_zero()]; }
 
+  // the two-term operands of this lane, read once per pass and held in 16
+  // registers through its products (the three-term ones stay in LDS and are
+  // read next to each product)
+  struct Areg {
+    V a1h, a1l, a2h, a2l;
+  };
+  __device__ __forceinline__ Areg load_ops(int lane) const {
+    if constexpr (NTERM == 2)
+      return Areg{ops[lane], ops[64 + lane], ops[128 + lane], ops[192 + lane]};
+    else
+      return Areg{};
+  }
+
   // y = F16 x for this lane's butterfly: x[q] are inputs 8h+q, results are
-  // outputs out_k(h, c), c < 8
-  __device__ __forceinline__ void butterfly(float2 (&x)[8], float2 (&y)[8]) const {
+  // outputs 2h + out_k0(c), c < 8
+  __device__ __forceinline__ void butterfly(float2 (&x)[8], float2 (&y)[8], const Areg &A) const {
     // FP16 needs the inputs brought near 2^13 (its range, and a normal low
     // part); BF16 has the FP32 exponent range and is split as it is
     constexpr bool kScale = PREC == TZ_SPLIT_FP16;
@@ -163,14 +184,12 @@ struct MfmaFft {
         bih[q] = hi;
         bil[q] = (S)(xi - (float)hi);
       }
-      const V a1h = op(0, lane), a1l = op(1, lane);
-      c = SP::mfma(a1h, brh, c);
-      c = SP::mfma(a1h, brl, c);
-      c = SP::mfma(a1l, brh, c);
-      const V a2h = op(2, lane), a2l = op(3, lane);
-      c = SP::mfma(a2h, bih, c);
-      c = SP::mfma(a2h, bil, c);
-      c = SP::mfma(a2l, bih, c);
+      c = SP::mfma(A.a1h, brh, c);
+      c = SP::mfma(A.a1h, brl, c);
+      c = SP::mfma(A.a1l, brh, c);
+      c = SP::mfma(A.a2h, bih, c);
+      c = SP::mfma(A.a2h, bil, c);
+      c = SP::mfma(A.a2l, bih, c);
     } else {
       // the real parts' three operand vectors and their six products first,
       // then the imaginary parts': 12 operand registers live instead of 24
@@ -210,64 +229,81 @@ struct MfmaFft {
       }
     }
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      if constexpr (kScale) {
-        y[cc] = make_float2(c[cc] * down, c[8 + cc] * down);          // outputs 4h + cc
-        y[4 + cc] = make_float2(c[4 + cc] * down, c[12 + cc] * down);  // outputs 8 + 4h + cc
-      } else {
-        y[cc] = make_float2(c[cc], c[8 + cc]);
-        y[4 + cc] = make_float2(c[4 + cc], c[12 + cc]);
-      }
-    }
+    for (int cc = 0; cc < 8; ++cc)  // output 2h + out_k0(cc)
+      y[cc] = kScale ? make_float2(c[2 * cc] * down, c[2 * cc + 1] * down) : make_float2(c[2 * cc], c[2 * cc + 1]);
   }
 
   // one radix-16 pass p on the matrix cores: twiddle, product, exchange.
   // xin[g][q] = input 8h+q of butterfly j(g); on return xin holds the inputs
   // of pass p+1 in the same layout (p < NP - 1), or of the trailing pass in
   // the VALU layout v (the last one).
+  //
+  // LDS addresses are one per-lane base and compile-time offsets: the padded
+  // index lds_idx(i + d) is lds_idx(i) + lds_step16(d) whenever d is a
+  // multiple of 16, or i is a multiple of 16 and d < 16.  Butterfly j's
+  // outputs go to (j / NS) 16 NS + j % NS + k NS; j and j + 32 (g = 0, 1)
+  // differ by 512 in that index for NS <= 16, by 32 for NS = 256 (j % 256
+  // stays below 224 for g = 0).
   template <int p>
   __device__ __forceinline__ void pass(float2 (&xin)[2][8], float2 (&v)[E], float2 *lds, int wave, int lane,
                                        const TwLds &tw) const {
     constexpr int NS = p == 0 ? 1 : (p == 1 ? 16 : 256);
     constexpr int TWS = L / (NS * 16);
+    constexpr int S = lds_step16(NS);                      // between outputs k and k + 1
+    constexpr int GW = lds_step16(NS == 256 ? 32 : 512);   // between butterflies j and j + 32
+    constexpr int SQ = lds_step16(Q);                      // between inputs q and q + 1
     const int h = lane / 32;
+    const int j0 = 64 * wave + lane % 32;
+    const Areg A = load_ops(lane);
     float2 y[2][8];
+    if constexpr (NS > 1) {
+      // twiddles W_L^{jm (8h + q) TWS}, q < 8: two table values and powers
+      // of the step (for NS = 16 both butterflies of the lane share them)
+      auto twiddled = [&](int g, float2 (&w)[8]) {
+        const unsigned jm = (unsigned)((j0 + 32 * g) % NS);
+        const float2 d = tw(jm * TWS);
+        w[0] = tw(jm * (unsigned)(8 * h) * TWS);
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const int j = 64 * wave + 32 * g + lane % 32;
-      if constexpr (NS > 1) {
-        const unsigned jm = (unsigned)(j % NS);
+        for (int q = 1; q < 8; ++q) w[q] = cmul(w[q - 1], d);
+      };
+      float2 w[8];
+      twiddled(0, w);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) xin[g][q] = cmul(xin[g][q], tw(jm * (unsigned)(8 * h + q) * TWS));
+      for (int g = 0; g < 2; ++g) {
+        if (g == 1 && NS == 256) twiddled(1, w);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xin[g][q] = cmul(xin[g][q], w[q]);
+        butterfly(xin[g], y[g], A);
       }
-      butterfly(xin[g], y[g]);
+    } else {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) butterfly(xin[g], y[g], A);
     }
     __syncthreads();  // previous readers of LDS are done
+    {
+      float2 *pw = lds + lds_idx((j0 / NS) * NS * 16 + j0 % NS) + 2 * h * S;
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const int j = 64 * wave + 32 * g + lane % 32;
-      const int base = (j / NS) * NS * 16 + (j % NS);
+      for (int g = 0; g < 2; ++g)
 #pragma unroll
-      for (int c = 0; c < 8; ++c) lds[lds_idx(base + out_k(h, c) * NS)] = y[g][c];
+        for (int c = 0; c < 8; ++c) pw[g * GW + out_k0(c) * S] = y[g][c];
     }
     __syncthreads();
     if constexpr (p < NP - 1) {
+      const float2 *pr = lds + lds_idx(j0) + 8 * h * SQ;
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        const int j = 64 * wave + 32 * g + lane % 32;
+      for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) xin[g][q] = lds[lds_idx(j + (8 * h + q) * Q)];
-      }
+        for (int q = 0; q < 8; ++q) xin[g][q] = pr[g * lds_step16(32) + q * SQ];
     } else {
       // layout of the trailing pass (radix RT) or, with RT = 1, the final
       // natural-order layout t + NT e
       constexpr int R = RT > 1 ? RT : 16;
       constexpr int NB = E / R;
-      const int t = threadIdx.x;
+      const float2 *pr = lds + lds_idx((int)threadIdx.x);
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[i * R + r] = lds[lds_idx(t + i * NT + r * (L / R))];
+        for (int r = 0; r < R; ++r) v[i * R + r] = pr[lds_step16(i * NT + r * (L / R))];
     }
   }
 
@@ -353,18 +389,22 @@ __global__ void __launch_bounds__(L / 16, 4)
     v[MF::out_slot(e)] = cconj(cmul(v[MF::out_slot(e)], ld_c64(rV, 8 * k)));
   }
   __syncthreads();
+  {
+    float2 *pw = lds + lds_idx(t);
 #pragma unroll
-  for (int e = 0; e < E; ++e) lds[lds_idx(t + NT * e)] = v[MF::out_slot(e)];
+    for (int e = 0; e < E; ++e) pw[lds_step16(NT * e)] = v[MF::out_slot(e)];
+  }
   __syncthreads();
   // fresh copies of the thread indices: the second transform recomputes its
   // LDS addresses instead of keeping those of the first one live
   const int t2 = (int)(t + opaque_zero()), wave2 = __builtin_amdgcn_readfirstlane(t2 / 64), lane2 = t2 % 64,
             h2 = lane2 / 32;
+  {
+    const float2 *pr = lds + lds_idx(64 * wave2 + lane2 % 32) + 8 * h2 * lds_step16(Q);
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const int j = 64 * wave2 + 32 * g + lane2 % 32;
+    for (int g = 0; g < 2; ++g)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) xin[g][q] = lds[lds_idx(j + (8 * h2 + q) * Q)];
+      for (int q = 0; q < 8; ++q) xin[g][q] = pr[g * lds_step16(32) + q * lds_step16(Q)];
   }
   mf.passes(xin, v, lds, wave2, lane2, twd);
   mf.trailing(v, twd);
@@ -424,17 +464,21 @@ __global__ void __launch_bounds__(L2 / 16, 4)
     v[MF::out_slot(e)] = cconj(cmul(v[MF::out_slot(e)], ld_c64(rv, 8 * k2)));
   }
   __syncthreads();
+  {
+    float2 *pw = lds + lds_idx(t);
 #pragma unroll
-  for (int e = 0; e < E; ++e) lds[lds_idx(t + NT * e)] = v[MF::out_slot(e)];
+    for (int e = 0; e < E; ++e) pw[lds_step16(NT * e)] = v[MF::out_slot(e)];
+  }
   __syncthreads();
   // fresh copies of the thread indices for the second transform
   const int t2 = (int)(t + opaque_zero()), wave2 = __builtin_amdgcn_readfirstlane(t2 / 64), lane2 = t2 % 64,
             h2 = lane2 / 32;
+  {
+    const float2 *pr = lds + lds_idx(64 * wave2 + lane2 % 32) + 8 * h2 * lds_step16(Q);
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const int j = 64 * wave2 + 32 * g + lane2 % 32;
+    for (int g = 0; g < 2; ++g)
 #pragma unroll
-    for (int qq = 0; qq < 8; ++qq) xin[g][qq] = lds[lds_idx(j + (8 * h2 + qq) * Q)];
+      for (int qq = 0; qq < 8; ++qq) xin[g][qq] = pr[g * lds_step16(32) + qq * lds_step16(Q)];
   }
   mf.passes(xin, v, lds, wave2, lane2, twd);
   mf.trailing(v, twd);
