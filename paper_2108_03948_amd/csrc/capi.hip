@@ -92,6 +92,7 @@ struct BluePlan {
   int nseg, nblk, L;
   int L1 = 0;  // > 0: four-step long path, L = L1 * (L / L1)
   DevMem c_pre, c_post, V, tbig;
+  DevMem c_pre1, c_post1;  // twisted tables of the half-length form (allocated when it applies)
   Workspace work;
 };
 
@@ -272,6 +273,13 @@ tz_status get_blue(Device &d, int64_t N, int64_t M, const PhaseParams &p, hipStr
   TZ_HIP(build_bluestein_tables(p, pl->Ns, pl->nseg, pl->Mb, pl->nblk, pl->L, pl->L1, pl->c_pre.as<float2>(),
                                 pl->c_post.as<float2>(), pl->V.as<float2>(), s),
          "chirp tables");
+  if (!pl->L1 && czt_half_supported(pl->L, pl->nseg, pl->Ns, pl->Mb)) {
+    TZ_HIP(pl->c_pre1.alloc(sizeof(float2) * pl->Ns * pl->nblk), "chirp table");
+    TZ_HIP(pl->c_post1.alloc(sizeof(float2) * pl->Mb * pl->nblk), "chirp table");
+    TZ_HIP(build_half_tables(p, pl->Ns, pl->Mb, pl->nblk, pl->L, pl->c_pre1.as<float2>(),
+                             pl->c_post1.as<float2>(), s),
+           "chirp tables");
+  }
   TZ_HIP(hipStreamSynchronize(s), "chirp tables");
   d.blue[key] = pl;
   *out = pl;
@@ -368,6 +376,7 @@ tz_status spiral_scaling(int64_t N, int64_t M, double ma, double mw, PhaseParams
 struct BlueExec {
   std::shared_ptr<BluePlan> pl;
   const float2 *tw = nullptr, *tw_col = nullptr, *tw_row = nullptr;
+  const float2 *tw_half = nullptr;  // twiddles of L/2 points (half-length form)
   int64_t chunk = 0;
   size_t ws = 0;
 };
@@ -395,6 +404,10 @@ tz_status prepare_blue(Device &d, const std::shared_ptr<BluePlan> &pl, int in_ki
     return fail(TZ_EUNSUPPORTED, "split precision needs L in {4096, 8192, 16384} with one bin block "
                                  "(N + M - 1 <= 16384) and real input; this plan has L=%d",
                 pl->L);
+  if (c.precision == TZ_FP32 && pl->c_pre1.p) {
+    tz_status st = get_twiddles(d, pl->L / 2, s, &e->tw_half, keep);
+    if (st) return st;
+  }
   return get_twiddles(d, pl->L, s, &e->tw, keep);
 }
 
@@ -445,6 +458,11 @@ tz_status exec_blue(const BlueExec &e, const void *x, int in_kind, void *X, cons
   a.L = pl.L;
   a.B = c.B;
   a.precision = c.precision;
+  if (e.tw_half) {
+    a.c_pre1 = pl.c_pre1.as<float2>();
+    a.c_post1 = pl.c_post1.as<float2>();
+    a.tw_half = e.tw_half;
+  }
   if (c.precision != TZ_FP32) {
     TZ_HIP(launch_czt_mfma(a, s), "czt (split precision) launch");
   } else {

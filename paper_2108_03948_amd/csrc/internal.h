@@ -129,6 +129,10 @@ hipError_t build_root_table(float2 *w, int64_t n, int64_t q, hipStream_t s);
 // in four-step order: V[k1 L2 + k2] holds bin k1 + L1 k2 (L = L1 L2)
 hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, int64_t Mb, int nblk,
                                   int64_t L, int L1, float2 *c_pre, float2 *c_post, float2 *V, hipStream_t s);
+// the twisted tables of the half-length form: c_pre1[blk][n] = c_pre[blk][n] W_L^{n},
+// c_post1[blk][k'] = c_post[blk][k'] W_L^{-k'} (one segment), phases in FP64
+hipError_t build_half_tables(const PhaseParams &p, int64_t Ns, int64_t Mb, int nblk, int64_t L, float2 *c_pre1,
+                             float2 *c_post1, hipStream_t s);
 hipError_t build_zoom_tables(double2 *g, int T, double nu_c, double nu_N, double2 *ph, int64_t LD,
                              int64_t D, hipStream_t s);
 
@@ -141,6 +145,10 @@ struct CztLaunch {
   int64_t Ns;  // samples per input segment
   int nseg;    // segments (1 unless N + M - 1 exceeds the longest FFT)
   const float2 *c_pre, *c_post, *V, *tw;
+  // L = 8192 with one segment, N <= L/2 and Mb <= L/2: premultiply and
+  // postmultiply tables twisted by W_L^{n} and W_L^{-k'}, and the twiddles
+  // of L/2 points; nullptr otherwise (the length-L kernel runs)
+  const float2 *c_pre1 = nullptr, *c_post1 = nullptr, *tw_half = nullptr;
   float2 *X;
   int64_t os, M, Mb;
   int nblk;
@@ -148,6 +156,8 @@ struct CztLaunch {
   int64_t B;
   int precision;  // TZ_FP32 / split
 };
+// whether a single-pass plan takes the half-length form (twisted tables)
+bool czt_half_supported(int L, int nseg, int64_t Ns, int64_t Mb);
 hipError_t launch_czt(const CztLaunch &a, hipStream_t s);
 // split-precision (MFMA) variant: L in {4096, 8192, 16384}, one segment, one
 // bin block, real input

@@ -128,6 +128,101 @@ __global__ void __launch_bounds__(Fft<L>::NT, 4)
 }
 
 // ---------------------------------------------------------------------------
+// The same transform when the trace (N <= L/2) and the bin block (Mb <= L/2)
+// each fill at most half of the FFT length: the length-L pair splits into
+// two L/2-point pairs and drops the radix-2 pass of each FFT.  With y zero
+// from n = L/2 on,
+//   Y[2k + h] = FFT_{L/2}( y[n] W_L^{h n} )[k],                h = 0, 1,
+// and the inverse at outputs n < L/2 is
+//   g[n] = conj(a_0[n]) + W_L^{-n} conj(a_1[n]),  a_h = FFT_{L/2}( conj(Y[2k + h] V[2k + h]) ).
+// Thread group h (threads h NT' .. h NT' + NT' - 1, NT' of the half-length
+// FFT) runs the pair of half h in its own half of LDS.  The twist W_L^{n} sits
+// in a second premultiply table, and W_L^{-n} in a second postmultiply one:
+//   X[k0 + n] = post[n] conj(a_0[n]) + post1[n] conj(a_1[n]).
+// For the combine, group 0 hands a_0 of the upper half of the outputs to
+// group 1 through LDS and takes a_1 of the lower half: each thread finishes
+// E/2 outputs.
+// ---------------------------------------------------------------------------
+template <int L, int KIND>
+__global__ void __launch_bounds__(Fft<L>::NT, 4)
+    k_czt_half(const void *__restrict__ x, int64_t xs, int64_t N, const float2 *__restrict__ c_pre,
+               const float2 *__restrict__ c_pre1, const float2 *__restrict__ c_post,
+               const float2 *__restrict__ c_post1, const float2 *__restrict__ V, const float2 *__restrict__ tw,
+               float2 *__restrict__ X, int64_t os, int64_t M, int64_t Mb, int nblk, int64_t nitems) {
+  constexpr int LH = L / 2;
+  using F = Fft<LH>;
+  constexpr int NT = F::NT, E = F::E;
+  static_assert(2 * NT == Fft<L>::NT && E == Fft<L>::E, "two half-length FFTs fill the workgroup");
+  constexpr int XB = KIND == 1 ? 8 : (KIND == 2 ? 8 : 4);
+  __shared__ float2 lds[2 * lds_points<LH>()];
+  __shared__ float2 twl[tw_lds_points<LH>()];
+  const unsigned t = threadIdx.x;
+  const int64_t q = nblk > 1 ? xcd_item(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  if (q >= nitems) return;
+  const int64_t b = q / nblk;
+  const int blk = (int)(q % nblk);
+  const int64_t k0 = (int64_t)blk * Mb;
+  if (k0 >= M) return;
+  const int64_t kmax = (M - k0 < Mb) ? (M - k0) : Mb;
+  const TwLds twd = load_twiddles<LH>(twl, tw, t, 2 * NT);
+  __syncthreads();
+  // the half this thread's group transforms (wave-uniform: NT is a multiple of 64)
+  const unsigned hh = __builtin_amdgcn_readfirstlane(t / NT);
+  const unsigned u = t - hh * NT;
+  float2 *lh = lds + hh * lds_points<LH>();
+  const Rsrc rx = make_rsrc((const char *)x + b * xs * XB, (uint64_t)N * XB);
+  const Rsrc rp = make_rsrc((hh ? c_pre1 : c_pre) + (int64_t)blk * N, (uint64_t)N * 8);
+  const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const unsigned n = u + NT * e;  // past N: 0 (both the sample and its chirp)
+    const float2 c = ld_c64(rp, 8 * n);
+    if constexpr (KIND == 2)
+      v[F::in_slot(e)] = cmul(ld_c64(rx, 8 * n), c);
+    else
+      v[F::in_slot(e)] = cscale(c, ld_real<KIND>(rx, n));
+  }
+  F::forward(v, lh, (int)u, twd);
+  // bins 2k + h: times V, conjugated for the inverse
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const unsigned k = u + opaque_zero() + NT * e;
+    v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * (2 * k + hh))));
+  }
+  F::out_to_in(v);
+  const unsigned u2 = u + opaque_zero();
+  F::forward(v, lh, (int)u2, twd);
+  // a_h[n] at slot out_slot(e), n = u + NT e.  Group 0 finishes n < LH/2
+  // (e < E/2), group 1 the rest; each hands the other its a_h of those n.
+  // The group index only selects between two copies of the code below, so
+  // that every register index stays a compile-time constant.
+  const Rsrc rq0 = make_rsrc(c_post + (int64_t)blk * Mb, (uint64_t)kmax * 8);
+  const Rsrc rq1 = make_rsrc(c_post1 + (int64_t)blk * Mb, (uint64_t)kmax * 8);
+  const Rsrc rX = make_rsrc(X + b * os + k0, (uint64_t)kmax * 8);
+  auto combine = [&](auto half) {
+    constexpr int H = decltype(half)::value;
+    constexpr int GIVE = H ? 0 : E / 2, KEEP = H ? E / 2 : 0;
+    __syncthreads();  // the last pass's LDS reads are done
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) lds[u2 + NT * (GIVE + e)] = v[F::out_slot(GIVE + e)];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {
+      const unsigned n = u2 + NT * (KEEP + e);
+      const float2 mine = v[F::out_slot(KEEP + e)], other = lds[n];
+      const float2 a0 = H ? other : mine, a1 = H ? mine : other;
+      const float2 r = cadd(cmul(cconj(a0), ld_c64(rq0, 8 * n)), cmul(cconj(a1), ld_c64(rq1, 8 * n)));
+      st_c64(r, rX, 8 * n);  // bins past this block are dropped
+    }
+  };
+  if (hh)
+    combine(std::integral_constant<int, 1>{});
+  else
+    combine(std::integral_constant<int, 0>{});
+}
+
+// ---------------------------------------------------------------------------
 // Frequency response of sample/reference pairs (Section 1): workgroup p runs
 // the Bluestein transform of row 2p (reference) and keeps its result in
 // registers, then that of row 2p+1 (sample), and writes only
@@ -835,6 +930,10 @@ __global__ void __launch_bounds__(kZoomThreads)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+bool czt_half_supported(int L, int nseg, int64_t Ns, int64_t Mb) {
+  return L == 8192 && nseg == 1 && Ns <= L / 2 && Mb <= L / 2;
+}
+
 bool fft_length_supported(int64_t L) {
   return L >= kMinL && L <= kMaxL && (L & (L - 1)) == 0;
 }
@@ -844,6 +943,13 @@ static void czt_dispatch_seg(const CztLaunch &a, hipStream_t s) {
   const int64_t items = a.B * a.nblk;
   // blocked plans: a multiple of 8 workgroups for the XCD-aware numbering
   const dim3 grid((unsigned)(a.nblk > 1 ? (items + 7) / 8 * 8 : items)), block(Fft<L>::NT);
+  if constexpr (L == 8192) {
+    if (a.c_pre1) {  // one segment, N and the bin block within L/2 (the plan checked)
+      hipLaunchKernelGGL((k_czt_half<L, KIND>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.c_pre1, a.c_post,
+                         a.c_post1, a.V, a.tw_half, a.X, a.os, a.M, a.Mb, a.nblk, items);
+      return;
+    }
+  }
   if (a.nseg > 1)
     hipLaunchKernelGGL((k_czt<L, KIND, true>), grid, block, 0, s, a.x, a.xs, a.N, a.Ns, a.nseg,
                        a.c_pre, a.c_post, a.V, a.tw, a.X, a.os, a.M, a.Mb, a.nblk, items);

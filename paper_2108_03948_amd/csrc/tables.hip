@@ -12,23 +12,25 @@
 namespace tz {
 
 // c_pre[blk][n] = A^{-n} W^{blk Mb n} W^{n^2/2}: block blk evaluates bins
-// blk*Mb + k', i.e. the CZT with start point A W^{-blk Mb}
-__global__ void k_chirp_pre(float2 *c_pre, int64_t N, int nblk, int64_t Mb, PhaseParams p) {
+// blk*Mb + k', i.e. the CZT with start point A W^{-blk Mb}.  With twist = L > 0
+// the table is c_pre[blk][n] W_L^{n} (the odd-bin half of a split FFT).
+__global__ void k_chirp_pre(float2 *c_pre, int64_t N, int nblk, int64_t Mb, PhaseParams p, int64_t twist) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * nblk) return;
   int64_t blk = i / N, n = i % N;
   double cyc = chirp_cycles(p, n, true);
-  if (blk) {
-    cyc += shift_cycles(p, blk * Mb, n);
-    cyc -= floor(cyc);
-  }
+  if (blk) cyc += shift_cycles(p, blk * Mb, n);
+  if (twist) cyc += (double)(n % twist) / (double)twist;  // W_L^n = e^{-j 2 pi n/L}
+  if (blk || twist) cyc -= floor(cyc);
   // (spiral contours come with one block and one segment)
   const double dn = (double)n;
   c_pre[i] = spiral(p) ? scaled_cycles(cyc, -dn * p.ma + 0.5 * dn * dn * p.mw - p.alpha) : unit_cycles(cyc);
 }
 
-// c_post[s][blk][k'] = W^{k'^2/2} A^{-s Ns} W^{(blk Mb + k') s Ns}
-__global__ void k_chirp_post(float2 *c_post, int64_t Ns, int nseg, int64_t Mb, int nblk, PhaseParams p) {
+// c_post[s][blk][k'] = W^{k'^2/2} A^{-s Ns} W^{(blk Mb + k') s Ns}; with
+// twist = L > 0 (one segment) times W_L^{-k'}
+__global__ void k_chirp_post(float2 *c_post, int64_t Ns, int nseg, int64_t Mb, int nblk, PhaseParams p,
+                             int64_t twist) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Mb * nblk * nseg) return;
   const int64_t k = i % Mb, blk = (i / Mb) % nblk, seg = i / (Mb * nblk);
@@ -43,6 +45,10 @@ __global__ void k_chirp_post(float2 *c_post, int64_t Ns, int nseg, int64_t Mb, i
     } else {
       cyc += frac_mul(p.a, (double)n0) + frac_mul(p.w, (double)(blk * Mb + k) * (double)n0);
     }
+    cyc -= floor(cyc);
+  }
+  if (twist) {
+    cyc -= (double)(k % twist) / (double)twist;
     cyc -= floor(cyc);
   }
   const double dk = (double)k;
@@ -205,9 +211,10 @@ hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, in
                                   int64_t L, int L1, float2 *c_pre, float2 *c_post, float2 *V, hipStream_t s) {
   hipError_t e;
   const int64_t N = Ns;
-  hipLaunchKernelGGL(k_chirp_pre, dim3(nblocks(Ns * nblk, 256)), dim3(256), 0, s, c_pre, Ns, nblk, Mb, p);
+  hipLaunchKernelGGL(k_chirp_pre, dim3(nblocks(Ns * nblk, 256)), dim3(256), 0, s, c_pre, Ns, nblk, Mb, p,
+                     (int64_t)0);
   hipLaunchKernelGGL(k_chirp_post, dim3(nblocks(Mb * nblk * nseg, 256)), dim3(256), 0, s, c_post, Ns,
-                     nseg, Mb, nblk, p);
+                     nseg, Mb, nblk, p, (int64_t)0);
   double2 *a = nullptr, *b = nullptr;
   if ((e = dev_malloc_async((void **)&a, sizeof(double2) * L, s)) != hipSuccess) return e;
   if ((e = dev_malloc_async((void **)&b, sizeof(double2) * L, s)) != hipSuccess) {
@@ -231,6 +238,14 @@ hipError_t build_bluestein_tables(const PhaseParams &p, int64_t Ns, int nseg, in
   hipFreeAsync(a, s);
   hipFreeAsync(b, s);
   return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t build_half_tables(const PhaseParams &p, int64_t Ns, int64_t Mb, int nblk, int64_t L, float2 *c_pre1,
+                             float2 *c_post1, hipStream_t s) {
+  hipLaunchKernelGGL(k_chirp_pre, dim3(nblocks(Ns * nblk, 256)), dim3(256), 0, s, c_pre1, Ns, nblk, Mb, p, L);
+  hipLaunchKernelGGL(k_chirp_post, dim3(nblocks(Mb * nblk, 256)), dim3(256), 0, s, c_post1, Ns, 1, Mb, nblk, p,
+                     L);
+  return hipGetLastError();
 }
 
 hipError_t build_zoom_tables(double2 *g, int T, double nu_c, double nu_N, double2 *ph, int64_t LD,

@@ -136,6 +136,34 @@ def test_czt_bin_blocks_on_shorter_ffts(tz, dev, orc, N, M):
     assert_close(X, orc.czt(x.astype(np.float64), M, W, A), what=f"czt blocks N={N} M={M}")
 
 
+@pytest.mark.parametrize("N,M,dtype", [(4096, 4096, "float32"), (2500, 4000, "float32"), (4000, 300, "float32"),
+                                       (4096, 4096, "float64"), (3500, 3000, "float32"), (4096, 100, "float32")])
+def test_czt_half_length_form(tz, dev, orc, N, M, dtype):
+    """Plans of L = 8192 whose trace and bins each fit in L/2 run as two
+    4096-point Bluestein pairs (odd bins from the trace twisted by W_L^n, the
+    inverse recombined with W_L^-n)."""
+    rng = np.random.default_rng(N + 5 * M)
+    x = rng.standard_normal((4, N)).astype(dtype)
+    W = np.exp(-2j * np.pi * 0.61 / M)
+    A = np.exp(2j * np.pi * 0.0417)
+    L, blocks = tz.czt_plan_shape(N, M)
+    say(f"case: czt half-length form N={N} M={M} {dtype} plan L={L} blocks={blocks}")
+    assert (L, blocks) == (8192, 1)
+    X = tz.czt(to_dev(x, dev), M, W, A).cpu().numpy()
+    assert_close(X, orc.czt(x.astype(np.float64), M, W, A), what=f"czt half N={N} M={M}")
+
+
+def test_zoom_short_dft_half_length_form(tz, dev, orc):
+    """Complex input: the zoom's short DFT on u (3334 samples, 4000 bins)
+    takes the half-length form of an 8192-point plan."""
+    N, D, M = 20000, 6, 4000
+    x = synth.pairs(1, N=N)[:1].astype(np.float32)
+    fs, f1, f2 = 20e12, 0.2e12, 2.5e12
+    say(f"case: zoom N={N} D={D} M={M}: short DFT of {-(-N // D)} samples, plan {tz.czt_plan_shape(-(-N // D), M)}")
+    Z = tz.zoom_fft(to_dev(x, dev), fs, f1, f2, M, D, taps=63).cpu().numpy()
+    assert_close(Z, orc.zoom_fft(x.astype(np.float64), fs, f1, f2, M, D, taps=63), what="zoom half-length short DFT")
+
+
 def test_fft_zeropad_half_spectrum_with_bin_blocks_stays_in_rows(tz, dev, orc):
     """N_fft = 30001 has no power-of-two factor >= N: its bins come from a
     blocked Bluestein plan, of which TZ_HALF needs the first 15001 only.
