@@ -404,7 +404,7 @@ tz_status prepare_blue(Device &d, const std::shared_ptr<BluePlan> &pl, int in_ki
     return fail(TZ_EUNSUPPORTED, "split precision needs L in {4096, 8192, 16384} with one bin block "
                                  "(N + M - 1 <= 16384) and real input; this plan has L=%d",
                 pl->L);
-  if (c.precision == TZ_FP32 && pl->c_pre1.p) {
+  if (pl->c_pre1.p) {
     tz_status st = get_twiddles(d, pl->L / 2, s, &e->tw_half, keep);
     if (st) return st;
   }

@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fft_core.h"
 #include "internal.h"
 #include "thzspec.h"
@@ -299,7 +301,7 @@ struct MfmaFft {
       // natural-order layout t + NT e
       constexpr int R = RT > 1 ? RT : 16;
       constexpr int NB = E / R;
-      const float2 *pr = lds + lds_idx((int)threadIdx.x);
+      const float2 *pr = lds + lds_idx(64 * wave + lane);  // the transform's thread index
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
@@ -315,13 +317,14 @@ struct MfmaFft {
     if constexpr (NP == 3) pass<2>(xin, v, lds, wave, lane, tw);
   }
 
-  // trailing VALU pass of radix RT over the SUB-point sub-transforms
-  __device__ __forceinline__ void trailing(float2 (&v)[E], const TwLds &tw) const {
+  // trailing VALU pass of radix RT over the SUB-point sub-transforms; tl is
+  // the thread's index in the transform
+  __device__ __forceinline__ void trailing(float2 (&v)[E], const TwLds &tw, int tl) const {
     if constexpr (RT > 1) {
       constexpr int NB = E / RT;
       // a fresh thread index: the twiddle addresses of this pass are formed
       // here, not shared with (and held live from) the other transform's
-      const int t = (int)(threadIdx.x + opaque_zero());
+      const int t = (int)(tl + opaque_zero());
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int j = t + i * NT;
@@ -380,7 +383,7 @@ __global__ void __launch_bounds__(L / 16, 4)
     }
   }
   mf.passes(xin, v, lds, wave, lane, twd);
-  mf.trailing(v, twd);
+  mf.trailing(v, twd, t);
   // spectral product with the conjugate chirp, then the inverse FFT as the
   // conjugate of a forward FFT of the conjugate
 #pragma unroll
@@ -407,12 +410,112 @@ __global__ void __launch_bounds__(L / 16, 4)
       for (int q = 0; q < 8; ++q) xin[g][q] = pr[g * lds_step16(32) + q * lds_step16(Q)];
   }
   mf.passes(xin, v, lds, wave2, lane2, twd);
-  mf.trailing(v, twd);
+  mf.trailing(v, twd, t2);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const unsigned k = (unsigned)(t2 + NT * e);
     st_c64(cmul(cconj(v[MF::out_slot(e)]), ld_c64(rq, 8 * k)), rX, 8 * k);
   }
+}
+
+// The half-length form of k_czt_mfma (L = 8192, N and M at most L/2; the
+// same algebra as k_czt_half): thread group h (256 threads) runs a
+// 4096-point split-precision Bluestein pair on the trace twisted by W_L^{h n}
+// and the bins 2k + h, in its own half of LDS; the two inverses are
+// recombined with the second postmultiply table.  Each 4096-point transform
+// is three matrix-core passes with no trailing VALU pass.
+template <int PREC, int KIND>
+__global__ void __launch_bounds__(512, 4)
+    k_czt_mfma_half(const void *__restrict__ x, int64_t xs, int64_t N, const float2 *__restrict__ c_pre,
+                    const float2 *__restrict__ c_pre1, const float2 *__restrict__ c_post,
+                    const float2 *__restrict__ c_post1, const float2 *__restrict__ V, const float2 *__restrict__ tw,
+                    float2 *__restrict__ X, int64_t os, int64_t M) {
+  constexpr int L = 8192, LH = L / 2;
+  using MF = MfmaFft<LH, PREC>;
+  constexpr int NT = MF::NT, E = MF::E, Q = MF::Q;
+  static_assert(2 * NT == 512 && MF::RT == 1, "two 4096-point transforms with no trailing pass");
+  constexpr int XB = KIND == 1 ? 8 : 4;
+  __shared__ float2 lds[2 * lds_points<LH>()];
+  __shared__ float2 twl[tw_lds_points<LH>()];
+  __shared__ __attribute__((aligned(16))) char opl[MF::kOpsBytes];
+  const int t = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const TwLds twd = load_twiddles<LH>(twl, tw, t, 2 * NT);
+  MF mf;
+  mf.init(opl, t);
+  __syncthreads();
+  const int hh = __builtin_amdgcn_readfirstlane(t / NT);  // the half of the bins (2k + hh)
+  const int u = t - hh * NT, wave = __builtin_amdgcn_readfirstlane(u / 64), lane = u % 64, h = lane / 32;
+  float2 *lh = lds + hh * lds_points<LH>();
+  const Rsrc rx = make_rsrc((const char *)x + b * xs * XB, (uint64_t)N * XB);
+  const Rsrc rp = make_rsrc(hh ? c_pre1 : c_pre, (uint64_t)N * 8);
+  const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
+
+  float2 xin[2][8];
+  float2 v[E];
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int j = 64 * wave + 32 * g + lane % 32;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const unsigned n = (unsigned)(j + (8 * h + q) * Q);  // past N: 0
+      float xv;
+      if constexpr (KIND == 1)
+        xv = (float)ld_f64(rx, 8 * n);
+      else
+        xv = ld_f32(rx, 4 * n);
+      xin[g][q] = cscale(ld_c64(rp, 8 * n), xv);
+    }
+  }
+  mf.passes(xin, v, lh, wave, lane, twd);
+  // bins 2k + hh: times V, conjugated for the inverse
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const unsigned k = (unsigned)(u + NT * e);
+    v[MF::out_slot(e)] = cconj(cmul(v[MF::out_slot(e)], ld_c64(rV, 8 * (2 * k + hh))));
+  }
+  __syncthreads();
+  {
+    float2 *pw = lh + lds_idx(u);
+#pragma unroll
+    for (int e = 0; e < E; ++e) pw[lds_step16(NT * e)] = v[MF::out_slot(e)];
+  }
+  __syncthreads();
+  const int u2 = (int)(u + opaque_zero()), wave2 = __builtin_amdgcn_readfirstlane(u2 / 64), lane2 = u2 % 64,
+            h2 = lane2 / 32;
+  {
+    const float2 *pr = lh + lds_idx(64 * wave2 + lane2 % 32) + 8 * h2 * lds_step16(Q);
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xin[g][q] = pr[g * lds_step16(32) + q * lds_step16(Q)];
+  }
+  mf.passes(xin, v, lh, wave2, lane2, twd);
+  // a_hh[n] at out_slot(e), n = u + NT e: group 0 finishes n < LH/2, group 1
+  // the rest, each taking the other's a of those n through LDS (two copies
+  // of the code, so that every register index is a compile-time constant)
+  const Rsrc rq0 = make_rsrc(c_post, (uint64_t)M * 8);
+  const Rsrc rq1 = make_rsrc(c_post1, (uint64_t)M * 8);
+  const Rsrc rX = make_rsrc(X + b * os, (uint64_t)M * 8);
+  auto combine = [&](auto half) {
+    constexpr int H = decltype(half)::value;
+    constexpr int GIVE = H ? 0 : E / 2, KEEP = H ? E / 2 : 0;
+    __syncthreads();  // the last pass's LDS reads are done
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) lds[u2 + NT * (GIVE + e)] = v[MF::out_slot(GIVE + e)];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {
+      const unsigned n = (unsigned)(u2 + NT * (KEEP + e));
+      const float2 mine = v[MF::out_slot(KEEP + e)], other = lds[n];
+      const float2 a0 = H ? other : mine, a1 = H ? mine : other;
+      st_c64(cadd(cmul(cconj(a0), ld_c64(rq0, 8 * n)), cmul(cconj(a1), ld_c64(rq1, 8 * n))), rX, 8 * n);
+    }
+  };
+  if (hh)
+    combine(std::integral_constant<int, 1>{});
+  else
+    combine(std::integral_constant<int, 0>{});
 }
 
 // Row pass of the four-step path (the spectral product of eq. (15) on the
@@ -457,7 +560,7 @@ __global__ void __launch_bounds__(L2 / 16, 4)
     }
   }
   mf.passes(xin, v, lds, wave, lane, twd);
-  mf.trailing(v, twd);
+  mf.trailing(v, twd, t);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const unsigned k2 = (unsigned)(t + NT * e);
@@ -481,7 +584,7 @@ __global__ void __launch_bounds__(L2 / 16, 4)
       for (int qq = 0; qq < 8; ++qq) xin[g][qq] = pr[g * lds_step16(32) + qq * lds_step16(Q)];
   }
   mf.passes(xin, v, lds, wave2, lane2, twd);
-  mf.trailing(v, twd);
+  mf.trailing(v, twd, t2);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const unsigned n2 = (unsigned)(t2 + NT * e);
@@ -536,6 +639,17 @@ bool czt_mfma_supported(int L, int nseg, int nblk, int in_kind) {
 template <int L, int PREC>
 static void mfma_dispatch(const CztLaunch &a, hipStream_t s) {
   const dim3 grid((unsigned)a.B), block(L / 16);
+  if constexpr (L == 8192) {
+    if (a.c_pre1) {  // N and M within L/2 (the plan checked)
+      if (a.in_kind == 1)
+        hipLaunchKernelGGL((k_czt_mfma_half<PREC, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.c_pre1,
+                           a.c_post, a.c_post1, a.V, a.tw_half, a.X, a.os, a.M);
+      else
+        hipLaunchKernelGGL((k_czt_mfma_half<PREC, 0>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.c_pre1,
+                           a.c_post, a.c_post1, a.V, a.tw_half, a.X, a.os, a.M);
+      return;
+    }
+  }
   if (a.in_kind == 1)
     hipLaunchKernelGGL((k_czt_mfma<L, PREC, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.c_post, a.V, a.tw,
                        a.X, a.os, a.M);
