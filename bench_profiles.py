@@ -6,6 +6,7 @@
          <calibration.json> <out.md> "<cmd>" <name-substring> ...
   python bench_profiles.py utilization <counter.csv> <out.md> "<cmd>" <name-substring> ...
   python bench_profiles.py timed <kernel_trace.csv> <out.json> "<cmd>" <warmup> <steps>
+  python bench_profiles.py instructions <counter.csv> <out.md> "<cmd>"
 
 Byte counters are scaled by what the same counters read for the 1 GiB device
 copy that ``bench.py --calib-copy`` runs first (dispatch with the largest grid
@@ -21,7 +22,7 @@ import sys
 # bench dispatches: (kernel-name substring, grid size in work-items or None);
 # the grid tells the timed 8192 x 4096 launches from the same kernels' use in
 # the multi-dimensional transforms
-KERNEL_KEYS = {"czt": ("k_czt<8192, 0, false>", 4194304), "fft_zeropad": ("k_fftpad_real<2048, 16, 0>", None),
+KERNEL_KEYS = {"czt": ("k_czt_half<8192, 0>", 4194304), "fft_zeropad": ("k_fftpad_real<2048, 16, 0>", None),
                "zoom_front": ("k_zoom_front<0, 1, false>", 6291456),
                "zoom_short_dft": ("k_czt<2048, 2, false>", 3145728),
                "transpose_2d_scans": ("k_transpose_c64", 524288), "transpose_3d_cube": ("k_transpose_c64", 2097152),
@@ -149,6 +150,44 @@ def timed(trace_csv, out, cmd, warmup, steps, source_hash):
     json.dump(res, open(out, "w"), indent=1)
 
 
+# the bench step's kernels: (name substring, grid size, points per dispatch, what a point is)
+STEP_POINTS = [
+    ("k_czt_half<8192, 0>", 4194304, 8192 * 8192,
+     "czt: 8192 Bluestein pairs of L = 8192, as two 4096-point pairs each (per point of L: premultiply, "
+     "two FFTs, x V, postmultiply)"),
+    ("k_fftpad_real<2048, 16, 0>", None, 8192 * 16 * 2048,
+     "fft_zeropad: 8192 traces x 16 FFTs of 2048 + the real-input combine to 65536 bins (per complex FFT point)"),
+    ("k_czt<2048, 2, false>", 3145728, 8192 * 3 * 2048,
+     "zoom short DFT: 8192 x 3 bin blocks, Bluestein pairs of L = 2048 (per point of L)"),
+    ("k_zoom_front<0, 1, false>", 6291456, 8192 * 683,
+     "zoom front end: 8192 x 683 outputs of 63 FP64 taps (per output)"),
+]
+
+
+def instructions(counter_csv, out, cmd):
+    """SQ_INSTS_VALU / SALU / LDS of the step's kernels per point (a wave's
+    instruction counts once for its 64 lanes)."""
+    acc = {}
+    for r in csv.DictReader(open(counter_csv)):
+        for key, grid, pts, what in STEP_POINTS:
+            if key in r["Kernel_Name"] and (grid is None or int(r["Grid_Size"]) == grid):
+                d = acc.setdefault((key, int(r["Grid_Size"])), {"pts": pts, "what": what, "n": {}, "v": {}})
+                c = r["Counter_Name"]
+                d["v"][c] = d["v"].get(c, 0.0) + float(r["Counter_Value"])
+                d["n"][c] = d["n"].get(c, 0) + 1
+    lines = ["# Instructions per point of the bench step's kernels\n", f"Command:\n\n    {cmd}\n",
+             "Counters are per dispatch, summed over the waves (one instruction of a wave counts once, for 64 "
+             "lanes); per point = counter x 64 / points of the launch.\n",
+             "| kernel | grid | waves | VALU / point | SALU / point | LDS / point | what a point is |",
+             "|---|---|---|---|---|---|---|"]
+    for (key, grid), d in acc.items():
+        avg = {c: d["v"][c] / d["n"][c] for c in d["v"]}
+        per = {c: avg.get(c, 0.0) * 64 / d["pts"] for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS")}
+        lines.append(f"| `{key}` | {grid} | {avg.get('SQ_WAVES', 0):.0f} | {per['SQ_INSTS_VALU']:.1f} | "
+                     f"{per['SQ_INSTS_SALU']:.1f} | {per['SQ_INSTS_LDS']:.1f} | {d['what']} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "timed":
         sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
@@ -158,6 +197,8 @@ if __name__ == "__main__":
         utilization(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:])
     elif sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "instructions":
+        instructions(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "kernel-traffic":
         kernel_traffic(*sys.argv[2:8], sys.argv[8:])
     else:

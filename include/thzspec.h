@@ -301,7 +301,10 @@ typedef struct tz_batch tz_batch;
  * index is in tz_last_error()). */
 tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opts,
                           tz_batch **batch);
-/* Run the batch on device buffers x_flat / X_flat (asynchronous on stream). */
+/* Run the batch on device buffers x_flat / X_flat (asynchronous on stream).
+ * Once a launch has returned an error (TZ_EDEVICE: a HIP call or the graph
+ * build failed), every later launch of the same batch returns TZ_EDEVICE
+ * without touching the device: destroy the batch and create a new one. */
 tz_status tz_batch_launch(tz_batch *batch, const void *x_flat, void *X_flat, void *stream);
 /* Free the batch (synchronises the device first). */
 void tz_batch_destroy(tz_batch *batch);

@@ -456,6 +456,7 @@ struct tz_batch {
   std::string sig;  // hash of the job table: the key of its schedule in the tune cache
   hipEvent_t done = nullptr;  // recorded after every launch (tz_batch_wait)
   bool launched = false;
+  bool failed = false;  // a launch returned an error: later launches are refused
   // every device buffer and graph object is released here, so an error
   // return anywhere in tz_batch_create frees what was allocated before it
   ~tz_batch() { tz::free_batch(this); }
@@ -553,6 +554,9 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
     (void)hipGraphDestroy(b->graph);
     b->graph = nullptr;
   }
+  // an injected failure fires before any graph object exists, so a failed
+  // launch leaves no half-built graph behind
+  if (fault_injected("graph")) return bfail(TZ_EDEVICE, "graph build: injected failure (TZ_FAULT=graph)");
   BHIP(hipGraphCreate(&b->graph, 0), "graph create");
   hipGraphNode_t reset, front = nullptr;
   {
@@ -619,7 +623,6 @@ tz_status build_graph(tz_batch *b, const void *x, void *X) {
       if (st) return st;
       chain[ch] = node;
     }
-  if (fault_injected("graph")) return bfail(TZ_EDEVICE, "graph instantiate: injected failure (TZ_FAULT=graph)");
   BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
   b->last_x = x;
   b->last_X = X;
@@ -908,10 +911,23 @@ tz_status tz_batch_create(const tz_job *jobs, int64_t n_jobs, const tz_opts *opt
   return TZ_OK;
 }
 
-tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *stream) {
-  if (!b) return bfail(TZ_EINVAL, "batch is NULL");
-  if (!x_flat || !X_flat) return bfail(TZ_EINVAL, "x_flat and X_flat must be device pointers");
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// the two events of the first launch's schedule timing, freed on every path
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair() = default;
+  EventPair(const EventPair &) = delete;
+  EventPair &operator=(const EventPair &) = delete;
+  ~EventPair() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+tz_status launch_batch(tz_batch *b, const void *x_flat, void *X_flat, hipStream_t s) {
   BatchTune cached;
   if (!b->tuned && tune_batch_lookup(b->sig, &cached)) {
     // a schedule this job table was tuned to before (this or an earlier process)
@@ -929,9 +945,10 @@ tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *s
     // first launch: time each candidate schedule on these buffers and keep
     // the fastest (every candidate computes the same outputs)
     const std::vector<BatchUnit> base = b->units;
-    hipEvent_t e0, e1;
-    BHIP(hipEventCreate(&e0), "autotune events");
-    BHIP(hipEventCreate(&e1), "autotune events");
+    EventPair ev;
+    BHIP(hipEventCreate(&ev.e0), "autotune events");
+    BHIP(hipEventCreate(&ev.e1), "autotune events");
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     int best = 0;
     for (int cand = 0; cand < 8; ++cand) {
       b->topology = cand / 2;
@@ -952,8 +969,6 @@ tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *s
       tz_log("batch autotune: topology %d, unit order %d: %.3f ms", b->topology, b->inner, ms);
       if (ms < b->tuned_ms[best]) best = cand;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     b->topology = best / 2;
     b->inner = best % 2;
     b->units = order_units(*b, base, b->inner);
@@ -975,6 +990,20 @@ tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *s
   BHIP(hipEventRecord(b->done, s), "batch launch");
   b->launched = true;
   return TZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tz_status tz_batch_launch(tz_batch *b, const void *x_flat, void *X_flat, void *stream) {
+  if (!b) return bfail(TZ_EINVAL, "batch is NULL");
+  if (!x_flat || !X_flat) return bfail(TZ_EINVAL, "x_flat and X_flat must be device pointers");
+  if (b->failed)
+    return bfail(TZ_EDEVICE, "an earlier launch of this batch failed: destroy it and create a new one");
+  const tz_status st = launch_batch(b, x_flat, X_flat, (hipStream_t)stream);
+  if (st) b->failed = true;
+  return st;
 }
 
 tz_status tz_batch_extents(const tz_batch *b, int64_t *x_elems, int64_t *X_elems) {

@@ -434,8 +434,11 @@ __global__ void __launch_bounds__(64 * P)
   // they drain.
   constexpr int SPT = 2 * F / NTH;
   static_assert(SPT * NTH == 2 * F, "the trace must split evenly over the threads");
-  auto prefetch = [&](int64_t tb, unsigned tid_, float (&pre)[SPT]) {
-    const Rsrc rx = make_rsrc((const char *)x + tb * xs * XB, tb < B ? (uint64_t)N * XB : 0);
+  // trace indices are 32-bit (the launcher refuses B >= 2^31): compares and
+  // increments stay on the scalar unit
+  const unsigned B32 = (unsigned)B;
+  auto prefetch = [&](unsigned tb, unsigned tid_, float (&pre)[SPT]) {
+    const Rsrc rx = make_rsrc((const char *)x + (int64_t)tb * xs * XB, tb < B32 ? (uint64_t)N * XB : 0);
 #pragma unroll
     for (int j = 0; j < SPT; ++j) pre[j] = ld_real<KIND>(rx, tid_ + NTH * j);  // past N (or B): 0
   };
@@ -448,7 +451,10 @@ __global__ void __launch_bounds__(64 * P)
   // run of traces per round: its workgroups' concurrent stores then stay
   // within a few contiguous MB instead of spreading over the whole round
   // (measured on plain 512 KB row writes: 5.2 TB/s against 4.6 TB/s)
-  const int64_t g = (gridDim.x & 7u) == 0 ? xcd_item(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  // (32-bit: the 64-bit form took scalar registers that pushed a value out
+  // to scratch, and its reload waited for the stores in flight)
+  const unsigned g = __builtin_amdgcn_readfirstlane(
+      (gridDim.x & 7u) == 0 ? (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x);
   {
     float pre[SPT];
     prefetch(g, threadIdx.x, pre);
@@ -462,7 +468,8 @@ __global__ void __launch_bounds__(64 * P)
   // any load, would wait for every store still in flight
   unsigned w0 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
   asm volatile("" : "+s"(w0));
-  for (int64_t b = g; b < B; b += gridDim.x) {
+  for (unsigned bu = g; bu < B32; bu += gridDim.x) {
+    const int64_t b = bu;
     __syncthreads();  // tables filled / previous trace's staging reads done
     // thread indices through an opaque zero (the lane from mbcnt): everything
     // derived from them (twiddles, LDS addresses) is formed per trace instead
@@ -526,7 +533,7 @@ __global__ void __launch_bounds__(64 * P)
         }
       }
       __syncthreads();
-      if (ph == 1) prefetch(b + gridDim.x, tid + opaque_zero(), pre);
+      if (ph == 1) prefetch(bu + gridDim.x, tid + opaque_zero(), pre);
 
       // wave r takes pairs (k, k+1), k even, k = k0 + 128 it (it < IT):
       // phase 0: k0 = 2 r PPW + 2 lane (r < P/2), 3Q4 + 2 + 2 (r PPW - Q4/2) + 2 lane;
@@ -1085,6 +1092,7 @@ bool fftpad_real_supported(int F, int P) {
 }
 
 hipError_t launch_fftpad_real(const PadRealLaunch &a, hipStream_t s) {
+  if (a.B >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit trace indices in the kernel
   switch (a.F * 100 + a.P) {
     case 102408: pad_real_launch<1024, 8>(a, s); break;   // N_fft 16384, N <= 2048
     case 102416: pad_real_launch<1024, 16>(a, s); break;  // N_fft 32768, N <= 2048
