@@ -1045,6 +1045,12 @@ tz_status czt_transfer(const void *x, int64_t N, int64_t M, tz_c64 W, tz_c64 A, 
   a.M = M;
   a.L = pl->L;
   a.pairs = c.B / 2;
+  if (pl->c_pre1.p) {
+    if ((st = get_twiddles(d, pl->L / 2, c.stream, &a.tw_half))) return st;
+    a.c_post = pl->c_post.as<float2>();
+    a.c_pre1 = pl->c_pre1.as<float2>();
+    a.c_post1 = pl->c_post1.as<float2>();
+  }
   TZ_HIP(launch_czt_transfer(a, c.stream), "czt_transfer launch");
   return TZ_OK;
 }

@@ -171,6 +171,9 @@ struct TransferLaunch {
   int in_kind;  // 0 = f32, 1 = f64
   int64_t xs, N;
   const float2 *c_pre, *V, *tw;
+  // half-length form (L = 8192, N and M within L/2): the postmultiply, the
+  // twisted tables and the twiddles of L/2 points; nullptr otherwise
+  const float2 *c_post = nullptr, *c_pre1 = nullptr, *c_post1 = nullptr, *tw_half = nullptr;
   float2 *H;
   int64_t os, M;
   int L;

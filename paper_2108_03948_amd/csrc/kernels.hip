@@ -300,6 +300,85 @@ __global__ void __launch_bounds__(Fft<L>::NT)
   }
 }
 
+// The transfer kernel in the half-length form of k_czt_half (L = 8192, N and
+// M at most L/2): each trace of the pair runs as two 4096-point Bluestein
+// pairs, X = post conj(a_0) + post1 conj(a_1) is formed for the bins this
+// thread finishes, the reference's X_r is held in registers and the
+// sample's X_s gives H = X_s / X_r (the postmultiply cancels in the ratio,
+// as in k_czt_transfer).  The group's half selects between two copies of
+// the code, so that every register index is a compile-time constant.
+template <int L, int KIND>
+__global__ void __launch_bounds__(Fft<L>::NT, 4)
+    k_czt_transfer_half(const void *__restrict__ x, int64_t xs, int64_t N, const float2 *__restrict__ c_pre,
+                        const float2 *__restrict__ c_pre1, const float2 *__restrict__ c_post,
+                        const float2 *__restrict__ c_post1, const float2 *__restrict__ V,
+                        const float2 *__restrict__ tw, float2 *__restrict__ H, int64_t os, int64_t M) {
+  constexpr int LH = L / 2;
+  using F = Fft<LH>;
+  constexpr int NT = F::NT, E = F::E;
+  static_assert(2 * NT == Fft<L>::NT && E == Fft<L>::E, "two half-length FFTs fill the workgroup");
+  constexpr int XB = KIND == 1 ? 8 : 4;
+  __shared__ float2 lds[2 * lds_points<LH>()];
+  __shared__ float2 twl[tw_lds_points<LH>()];
+  const unsigned t = threadIdx.x;
+  const int64_t pr = blockIdx.x;
+  const TwLds twd = load_twiddles<LH>(twl, tw, t, 2 * NT);
+  __syncthreads();
+  const unsigned hh = __builtin_amdgcn_readfirstlane(t / NT);
+  const unsigned u = t - hh * NT;
+  float2 *lh = lds + hh * lds_points<LH>();
+  const Rsrc rp = make_rsrc(hh ? c_pre1 : c_pre, (uint64_t)N * 8);
+  const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
+  const Rsrc rq0 = make_rsrc(c_post, (uint64_t)M * 8);
+  const Rsrc rq1 = make_rsrc(c_post1, (uint64_t)M * 8);
+  const Rsrc rH = make_rsrc(H + pr * os, (uint64_t)M * 8);  // bins past M are dropped
+  auto run = [&](auto half) {
+    constexpr int HH = decltype(half)::value;
+    constexpr int GIVE = HH ? 0 : E / 2, KEEP = HH ? E / 2 : 0;
+    float2 xr[E / 2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const unsigned u1 = u + opaque_zero();
+      const Rsrc rx = make_rsrc((const char *)x + (2 * pr + s) * xs * XB, (uint64_t)N * XB);
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const unsigned n = u1 + NT * e;  // past N: 0
+        v[F::in_slot(e)] = cscale(ld_c64(rp, 8 * n), ld_real<KIND>(rx, n));
+      }
+      F::forward(v, lh, (int)u1, twd);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const unsigned k = u1 + opaque_zero() + NT * e;
+        v[F::out_slot(e)] = cconj(cmul(v[F::out_slot(e)], ld_c64(rV, 8 * (2 * k + HH))));
+      }
+      F::out_to_in(v);
+      const unsigned u2 = u + opaque_zero();
+      F::forward(v, lh, (int)u2, twd);
+      __syncthreads();  // the last pass's LDS reads are done
+#pragma unroll
+      for (int e = 0; e < E / 2; ++e) lds[u2 + NT * (GIVE + e)] = v[F::out_slot(GIVE + e)];
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E / 2; ++e) {
+        const unsigned n = u2 + NT * (KEEP + e);
+        const float2 mine = v[F::out_slot(KEEP + e)], other = lds[n];
+        const float2 a0 = HH ? other : mine, a1 = HH ? mine : other;
+        const float2 X = cadd(cmul(cconj(a0), ld_c64(rq0, 8 * n)), cmul(cconj(a1), ld_c64(rq1, 8 * n)));
+        if (s == 0)
+          xr[e] = X;
+        else
+          st_c64(cdiv(X, xr[e]), rH, 8 * n);
+      }
+      __syncthreads();  // the swap slots are read before the next trace's FFT reuses LDS
+    }
+  };
+  if (hh)
+    run(std::integral_constant<int, 1>{});
+  else
+    run(std::integral_constant<int, 0>{});
+}
+
 // ---------------------------------------------------------------------------
 // Zero-padded FFT (eqs. (2)-(5)), N_fft = P * F with F >= N:
 //   X[P q + r] = sum_{n<N} (x[n] W_{Nfft}^{r n}) W_F^{q n},   r < P, q < F.
@@ -991,6 +1070,17 @@ hipError_t launch_czt(const CztLaunch &a, hipStream_t s) {
 template <int L>
 static void transfer_dispatch(const TransferLaunch &a, hipStream_t s) {
   const dim3 grid((unsigned)a.pairs), block(Fft<L>::NT);
+  if constexpr (L == 8192) {
+    if (a.c_pre1) {  // N and M within L/2 (the plan checked)
+      if (a.in_kind == 1)
+        hipLaunchKernelGGL((k_czt_transfer_half<L, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.c_pre1,
+                           a.c_post, a.c_post1, a.V, a.tw_half, a.H, a.os, a.M);
+      else
+        hipLaunchKernelGGL((k_czt_transfer_half<L, 0>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.c_pre1,
+                           a.c_post, a.c_post1, a.V, a.tw_half, a.H, a.os, a.M);
+      return;
+    }
+  }
   if (a.in_kind == 1)
     hipLaunchKernelGGL((k_czt_transfer<L, 1>), grid, block, 0, s, a.x, a.xs, a.N, a.c_pre, a.V, a.tw, a.H,
                        a.os, a.M);

@@ -60,6 +60,16 @@ def test_transfer_pairs(tz, orc, N, M):
     check(tz, orc, x, M, W, A, "pairs")
 
 
+@pytest.mark.parametrize("N,M,dtype", [(3000, 4000, np.float32), (4096, 4096, np.float64), (4000, 1500, np.float32)])
+def test_transfer_half_length_form(tz, orc, N, M, dtype):
+    """Plans of L = 8192 whose traces and bins fit in L/2 run each trace of
+    the pair as two 4096-point Bluestein pairs."""
+    x = in_window_pairs(2, N).astype(dtype)
+    W, A = tz.czt_band(20e12, 0.2e12, 2.5e12, M)
+    say(f"case: czt_transfer half-length form N={N} M={M} {np.dtype(dtype).name}")
+    check(tz, orc, x, M, W, A, "half")
+
+
 def test_transfer_fp64_input(tz, orc):
     x = in_window_pairs(2, 1500).astype(np.float64)
     W, A = tz.czt_band(20e12, 0.3e12, 1.8e12, 900)
