@@ -260,23 +260,27 @@ struct MfmaFft {
     float2 y[2][8];
     if constexpr (NS > 1) {
       // twiddles W_L^{jm (8h + q) TWS}, q < 8: two table values and powers
-      // of the step (for NS = 16 both butterflies of the lane share them)
-      auto twiddled = [&](int g, float2 (&w)[8]) {
+      // of the step, applied as they are formed (two complex values live);
+      // for NS = 16 both butterflies of the lane share them
+      auto twist = [&](int g, int g_end) {
         const unsigned jm = (unsigned)((j0 + 32 * g) % NS);
         const float2 d = tw(jm * TWS);
-        w[0] = tw(jm * (unsigned)(8 * h) * TWS);
+        float2 w = tw(jm * (unsigned)(8 * h) * TWS);
 #pragma unroll
-        for (int q = 1; q < 8; ++q) w[q] = cmul(w[q - 1], d);
+        for (int q = 0; q < 8; ++q) {
+#pragma unroll
+          for (int gg = g; gg < g_end; ++gg) xin[gg][q] = cmul(xin[gg][q], w);
+          if (q < 7) w = cmul(w, d);
+        }
       };
-      float2 w[8];
-      twiddled(0, w);
-#pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        if (g == 1 && NS == 256) twiddled(1, w);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) xin[g][q] = cmul(xin[g][q], w[q]);
-        butterfly(xin[g], y[g], A);
+      if constexpr (NS == 256) {
+        twist(0, 1);
+        twist(1, 2);
+      } else {
+        twist(0, 2);
       }
+#pragma unroll
+      for (int g = 0; g < 2; ++g) butterfly(xin[g], y[g], A);
     } else {
 #pragma unroll
       for (int g = 0; g < 2; ++g) butterfly(xin[g], y[g], A);
