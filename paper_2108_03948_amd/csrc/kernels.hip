@@ -256,12 +256,14 @@ __global__ void __launch_bounds__(Fft<L>::NT)
   const Rsrc rV = make_rsrc(V, (uint64_t)L * 8);
   const Rsrc rp = make_rsrc(c_pre, (uint64_t)N * 8);
   const Rsrc rH = make_rsrc(H + p * os, (uint64_t)M * 8);  // bins past M are dropped
-  // From L = 16384 up the reference's g_r waits in H[k] itself (each thread
+  // From L = 8192 up the reference's g_r waits in H[k] itself (each thread
   // reads back only its own stores of those bins, which stay in program
   // order with its loads) rather than in 2E registers, and each trace of the
-  // pair derives its thread offsets afresh: 125-140 registers spilled
-  // otherwise.  Shorter transforms keep g_r in registers.
-  constexpr bool kInH = L >= 16384;
+  // pair derives its thread offsets afresh: at 16384, 125-140 registers
+  // spilled otherwise, and at 8192 the kernel drops from 163 to 84 VGPRs (two
+  // workgroups per CU, 4% faster).  Shorter transforms keep g_r in registers
+  // (measured faster there).
+  constexpr bool kInH = L >= 8192;
   float2 gr[kInH ? 1 : E], v[E];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
