@@ -780,7 +780,7 @@ __global__ void __launch_bounds__(kZoomThreads)
   const int top = j * (int)D + T - 1;  // tile index of x[(m0 + j) D]
   double ar = 0.0, ai = 0.0;
   if (j < opb) {
-#pragma unroll 4
+#pragma unroll 8
     for (int t = sidx; t < T; t += S) {
       const double2 gt = g[t];
       if constexpr (KIND == 2) {
