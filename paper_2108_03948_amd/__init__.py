@@ -235,6 +235,15 @@ def _opts(x, out_stride=0, precision="fp32", flags=0, taps=0, cutoff=0.0, stream
     return o
 
 
+def _empty(x) -> bool:
+    """A batch of no rows (of at least one sample each) has an empty result:
+    the transforms return it without a library call (the C entry points read
+    batch = 0 as one trace)."""
+    if x.shape[1] < 1:
+        raise ValueError("traces must hold at least one sample")
+    return x.shape[0] == 0
+
+
 def _out(x, bins, out, dtype=None):
     torch = _torch()
     dtype = dtype or torch.complex64
@@ -255,6 +264,8 @@ def fft_zeropad(x, n_zeros: int, *, half: bool = False, out=None, stream=None):
     bins = nfft // 2 + 1 if half else nfft
     out = _out(x, bins, out)
     o = _opts(x, out.stride(0), flags=TZ_HALF if half else 0, stream=stream)
+    if _empty(x):
+        return out
     with _torch().cuda.device(x.device):
         _check(lib().fft_zeropad(x.data_ptr(), x.shape[1], int(n_zeros), out.data_ptr(), ctypes.byref(o)))
     return out
@@ -267,6 +278,8 @@ def czt(x, M: int, W: complex, A: complex, *, out=None, precision="fp32", stream
     out = _out(x, int(M), out, _torch().complex128 if precision == "fp64" else None)
     o = _opts(x, out.stride(0), precision=precision, stream=stream)
     W, A = complex(W), complex(A)
+    if _empty(x):
+        return out
     with _torch().cuda.device(x.device):
         _check(lib().czt(x.data_ptr(), x.shape[1], int(M), tz_c64(W.real, W.imag), tz_c64(A.real, A.imag),
                          out.data_ptr(), ctypes.byref(o)))
@@ -309,6 +322,8 @@ def ifft(X, *, out=None, stream=None, half=False, N=None):
     if stream is None:
         stream = torch.cuda.current_stream(X.device)
     o.stream = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    if _empty(X):
+        return out
     with torch.cuda.device(X.device):
         _check(lib().ifft(X.data_ptr(), N, out.data_ptr(), ctypes.byref(o)))
     return out
@@ -328,6 +343,8 @@ def czt_transfer(x, M: int, W: complex, A: complex, *, out=None, stream=None):
         raise ValueError("out must be a complex64 GPU tensor [B/2, M] with unit inner stride")
     o = _opts(x, out.stride(0), stream=stream)
     W, A = complex(W), complex(A)
+    if _empty(x):
+        return out
     with torch.cuda.device(x.device):
         _check(lib().czt_transfer(x.data_ptr(), x.shape[1], M, tz_c64(W.real, W.imag), tz_c64(A.real, A.imag),
                                   out.data_ptr(), ctypes.byref(o)))
@@ -339,6 +356,8 @@ def czt_band_exact(x, M: int, fs_hz: int, f1_hz: int, f2_hz: int, *, out=None, p
     x = _traces(x)
     out = _out(x, int(M), out)
     o = _opts(x, out.stride(0), precision=precision, stream=stream)
+    if _empty(x):
+        return out
     with _torch().cuda.device(x.device):
         _check(lib().czt_band_exact(x.data_ptr(), x.shape[1], int(M), int(fs_hz), int(f1_hz), int(f2_hz),
                                     out.data_ptr(), ctypes.byref(o)))
@@ -353,6 +372,8 @@ def zoom_fft(x, fs: float, f1: float, f2: float, M: int, D: int, *, taps: int = 
     out = _out(x, int(M), out)
     o = _opts(x, out.stride(0), precision=precision, taps=int(taps), cutoff=float(cutoff_hz or 0.0),
               stream=stream)
+    if _empty(x):
+        return out
     with _torch().cuda.device(x.device):
         _check(lib().zoom_fft(x.data_ptr(), x.shape[1], float(fs), float(f1), float(f2), int(M), int(D),
                               out.data_ptr(), ctypes.byref(o)))

@@ -336,6 +336,34 @@ def test_deterministic(tz, dev):
     assert np.array_equal(f.view(np.uint32), g.view(np.uint32))
 
 
+def test_empty_batch_and_empty_traces(tz, dev):
+    """A batch of no traces gives an empty result of the right shape on every
+    transform (no library call); traces of no samples are refused."""
+    import torch
+    say("case: empty batches (0 x 300 traces) and traces of 0 samples")
+    x0 = torch.empty((0, 300), dtype=torch.float32, device=dev)
+    W, A = tz.czt_band(20e12, 0.2e12, 2.5e12, 50)
+    assert tz.fft_zeropad(x0, 212).shape == (0, 512)
+    assert tz.fft_zeropad(x0, 212, half=True).shape == (0, 257)
+    assert tz.czt(x0, 50, W, A).shape == (0, 50)
+    assert tz.czt(x0.double(), 50, W, A, precision="fp64").dtype == torch.complex128
+    assert tz.czt_band_exact(x0, 50, 20 * 10**12, 2 * 10**11, 25 * 10**11).shape == (0, 50)
+    assert tz.zoom_fft(x0, 20e12, 0.2e12, 2.5e12, 50, 3).shape == (0, 50)
+    assert tz.czt_transfer(x0, 50, W, A).shape == (0, 50)
+    X0 = torch.empty((0, 512), dtype=torch.complex64, device=dev)
+    assert tz.ifft(X0).shape == (0, 512)
+    assert tz.ifft(X0[:, :257], half=True).shape == (0, 512)
+    out = torch.empty((0, 50), dtype=torch.complex64, device=dev)
+    assert tz.czt(x0, 50, W, A, out=out) is out
+    torch.cuda.synchronize()
+    for empty in (torch.empty((3, 0), dtype=torch.float32, device=dev),
+                  torch.empty((0,), dtype=torch.float32, device=dev)):
+        with pytest.raises(ValueError):
+            tz.czt(empty, 50, W, A)
+        with pytest.raises(ValueError):
+            tz.fft_zeropad(empty, 100)
+
+
 def test_full_size_batch_sampled(tz, dev, orc):
     """The 8192 x 4096 batch exactly as the benchmark launches it; seeded
     traces and bins are recomputed one by one by the oracle."""
