@@ -153,6 +153,32 @@ def test_czt_half_length_form(tz, dev, orc, N, M, dtype):
     assert_close(X, orc.czt(x.astype(np.float64), M, W, A), what=f"czt half N={N} M={M}")
 
 
+@pytest.mark.parametrize("dtype,precision", [("float32", "fp32"), ("float64", "fp32"), ("float32", "split_bf16"),
+                                             ("float32", "split_fp16")])
+def test_czt_half_length_form_strided_rows(tz, dev, orc, dtype, precision):
+    """The half-length kernels (FP32 and matrix-core) on row views: traces
+    4000 samples long at a row stride of 4500, bins written into rows 4100
+    wide; the 100 columns past the bins keep their contents."""
+    import torch
+    N, M, B = 4000, 4000, 5
+    rng = np.random.default_rng(91)
+    big = rng.standard_normal((B, 4500)).astype(dtype)
+    W = np.exp(-2j * np.pi * 0.53 / M)
+    A = np.exp(2j * np.pi * 0.021)
+    say(f"case: czt half-length form, strided rows, {dtype} {precision} plan {tz.czt_plan_shape(N, M)}")
+    assert tz.czt_plan_shape(N, M) == (8192, 1)
+    xd = to_dev(big, dev)[:, :N]
+    full = torch.empty((B, 4100), dtype=torch.complex64, device=dev)
+    torch.view_as_real(full).fill_(float("nan"))  # both parts NaN
+    out = full[:, :M]
+    assert tz.czt(xd, M, W, A, out=out, precision=precision) is out
+    got = full.cpu().numpy()
+    assert np.isnan(got[:, M:].real).all() and np.isnan(got[:, M:].imag).all()
+    tol = 1e-5 if precision == "split_bf16" else TOL_FP32
+    assert_close(got[:, :M], orc.czt(big[:, :N].astype(np.float64), M, W, A), tol=tol,
+                 what=f"czt half strided {dtype} {precision}")
+
+
 def test_zoom_short_dft_half_length_form(tz, dev, orc):
     """Complex input: the zoom's short DFT on u (3334 samples, 4000 bins)
     takes the half-length form of an 8192-point plan."""
