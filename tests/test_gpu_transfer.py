@@ -70,6 +70,28 @@ def test_transfer_half_length_form(tz, orc, N, M, dtype):
     check(tz, orc, x, M, W, A, "half")
 
 
+def test_transfer_half_length_form_strided_rows(tz, orc):
+    """The half-length transfer kernel on row views: 4 pairs of 4000-sample
+    traces at a row stride of 4300, H written into rows 4200 wide; the
+    columns past the bins keep their contents."""
+    import torch
+    N, M = 4000, 4000
+    x = in_window_pairs(4, N)
+    big = np.zeros((x.shape[0], 4300), np.float32)
+    big[:, :N] = x
+    big[:, N:] = 1e6  # past each trace: must not be read
+    W, A = tz.czt_band(20e12, 0.2e12, 2.5e12, M)
+    say(f"case: czt_transfer half-length form, strided rows, plan {tz.czt_plan_shape(N, M)}")
+    assert tz.czt_plan_shape(N, M) == (8192, 1)
+    full = torch.empty((x.shape[0] // 2, 4200), dtype=torch.complex64, device="cuda")
+    torch.view_as_real(full).fill_(float("nan"))
+    out = full[:, :M]
+    assert tz.czt_transfer(torch.from_numpy(big).cuda()[:, :N], M, W, A, out=out) is out
+    got = full.cpu().numpy()
+    assert np.isnan(got[:, M:].view(np.float32)).all()
+    check_transfer(got[:, :M], orc.czt(x.astype(np.float64), M, W, A), TOL, 1e-5, say=say, what="half strided")
+
+
 def test_transfer_fp64_input(tz, orc):
     x = in_window_pairs(2, 1500).astype(np.float64)
     W, A = tz.czt_band(20e12, 0.3e12, 1.8e12, 900)
