@@ -450,6 +450,29 @@ def test_czt_split_precision(tz, dev, orc, prec, N, M):
     assert r.max() <= TOL_SPLIT
 
 
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16"])
+def test_full_size_split_precision_sampled(tz, dev, orc, prec):
+    """The split-precision CZT on the 8192 x 4096 batch exactly as the
+    benchmark launches it (M = 4096, the half-length matrix-core kernel):
+    sampled traces (the first and the last among them) on all bins and
+    sampled bins of more traces against the oracle; every output finite."""
+    import torch
+    n_pairs, M = 4096, 4096
+    say(f"case: full batch 8192 x 4096 czt M=4096 {prec}, sampled check")
+    x = synth.pairs(n_pairs, N=4096)
+    W, A = tz.czt_band(20e12, 0.2e12, 2.5e12, M)
+    X = tz.czt(to_dev(x, dev), M, W, A, precision=prec)
+    assert bool(torch.isfinite(torch.view_as_real(X)).all())
+    rng = np.random.default_rng(78)
+    rows = np.r_[0, np.sort(rng.choice(np.arange(1, 2 * n_pairs - 1), 3, replace=False)), 2 * n_pairs - 1]
+    assert_close(X[rows].cpu().numpy(), orc.czt(x[rows].astype(np.float64), M, W, A), tol=TOL_SPLIT,
+                 what=f"{prec} rows")
+    more = np.sort(rng.choice(2 * n_pairs, 24, replace=False))
+    bins = np.sort(rng.choice(M, 128, replace=False))
+    assert_close(X[more][:, bins].cpu().numpy(), orc.czt(x[more].astype(np.float64), M, W, A, bins),
+                 tol=TOL_SPLIT, what=f"{prec} sampled bins")
+
+
 def test_split_precision_rejects_other_shapes(tz, dev):
     x = to_dev(np.ones((1, 100), np.float32), dev)
     with pytest.raises(tz.ThzError) as e:
