@@ -92,6 +92,24 @@ def test_transfer_half_length_form_strided_rows(tz, orc):
     check_transfer(got[:, :M], orc.czt(x.astype(np.float64), M, W, A), TOL, 1e-5, say=say, what="half strided")
 
 
+def test_transfer_full_batch_sampled(tz, orc):
+    """The 4096 reference/sample pairs of 4096 samples with M = 4096 exactly
+    as the benchmark launches them (the half-length kernel): every H finite,
+    sampled pairs (the first and the last among them) against the oracle."""
+    import torch
+    n_pairs, N, M = 4096, 4096, 4096
+    x = synth.pairs(n_pairs, N=N)
+    W, A = tz.czt_band(20e12, 0.2e12, 2.5e12, M)
+    say(f"case: czt_transfer full batch {n_pairs} pairs N={N} M={M} plan {tz.czt_plan_shape(N, M)}")
+    H = tz.czt_transfer(torch.from_numpy(x).cuda(), M, W, A)
+    assert bool(torch.isfinite(torch.view_as_real(H)).all())
+    rng = np.random.default_rng(79)
+    pairs = np.r_[0, np.sort(rng.choice(np.arange(1, n_pairs - 1), 4, replace=False)), n_pairs - 1]
+    rows = np.stack([2 * pairs, 2 * pairs + 1], axis=1).ravel()
+    X = orc.czt(x[rows].astype(np.float64), M, W, A)
+    check_transfer(H[pairs].cpu().numpy(), X, TOL, 1e-5, say=say, what="full batch sampled")
+
+
 def test_transfer_fp64_input(tz, orc):
     x = in_window_pairs(2, 1500).astype(np.float64)
     W, A = tz.czt_band(20e12, 0.3e12, 1.8e12, 900)
