@@ -76,6 +76,30 @@ def test_ifft_matches_oracle(tz, orc, N):
     assert np.isfinite(g).all() and r.max() <= TOL
 
 
+def test_ifft_full_batch_sampled(tz, orc):
+    """8192 spectra of 4096 bins, the size the benchmark times: the first, the
+    last and sampled rows in full, and sampled samples of more rows, against
+    the oracle; every output finite."""
+    import torch
+    B, N = 8192, 4096
+    X = spectra(B, N, 4242)
+    say(f"case: ifft full batch {B} x {N}, sampled check")
+    out = tz.ifft(torch.from_numpy(X).cuda())
+    assert bool(torch.isfinite(torch.view_as_real(out)).all())
+    rng = np.random.default_rng(80)
+    rows = np.r_[0, np.sort(rng.choice(np.arange(1, B - 1), 3, replace=False)), B - 1]
+    got = out[rows].cpu().numpy()
+    ref = orc.ifft(X[rows].astype(np.complex128))
+    e = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    more = np.sort(rng.choice(B, 32, replace=False))
+    samples = np.unique(np.r_[0, N - 1, rng.integers(0, N, 62)])
+    got2 = out[more][:, samples].cpu().numpy()
+    ref2 = orc.ifft(X[more].astype(np.complex128), samples=samples)
+    e2 = np.linalg.norm(got2 - ref2, axis=1) / np.linalg.norm(ref2, axis=1)
+    say(f"  full rows: max rel L2 {e.max():.3e}; sampled samples of 32 rows: {e2.max():.3e}")
+    assert e.max() <= TOL and e2.max() <= TOL
+
+
 @pytest.mark.parametrize("N", [1000, 4096, 30000])
 def test_ifft_inverts_fft_zeropad(tz, N):
     """ifft(fft_zeropad(x, 0)) returns the real traces (imaginary part ~ 0)."""
